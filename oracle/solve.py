@@ -1,0 +1,157 @@
+"""The N-D problem and its solution by plain definitions (test infrastructure only).
+
+Sect. 4: the FEM system on (0,X_1) x ... x (0,X_N) with homogeneous Dirichlet
+conditions is, in the scaled form (generalized here to per-axis diffusion
+coefficients diff[d] and a reaction coefficient react),
+
+    ( sum_d diff[d] 4 h_d^{-2} C_1 x..x A_d x..x C_N + react C_1 x..x C_N ) u = f,
+
+h_d = X_d / K_d, with f the FEM average of the load,
+f_i = prod_d (2/h_d) int f phi_i.  The operator is symmetric positive
+definite whenever every denominator react + sum_d diff[d] 4 h_d^{-2} lam_d is
+positive, so u is unique.
+
+``solve`` computes u = A^{-1} f with no fast transforms: per axis the dense
+generalized eigendecomposition Acal_d S_d = Ccal_d S_d Lam_d (S_d^T Ccal_d S_d = I,
+SciPy/LAPACK), then u = (x S_d) [ ((x S_d^T) f) / (react + sum_d diff[d] 4 h_d^-2 Lam_d) ]
+with the Kronecker factors applied as mode products; then float64 iterative
+refinement with the residual computed by the element-by-element operator
+(``apply_A``), because a dense float64 eigensolver loses relative accuracy on
+the smallest eigenvalues at large K.  ``solve_cholesky`` assembles the full
+N-D matrix (tiny meshes only) and solves by Cholesky.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import numpy as np
+import scipy.linalg
+
+from .element import element_matrices
+from .fem1d import apply_elementwise, assemble, dense_eigen
+
+
+def _h(K, X):
+    X = [1.0] * len(K) if X is None else list(X)
+    return [x / k for x, k in zip(X, K)]
+
+
+def coefficients(K: Sequence[int], diff: Sequence[float], X=None):
+    """diff[d] * 4 / h_d^2 for every axis."""
+    return [dd * 4.0 / (h * h) for dd, h in zip(diff, _h(K, X))]
+
+
+def mode_product(B: np.ndarray, u: np.ndarray, axis: int) -> np.ndarray:
+    """Apply the matrix B along ``axis`` of u."""
+    return np.moveaxis(np.tensordot(B, u, axes=([1], [axis])), 0, axis)
+
+
+def apply_A(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+            X=None) -> np.ndarray:
+    """y = A u, by element-wise 1D operators along each axis (float64)."""
+    A, C = element_matrices(n)
+    N = len(K)
+    coef = coefficients(K, diff, X)
+    y = np.zeros_like(u)
+    # mass along every axis: Cu_all
+    for d in range(N):
+        t = u
+        for e in range(N):
+            t = apply_elementwise(A if e == d else C, t, e)
+        y += coef[d] * t
+    if react != 0.0:
+        t = u
+        for e in range(N):
+            t = apply_elementwise(C, t, e)
+        y += react * t
+    return y
+
+
+class EigenSolver:
+    """u = A^{-1} f by per-axis dense eigendecomposition, plus refinement."""
+
+    def __init__(self, n: int, K: Sequence[int], diff: Sequence[float], react: float, X=None):
+        self.n, self.K, self.diff, self.react, self.X = n, tuple(K), tuple(diff), react, X
+        cache = {}
+        self.lam, self.S = [], []
+        for k in self.K:
+            if k not in cache:
+                cache[k] = dense_eigen(n, k)
+            lam, S = cache[k]
+            self.lam.append(lam)
+            self.S.append(S)
+        coef = coefficients(self.K, self.diff, X)
+        den = np.full([len(l) for l in self.lam], float(react))
+        for d, lam in enumerate(self.lam):
+            shape = [1] * len(self.K)
+            shape[d] = len(lam)
+            den = den + (coef[d] * lam).reshape(shape)
+        self.den = den
+
+    def apply_inverse(self, f: np.ndarray) -> np.ndarray:
+        t = f
+        for d, S in enumerate(self.S):
+            t = mode_product(S.T, t, d)
+        t = t / self.den
+        for d, S in enumerate(self.S):
+            t = mode_product(S, t, d)
+        return t
+
+    def residual(self, f, u):
+        return f - apply_A(u, self.n, self.K, self.diff, self.react, self.X)
+
+    def solve(self, f: np.ndarray, max_refine: int = 6, history=None) -> np.ndarray:
+        u = self.apply_inverse(f)
+        r = self.residual(f, u)
+        rn = np.linalg.norm(r)
+        for _ in range(max_refine):
+            du = self.apply_inverse(r)
+            u_new = u + du
+            r_new = self.residual(f, u_new)
+            rn_new = np.linalg.norm(r_new)
+            if history is not None:
+                history.append((float(np.linalg.norm(du) / max(np.linalg.norm(u_new), 1e-300)),
+                                float(rn_new)))
+            if not rn_new < rn:
+                break
+            u, r, rn = u_new, r_new, rn_new
+            if np.linalg.norm(du) <= 1e-17 * np.linalg.norm(u):
+                break
+        return u
+
+
+def solve(f: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+          X=None, max_refine: int = 6) -> np.ndarray:
+    """u = A^{-1} f (float64, with refinement).  f may carry a leading RHS axis."""
+    s = EigenSolver(n, K, diff, react, X)
+    if f.ndim == len(K) + 1:
+        return np.stack([s.solve(fi, max_refine) for fi in f])
+    return s.solve(f, max_refine)
+
+
+def assemble_full(n: int, K: Sequence[int], diff: Sequence[float], react: float, X=None):
+    """The full N-D matrix via Kronecker products (tiny meshes only)."""
+    ops = [assemble(n, k) for k in K]
+    coef = coefficients(K, diff, X)
+    N = len(K)
+    size = int(np.prod([n * k - 1 for k in K]))
+    Afull = np.zeros((size, size))
+    for d in range(N):
+        T = np.ones((1, 1))
+        for e in range(N):
+            T = np.kron(T, ops[e][0] if e == d else ops[e][1])
+        Afull += coef[d] * T
+    if react != 0.0:
+        T = np.ones((1, 1))
+        for e in range(N):
+            T = np.kron(T, ops[e][1])
+        Afull += react * T
+    return Afull
+
+
+def solve_cholesky(f: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+                   X=None) -> np.ndarray:
+    """u = A^{-1} f by dense Cholesky of the assembled N-D matrix."""
+    Afull = assemble_full(n, K, diff, react, X)
+    c = scipy.linalg.cho_factor(Afull)
+    return scipy.linalg.cho_solve(c, f.reshape(-1)).reshape(f.shape)
