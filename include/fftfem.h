@@ -1,0 +1,168 @@
+/*
+ * fftfem.h -- C ABI of the MI355X fast direct solver for the tensor-product
+ * nth-order finite element method on a box (Zlotnik & Zlotnik, "On fast
+ * Fourier solvers for the tensor product high-order FEM for a generalized
+ * Poisson equation").
+ *
+ * Problem (Sect. 4 of the paper, "algorithm (a)", generalized to per-axis
+ * diffusion diff[d] and reaction react):
+ *
+ *   ( sum_d diff[d] * 4/h_d^2 * C_1 x .. x A_d x .. x C_N
+ *     + react * C_1 x .. x C_N ) u = f,          h_d = X_d / K_d,
+ *
+ * where A_d, C_d are the scaled 1D stiffness and mass operators of the
+ * nth-order Lagrange elements on K_d uniform elements with homogeneous
+ * Dirichlet conditions (Sect. 2), and f is the "FEM average" load
+ * f_i = prod_d (2/h_d) * integral(f * phi_i).  The solver applies the direct
+ * FC_n transform along every axis, divides by react + sum_d diff[d] 4/h_d^2
+ * lambda_d, and applies the inverse F_n transform along every axis
+ * (Sect. 3, Theorem 2; Sect. 4, algorithm (a)).
+ *
+ * Array layout (f, u, y): dense row-major float64 of shape (M_1, ..., M_N),
+ * M_d = n*K_d - 1, last axis contiguous, optionally with a leading dimension
+ * of nrhs.  Along axis d, 0-based index g is the dof at x = (g+1) h_d / n:
+ * mesh node j = (g+1)/n when (g+1) % n == 0, else bubble l = g % n + 1 of
+ * element j = g / n + 1 (the ordering of S_K^(n), Sect. 2).  Boundary dofs
+ * are not stored.
+ *
+ * Pointers named "device" must point to memory allocated on the current HIP
+ * device; everything else is host memory.  All functions return an int
+ * status (FFTFEM_OK = 0, negative on error) unless stated otherwise.
+ * Arguments are validated synchronously; kernel-side outcomes (refinement
+ * convergence) are reported by fftfem_get_stats after the caller has
+ * synchronized the stream.
+ */
+#ifndef FFTFEM_H
+#define FFTFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;
+typedef struct fftfem_plan_s* fftfem_plan_t;
+
+enum {
+  FFTFEM_OK = 0,
+  FFTFEM_EINVAL = -1,     /* bad argument (null pointer, size, order, aliasing) */
+  FFTFEM_ENOMEM = -2,     /* device or host allocation failed */
+  FFTFEM_EHIP = -3,       /* a HIP runtime call failed */
+  FFTFEM_ESPECTRUM = -4,  /* plan eigen-solve failed (non-finite or non-positive pencil) */
+  FFTFEM_EINDEF = -5,     /* the operator is not positive definite (a denominator <= 0) */
+  FFTFEM_ENOCONV = -6,    /* refinement did not reach the tolerance */
+  FFTFEM_ENOTIMPL = -7    /* configuration not supported by this build */
+};
+
+enum {
+  FFTFEM_FP64 = 0,        /* transforms and tables in float64, one pass, no refinement */
+  FFTFEM_FP32 = 1,        /* transforms in float32 (float32 accumulate), no refinement */
+  FFTFEM_FP32_REFINE = 2  /* float32 transforms + float64 residual/update refinement */
+};
+
+#define FFTFEM_MAX_DIMS 3
+#define FFTFEM_MAX_ORDER 16
+#define FFTFEM_MAX_ITERS 16
+
+/* Full plan description.  Fields left zero take the documented defaults. */
+typedef struct {
+  int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
+  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, K[d] >= 2 */
+  int n;                          /* element order, 1..FFTFEM_MAX_ORDER */
+  double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
+  double react;                   /* reaction coefficient */
+  double X[FFTFEM_MAX_DIMS];      /* domain lengths (0 -> 1.0) */
+  int precision;                  /* FFTFEM_FP64 / FFTFEM_FP32 / FFTFEM_FP32_REFINE */
+  int max_iter;                   /* refinement iterations after the first solve (0 -> 3) */
+  double tol;                     /* refinement stop: ||correction||/||u|| <= tol (0 -> 1e-12) */
+  int nrhs;                       /* right-hand sides per solve (0 -> 1) */
+  unsigned flags;                 /* reserved, must be 0 */
+} fftfem_desc;
+
+/* Refinement statistics of the last fftfem_solve on a plan. */
+typedef struct {
+  int iterations;                     /* refinement corrections applied */
+  int converged;                      /* 1 if the last relative correction <= tol */
+  double rel_correction[FFTFEM_MAX_ITERS + 1];  /* ||c_i|| / ||u_i|| per iteration, i = 0 is the first solve */
+} fftfem_stats;
+
+/*
+ * Build a plan (Sect. 3, Theorem 1: the 1D eigenpairs; Sect. 4: the
+ * denominators).  Host computation in 113-bit floating point, then upload of
+ * the tables and allocation of the device workspace on the current device
+ * (synchronous).  Returns FFTFEM_EINVAL for bad sizes, FFTFEM_EINDEF if some
+ * denominator react + sum_d diff[d] 4/h_d^2 lambda_d is <= 0,
+ * FFTFEM_ESPECTRUM if an eigen-solve fails, FFTFEM_ENOMEM/EHIP on device
+ * errors.  On failure *out is set to NULL.  The plan owns all device memory
+ * it allocates; release it with fftfem_destroy.
+ */
+int fftfem_plan(fftfem_plan_t* out, int N, const int64_t* K, int n, const double* diff,
+                double react);
+int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* desc);
+
+/*
+ * Solve A u = f (algorithm (a) of Sect. 4).  f, u: device float64 arrays in
+ * the layout above (times nrhs).  f is read only; u must not overlap f.
+ * Asynchronous on stream s (NULL = default stream); no host synchronization
+ * and no allocation.  A plan may be used by one stream at a time.
+ */
+int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s);
+
+/*
+ * y = A u in float64 (the operator above, as the sum over elements of the
+ * reference matrices along each axis, Sect. 2 and 4).  u, y: device arrays,
+ * y must not overlap u.  Asynchronous on s.
+ */
+int fftfem_apply_A(fftfem_plan_t p, const double* u, double* y, hipStream_t s);
+
+/* Statistics of the last solve.  Synchronizes the plan's last stream. */
+int fftfem_get_stats(fftfem_plan_t p, fftfem_stats* out);
+
+/* Device bytes owned by the plan (tables + workspace). */
+size_t fftfem_workspace_bytes(const fftfem_plan_t p);
+
+/* Release a plan (NULL is accepted). */
+void fftfem_destroy(fftfem_plan_t p);
+
+/* Static description of a status code. */
+const char* fftfem_status_string(int status);
+
+/*
+ * Plan tables on the host, for tests.  For axis d (0-based) with M = n K - 1:
+ * lam (M doubles): the scaled 1D eigenvalues in spectral order -- k = 0 with
+ * l = 1..n-1, then k = 1..K-1 with l = 1..n (ascending within k);
+ * Q (n*n*K doubles, may be NULL): per frequency k the channel-by-mode matrix
+ * (row c = nodal, even 1..n/2, odd 1..(n-1)/2 channel; column l = mode) of
+ * the C-orthonormal eigenvectors; block k = 0 is (n-1)x(n-1) stored in the
+ * leading rows/columns of an n x n block.
+ */
+int fftfem_plan_tables(const fftfem_plan_t p, int axis, double* lam, double* Q);
+
+/*
+ * One stage of the solve on one axis, for unit parity tests (not a stable
+ * interface).  dir = +1: direct FC_n transform along `axis` of the device
+ * array in (float64) into out (float64) in spectral order along that axis,
+ * with coefficients (y, s~) for C-orthonormal eigenvectors s~; dir = -1: the
+ * inverse F_n transform (spectral -> physical); dir = 0: forward, divide by
+ * the axis-only denominator react + diff[d] 4/h_d^2 lambda, inverse.  dtype:
+ * 0 = compute in float64, 1 = compute in float32.  in and out may be equal.
+ */
+int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in, double* out,
+                           int dtype, hipStream_t s);
+
+/*
+ * Host-only access to the plan arithmetic, for tests on machines without a
+ * GPU (no device is touched).  fftfem_axis_tables_host: the lam and Q tables
+ * of fftfem_plan_tables for one axis of n-th order elements on K elements.
+ * fftfem_element_matrices_host: the (n+1) x (n+1) reference stiffness A and
+ * mass C of Sect. 2, row-major.
+ */
+int fftfem_axis_tables_host(int n, int64_t K, double* lam, double* Q);
+int fftfem_element_matrices_host(int n, double* A, double* C);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTFEM_H */

@@ -78,6 +78,21 @@ def element_matrices(n: int) -> Tuple[np.ndarray, np.ndarray]:
             np.array([[float(x) for x in r] for r in C]))
 
 
+def element_matrices_ld(n: int) -> Tuple[np.ndarray, np.ndarray]:
+    """(A, C) rounded once from the exact rationals to x87 extended precision
+    (np.longdouble, 64-bit mantissa), for extended-precision residuals."""
+    import mpmath as mp
+
+    A, C = element_matrices_exact(n)
+
+    def conv(x: Fraction):
+        with mp.workdps(40):
+            return np.longdouble(mp.nstr(mp.mpf(x.numerator) / x.denominator, 30))
+
+    return (np.array([[conv(x) for x in r] for r in A], dtype=np.longdouble),
+            np.array([[conv(x) for x in r] for r in C], dtype=np.longdouble))
+
+
 def blocks(X: np.ndarray):
     """The 3x3 block form of Sect. 2: corner X00, X0n, border x, interior X~.
 

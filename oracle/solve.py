@@ -16,8 +16,9 @@ generalized eigendecomposition Acal_d S_d = Ccal_d S_d Lam_d (S_d^T Ccal_d S_d =
 SciPy/LAPACK), then u = (x S_d) [ ((x S_d^T) f) / (react + sum_d diff[d] 4 h_d^-2 Lam_d) ]
 with the Kronecker factors applied as mode products; then float64 iterative
 refinement with the residual computed by the element-by-element operator
-(``apply_A``), because a dense float64 eigensolver loses relative accuracy on
-the smallest eigenvalues at large K.  ``solve_cholesky`` assembles the full
+(``apply_A``) from the exact element matrices in extended precision, because
+a dense float64 eigensolver loses relative accuracy on the smallest
+eigenvalues at large K and a float64 residual stalls near cond(A) * eps.  ``solve_cholesky`` assembles the full
 N-D matrix (tiny meshes only) and solves by Cholesky.
 """
 from __future__ import annotations
@@ -27,7 +28,7 @@ from typing import Sequence
 import numpy as np
 import scipy.linalg
 
-from .element import element_matrices
+from .element import element_matrices, element_matrices_ld
 from .fem1d import apply_elementwise, assemble, dense_eigen
 
 
@@ -47,13 +48,21 @@ def mode_product(B: np.ndarray, u: np.ndarray, axis: int) -> np.ndarray:
 
 
 def apply_A(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
-            X=None) -> np.ndarray:
-    """y = A u, by element-wise 1D operators along each axis (float64)."""
-    A, C = element_matrices(n)
+            X=None, extended: bool = False) -> np.ndarray:
+    """y = A u, by element-wise 1D operators along each axis.
+
+    float64 by default; with ``extended`` the element matrices and all
+    arithmetic are x87 extended precision (np.longdouble) and the result is
+    returned in that precision.
+    """
+    if extended:
+        A, C = element_matrices_ld(n)
+        u = u.astype(np.longdouble)
+    else:
+        A, C = element_matrices(n)
     N = len(K)
     coef = coefficients(K, diff, X)
     y = np.zeros_like(u)
-    # mass along every axis: Cu_all
     for d in range(N):
         t = u
         for e in range(N):
@@ -98,24 +107,31 @@ class EigenSolver:
         return t
 
     def residual(self, f, u):
-        return f - apply_A(u, self.n, self.K, self.diff, self.react, self.X)
+        """f - A u with the exact element matrices, in extended precision.
+
+        A float64 residual (element matrices rounded to float64, float64
+        sums) limits refinement to about cond(A) * eps and also solves a
+        slightly different operator; the extended residual converges to the
+        float64 rounding of the exact discrete solution.
+        """
+        r = f.astype(np.longdouble) - apply_A(u, self.n, self.K, self.diff, self.react, self.X,
+                                              extended=True)
+        return r.astype(np.float64)
 
     def solve(self, f: np.ndarray, max_refine: int = 6, history=None) -> np.ndarray:
+        """Dense-eigen solve, then refinement while the corrections contract."""
         u = self.apply_inverse(f)
-        r = self.residual(f, u)
-        rn = np.linalg.norm(r)
+        prev = np.inf
         for _ in range(max_refine):
-            du = self.apply_inverse(r)
-            u_new = u + du
-            r_new = self.residual(f, u_new)
-            rn_new = np.linalg.norm(r_new)
+            du = self.apply_inverse(self.residual(f, u))
+            ndu = float(np.linalg.norm(du))
             if history is not None:
-                history.append((float(np.linalg.norm(du) / max(np.linalg.norm(u_new), 1e-300)),
-                                float(rn_new)))
-            if not rn_new < rn:
+                history.append(ndu / max(float(np.linalg.norm(u)), 1e-300))
+            if not ndu < prev:
                 break
-            u, r, rn = u_new, r_new, rn_new
-            if np.linalg.norm(du) <= 1e-17 * np.linalg.norm(u):
+            u = u + du
+            prev = ndu
+            if ndu <= 1e-16 * np.linalg.norm(u):
                 break
         return u
 

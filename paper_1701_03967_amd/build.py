@@ -1,0 +1,67 @@
+"""Build libfftfem.so in-tree for gfx950.
+
+    python -m paper_1701_03967_amd.build
+
+The plan builder (113-bit host arithmetic) is compiled by g++; the C ABI and
+the kernels by hipcc.  Packed-FP32 instructions are disabled for all device
+code.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libfftfem.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd):
+    t = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"build step failed: {cmd[0]} ({r.returncode})")
+    return time.time() - t
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    plan_o = os.path.join(BUILD, "plan.o")
+    dt = _run(["g++", "-O2", "-std=gnu++17", "-fPIC", "-pthread", "-Wall", "-I", CSRC, "-I", INCLUDE,
+               "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
+    objs.append(plan_o)
+    if verbose:
+        print(f"[build] plan.cpp {dt:.1f}s", flush=True)
+    api_o = os.path.join(BUILD, "api.o")
+    dt = _run([HIPCC, "-O2", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
+               "-c", os.path.join(CSRC, "api.cpp"), "-o", api_o])
+    objs.append(api_o)
+    if verbose:
+        print(f"[build] api.cpp {dt:.1f}s", flush=True)
+    ker_o = os.path.join(BUILD, "kernels.o")
+    dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
+               "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, "kernels.hip"), "-o", ker_o])
+    objs.append(ker_o)
+    if verbose:
+        print(f"[build] kernels.hip {dt:.1f}s", flush=True)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[build] {LIB}", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,526 @@
+// C ABI of the solver: plan construction, solve schedule, operator apply,
+// refinement loop and statistics.  Host code only; every arithmetic step of
+// a solve runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "fftfem.h"
+#include "fftfem_internal.h"
+#include "launch.h"
+
+using namespace fftfem;
+
+namespace {
+
+struct DevTables {
+  double* d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // Q, twf, twm, twd, mu
+  float* f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
+struct fftfem_plan_s {
+  fftfem_desc desc{};
+  int N = 0, n = 0, nrhs = 1;
+  int64_t K[3] = {0, 0, 0}, M[3] = {0, 0, 0}, stride[3] = {0, 0, 0};
+  int64_t size = 0;  // per right-hand side
+  double coef[3] = {0, 0, 0};
+  std::vector<AxisTables> host;
+  DevTables dev[3];
+  double* Ael = nullptr;
+  double* Cel = nullptr;
+  float* W32 = nullptr;      // float32 workspace (float32 modes)
+  double* tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // operator-apply partial products
+  int ntmp = 0;
+  double* partials = nullptr;
+  int npartials = 0;
+  int* flags = nullptr;      // one per rhs
+  double* stats = nullptr;   // (2 + FFTFEM_MAX_ITERS + 1) per rhs
+  size_t bytes = 0;
+  int lds_max = 65536;
+  hipStream_t last = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+constexpr int kStatsLen = 2 + FFTFEM_MAX_ITERS + 1;
+
+int from_hip(hipError_t e) {
+  if (e == hipSuccess) return FFTFEM_OK;
+  if (e == hipErrorOutOfMemory) return FFTFEM_ENOMEM;
+  return FFTFEM_EHIP;
+}
+
+int dev_alloc(fftfem_plan_t p, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) return FFTFEM_OK;
+  const char* fail = std::getenv("FFTFEM_TEST_FAIL_ALLOC");
+  if (fail && fail[0] == '1') return FFTFEM_ENOMEM;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? FFTFEM_ENOMEM : FFTFEM_EHIP;
+  }
+  p->allocs.push_back(*ptr);
+  p->bytes += bytes;
+  return FFTFEM_OK;
+}
+
+template <typename T>
+int upload(fftfem_plan_t p, T** dst, const std::vector<double>& src) {
+  std::vector<T> tmp(src.begin(), src.end());
+  int rc = dev_alloc(p, (void**)dst, tmp.size() * sizeof(T));
+  if (rc) return rc;
+  return from_hip(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+
+int validate(const fftfem_desc* d) {
+  if (!d) return FFTFEM_EINVAL;
+  if (d->N < 1 || d->N > FFTFEM_MAX_DIMS) return FFTFEM_EINVAL;
+  if (d->n < 1 || d->n > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
+  if (d->flags != 0) return FFTFEM_EINVAL;
+  if (d->precision < FFTFEM_FP64 || d->precision > FFTFEM_FP32_REFINE) return FFTFEM_EINVAL;
+  if (d->max_iter < 0 || d->max_iter > FFTFEM_MAX_ITERS) return FFTFEM_EINVAL;
+  if (d->nrhs < 0 || !(d->tol >= 0) || !std::isfinite(d->react)) return FFTFEM_EINVAL;
+  for (int i = 0; i < d->N; ++i) {
+    if (d->K[i] < 2) return FFTFEM_EINVAL;
+    if (!(d->diff[i] > 0) || !std::isfinite(d->diff[i])) return FFTFEM_EINVAL;
+    if (d->X[i] < 0 || !std::isfinite(d->X[i])) return FFTFEM_EINVAL;
+  }
+  return FFTFEM_OK;
+}
+
+// Lines per workgroup for a line pass: as many as fit the LDS budget, the
+// register-held contraction tasks (G * ceil(K/2) <= 1024) and 64.
+int choose_G(const fftfem_plan_s* p, int64_t K, size_t elt, int64_t nlines) {
+  size_t per = (size_t)(1 + p->n / 2) * K * 2 * elt;
+  int64_t halfK = (K + 1) / 2;
+  size_t budget = std::max<size_t>(per, 65536);
+  int G = 1;
+  while (G < 64 && (size_t)(2 * G) * per <= budget && 2 * G * halfK <= 1024 && 2 * G <= nlines)
+    G *= 2;
+  return G;
+}
+
+template <typename T>
+const T* tab(const fftfem_plan_s* p, int axis, int which);
+template <>
+const double* tab<double>(const fftfem_plan_s* p, int axis, int which) {
+  return p->dev[axis].d[which];
+}
+template <>
+const float* tab<float>(const fftfem_plan_s* p, int axis, int which) {
+  return p->dev[axis].f[which];
+}
+
+// One line pass along `axis`.  `others` selects whether the other axes'
+// denominators enter the MID division (false for the 1D debug transform).
+template <typename T>
+int line_pass(fftfem_plan_t p, int axis, int mode, const void* in, int in_f64, void* out,
+              int out_f64, const double* upd, const int* flag, hipStream_t s, bool others,
+              bool want_partials) {
+  LineArgs<T> a{};
+  const AxisTables& t = p->host[axis];
+  a.in = in;
+  a.out = out;
+  a.upd = upd;
+  a.in_f64 = in_f64;
+  a.out_f64 = out_f64;
+  a.K = (int)t.K;
+  a.log2K = ilog2(t.K);
+  a.M = t.M;
+  a.es = p->stride[axis];
+  a.nlines = p->size / t.M;
+  a.G = choose_G(p, t.K, sizeof(T), a.nlines);
+  a.Q = tab<T>(p, axis, 0);
+  a.twf = tab<T>(p, axis, 1);
+  a.twm = tab<T>(p, axis, 2);
+  a.twd = tab<T>(p, axis, 3);
+  a.mu_self = tab<T>(p, axis, 4);
+  a.react = (T)p->desc.react;
+  a.nother = 0;
+  if (others)
+    for (int e = 0; e < p->N; ++e)
+      if (e != axis) {
+        a.mu_o[a.nother] = tab<T>(p, e, 4);
+        a.so[a.nother] = p->stride[e];
+        a.Mo[a.nother] = p->M[e];
+        ++a.nother;
+      }
+  a.partials = want_partials ? p->partials : nullptr;
+  a.flag = flag;
+  size_t lds = (size_t)a.G * (1 + p->n / 2) * t.K * 2 * sizeof(T);
+  if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
+  int64_t nblocks = (a.nlines + a.G - 1) / a.G;
+  if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
+  return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
+}
+
+// One operator pass along `axis` (see ApplyArgs in launch.h).
+int apply_pass(fftfem_plan_t p, int axis, const double* in1, const double* in2, const double* f,
+               void* o1, int o1_f64, double* o2, const double c1[4], const double c2[4],
+               const int* flag, hipStream_t s) {
+  ApplyArgs a{};
+  a.in1 = in1;
+  a.in2 = in2;
+  a.f = f;
+  a.o1 = o1;
+  a.o2 = o2;
+  a.o1_f64 = o1_f64;
+  a.sub_f = f != nullptr;
+  for (int i = 0; i < 4; ++i) {
+    a.c1[i] = c1[i];
+    a.c2[i] = c2 ? c2[i] : 0.0;
+  }
+  a.M = p->M[axis];
+  a.es = p->stride[axis];
+  a.nlines = p->size / a.M;
+  if (a.es > 1) {
+    a.G = 32;
+    a.TL = 64;
+  } else {
+    a.G = 4;
+    a.TL = 512;
+  }
+  a.Ael = p->Ael;
+  a.Cel = p->Cel;
+  a.flag = flag;
+  int64_t W = a.TL + 2 * p->n;
+  size_t lds = (size_t)(in2 ? 2 : 1) * a.G * W * sizeof(double);
+  int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
+  return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
+}
+
+// y = A u (out_f64) or r = f - A u, for one right-hand side.
+int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_f64,
+                   const int* flag, hipStream_t s) {
+  const double* c = p->coef;
+  double react = p->desc.react;
+  int rc;
+  if (p->N == 1) {
+    double c1[4] = {c[0], react, 0, 0};
+    return apply_pass(p, 0, u, nullptr, f, out, out_f64, nullptr, c1, nullptr, flag, s);
+  }
+  if (p->N == 2) {
+    double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
+    rc = apply_pass(p, 1, u, nullptr, nullptr, p->tmp[0], 1, p->tmp[1], cC, cA, flag, s);
+    if (rc) return rc;
+    double c1[4] = {c[0], react, 0, c[1]};
+    return apply_pass(p, 0, p->tmp[0], p->tmp[1], f, out, out_f64, nullptr, c1, nullptr, flag, s);
+  }
+  double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
+  rc = apply_pass(p, 2, u, nullptr, nullptr, p->tmp[0], 1, p->tmp[1], cC, cA, flag, s);
+  if (rc) return rc;
+  double c4[4] = {c[1], react, 0, c[2]};
+  rc = apply_pass(p, 1, p->tmp[0], p->tmp[1], nullptr, p->tmp[2], 1, p->tmp[3], cC, c4, flag, s);
+  if (rc) return rc;
+  double c1[4] = {c[0], 0, 0, 1};
+  return apply_pass(p, 0, p->tmp[2], p->tmp[3], f, out, out_f64, nullptr, c1, nullptr, flag, s);
+}
+
+// Forward on axes N-1..1, MID on axis 0, inverse on axes 1..N-1.
+// work: T array used in place between passes (may equal out when T is double).
+template <typename T>
+int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, double* out,
+                    const double* upd, const int* flag, hipStream_t s, bool partials) {
+  int N = p->N, rc;
+  if (N == 1)
+    return line_pass<T>(p, 0, MID, in, in_f64, out, 1, upd, flag, s, true, partials);
+  rc = line_pass<T>(p, N - 1, FWD, in, in_f64, work, 0, nullptr, flag, s, true, false);
+  if (rc) return rc;
+  for (int d = N - 2; d >= 1; --d) {
+    rc = line_pass<T>(p, d, FWD, work, 0, work, 0, nullptr, flag, s, true, false);
+    if (rc) return rc;
+  }
+  rc = line_pass<T>(p, 0, MID, work, 0, work, 0, nullptr, flag, s, true, false);
+  if (rc) return rc;
+  for (int d = 1; d <= N - 2; ++d) {
+    rc = line_pass<T>(p, d, INV, work, 0, work, 0, nullptr, flag, s, true, false);
+    if (rc) return rc;
+  }
+  return line_pass<T>(p, N - 1, INV, work, 0, out, 1, upd, flag, s, true, partials);
+}
+
+int64_t max_blocks_last_pass(const fftfem_plan_s* p, size_t elt) {
+  int axis = p->N - 1;
+  int64_t nlines = p->size / p->M[axis];
+  int G = choose_G(p, p->K[axis], elt, nlines);
+  return (nlines + G - 1) / G;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fftfem_status_string(int st) {
+  switch (st) {
+    case FFTFEM_OK: return "ok";
+    case FFTFEM_EINVAL: return "invalid argument";
+    case FFTFEM_ENOMEM: return "out of memory";
+    case FFTFEM_EHIP: return "HIP runtime error";
+    case FFTFEM_ESPECTRUM: return "plan eigen-solve failed";
+    case FFTFEM_EINDEF: return "operator not positive definite";
+    case FFTFEM_ENOCONV: return "refinement did not converge";
+    case FFTFEM_ENOTIMPL: return "configuration not supported";
+    default: return "unknown status";
+  }
+}
+
+void fftfem_destroy(fftfem_plan_t p) {
+  if (!p) return;
+  for (void* a : p->allocs) (void)hipFree(a);
+  delete p;
+}
+
+int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
+  if (!out) return FFTFEM_EINVAL;
+  *out = nullptr;
+  int rc = validate(din);
+  if (rc) return rc;
+  fftfem_desc d = *din;
+  if (d.max_iter == 0) d.max_iter = 3;
+  if (d.tol == 0) d.tol = 1e-12;
+  if (d.nrhs == 0) d.nrhs = 1;
+  for (int i = 0; i < d.N; ++i)
+    if (d.X[i] == 0) d.X[i] = 1.0;
+  if (d.n > kMaxLineOrder) return FFTFEM_ENOTIMPL;
+  for (int i = 0; i < d.N; ++i)
+    if (!is_pow2(d.K[i]) || d.K[i] > 2048) return FFTFEM_ENOTIMPL;
+  fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
+  if (!p) return FFTFEM_ENOMEM;
+  p->desc = d;
+  p->N = d.N;
+  p->n = d.n;
+  p->nrhs = d.nrhs;
+  p->size = 1;
+  for (int i = 0; i < d.N; ++i) {
+    p->K[i] = d.K[i];
+    p->M[i] = (int64_t)d.n * d.K[i] - 1;
+    p->size *= p->M[i];
+  }
+  for (int i = 0; i < d.N; ++i) {
+    p->stride[i] = 1;
+    for (int e = i + 1; e < d.N; ++e) p->stride[i] *= p->M[e];
+  }
+  // tables (identical axes are computed once)
+  p->host.resize(d.N);
+  std::map<int64_t, int> seen;
+  for (int i = 0; i < d.N; ++i) {
+    auto it = seen.find(d.K[i]);
+    if (it != seen.end()) {
+      p->host[i] = p->host[it->second];
+    } else {
+      rc = build_axis_tables(d.n, d.K[i], 1.0, 1.0, &p->host[i]);
+      if (rc) {
+        delete p;
+        return rc;
+      }
+      seen[d.K[i]] = i;
+    }
+    p->coef[i] = d.diff[i] * 4.0 * ((double)d.K[i] / d.X[i]) * ((double)d.K[i] / d.X[i]);
+    p->host[i].coef = p->coef[i];
+  }
+  double dmin = d.react;
+  for (int i = 0; i < d.N; ++i) {
+    double m = p->host[i].lam[0];
+    for (double v : p->host[i].lam) m = std::min(m, v);
+    dmin += p->coef[i] * m;
+  }
+  if (!(dmin > 0)) {
+    delete p;
+    return FFTFEM_EINDEF;
+  }
+  int dev = 0;
+  if ((rc = from_hip(hipGetDevice(&dev)))) {
+    delete p;
+    return rc;
+  }
+  int lmax = 0;
+  if (hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      lmax > 0)
+    p->lds_max = lmax;
+  // device tables
+  for (int i = 0; i < d.N && !rc; ++i) {
+    const AxisTables& t = p->host[i];
+    std::vector<double> mu(t.lam.size());
+    for (size_t c = 0; c < mu.size(); ++c) mu[c] = p->coef[i] * t.lam[c];
+    const std::vector<double>* src[5] = {&t.Q, &t.twf, &t.twm, &t.twd, &mu};
+    for (int w = 0; w < 5 && !rc; ++w) {
+      rc = upload<double>(p, &p->dev[i].d[w], *src[w]);
+      if (!rc) rc = upload<float>(p, &p->dev[i].f[w], *src[w]);
+    }
+  }
+  if (!rc) {
+    std::vector<double> A, C;
+    element_matrices(d.n, &A, &C);
+    rc = upload<double>(p, &p->Ael, A);
+    if (!rc) rc = upload<double>(p, &p->Cel, C);
+  }
+  // workspace
+  if (!rc && d.precision != FFTFEM_FP64)
+    rc = dev_alloc(p, (void**)&p->W32, (size_t)p->size * sizeof(float));
+  p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 2 : 4);
+  for (int i = 0; i < p->ntmp && !rc; ++i)
+    rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
+  if (!rc) {
+    p->npartials = (int)std::max<int64_t>(max_blocks_last_pass(p, sizeof(float)),
+                                          max_blocks_last_pass(p, sizeof(double)));
+    rc = dev_alloc(p, (void**)&p->partials, (size_t)p->npartials * 2 * sizeof(double));
+  }
+  if (!rc) rc = dev_alloc(p, (void**)&p->flags, (size_t)p->nrhs * sizeof(int));
+  if (!rc) rc = dev_alloc(p, (void**)&p->stats, (size_t)p->nrhs * kStatsLen * sizeof(double));
+  if (!rc) {
+    for (int r = 0; r < p->nrhs && !rc; ++r)
+      rc = from_hip(launch_reset(p->flags + r, p->stats + r * kStatsLen, kStatsLen, nullptr));
+    if (!rc) rc = from_hip(hipDeviceSynchronize());
+  }
+  if (rc) {
+    fftfem_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return FFTFEM_OK;
+}
+
+int fftfem_plan(fftfem_plan_t* out, int N, const int64_t* K, int n, const double* diff,
+                double react) {
+  if (!out) return FFTFEM_EINVAL;
+  *out = nullptr;
+  if (!K || !diff || N < 1 || N > FFTFEM_MAX_DIMS) return FFTFEM_EINVAL;
+  fftfem_desc d{};
+  d.N = N;
+  d.n = n;
+  d.react = react;
+  for (int i = 0; i < N; ++i) {
+    d.K[i] = K[i];
+    d.diff[i] = diff[i];
+  }
+  d.precision = FFTFEM_FP64;
+  return fftfem_plan_ex(out, &d);
+}
+
+static bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
+  if (!p || !f || !u) return FFTFEM_EINVAL;
+  size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
+  if (overlap(f, u, bytes)) return FFTFEM_EINVAL;
+  p->last = s;
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r) {
+    const double* fr = f + (size_t)r * p->size;
+    double* ur = u + (size_t)r * p->size;
+    int* flag = p->flags + r;
+    double* st = p->stats + (size_t)r * kStatsLen;
+    rc = from_hip(launch_reset(flag, st, kStatsLen, s));
+    if (rc) break;
+    if (p->desc.precision == FFTFEM_FP64) {
+      rc = transform_chain<double>(p, fr, 1, ur, ur, nullptr, nullptr, s, false);
+      continue;
+    }
+    rc = transform_chain<float>(p, fr, 1, p->W32, ur, nullptr, nullptr, s, false);
+    if (rc || p->desc.precision == FFTFEM_FP32) continue;
+    for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
+      rc = operator_apply(p, ur, fr, p->W32, 0, flag, s);
+      if (!rc) rc = transform_chain<float>(p, p->W32, 0, p->W32, ur, ur, flag, s, true);
+      if (!rc)
+        rc = from_hip(launch_reduce(p->partials, (int)max_blocks_last_pass(p, sizeof(float)), it,
+                                    p->desc.tol, flag, st, s));
+    }
+  }
+  return rc;
+}
+
+int fftfem_apply_A(fftfem_plan_t p, const double* u, double* y, hipStream_t s) {
+  if (!p || !u || !y) return FFTFEM_EINVAL;
+  size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
+  if (overlap(u, y, bytes)) return FFTFEM_EINVAL;
+  p->last = s;
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r)
+    rc = operator_apply(p, u + (size_t)r * p->size, nullptr, y + (size_t)r * p->size, 1, nullptr, s);
+  return rc;
+}
+
+int fftfem_get_stats(fftfem_plan_t p, fftfem_stats* out) {
+  if (!p || !out) return FFTFEM_EINVAL;
+  int rc = from_hip(hipStreamSynchronize(p->last));
+  if (rc) return rc;
+  std::vector<double> h((size_t)p->nrhs * kStatsLen);
+  rc = from_hip(hipMemcpy(h.data(), p->stats, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->converged = 1;
+  for (int r = 0; r < p->nrhs; ++r) {
+    const double* st = &h[(size_t)r * kStatsLen];
+    out->iterations = std::max(out->iterations, (int)st[0]);
+    if (p->desc.precision == FFTFEM_FP32_REFINE && st[1] == 0) out->converged = 0;
+    for (int i = 0; i <= FFTFEM_MAX_ITERS; ++i)
+      out->rel_correction[i] = std::max(out->rel_correction[i], st[2 + i]);
+  }
+  if (p->desc.precision != FFTFEM_FP32_REFINE) out->converged = 1;
+  return FFTFEM_OK;
+}
+
+size_t fftfem_workspace_bytes(const fftfem_plan_t p) { return p ? p->bytes : 0; }
+
+int fftfem_plan_tables(const fftfem_plan_t p, int axis, double* lam, double* Q) {
+  if (!p || axis < 0 || axis >= p->N || !lam) return FFTFEM_EINVAL;
+  const AxisTables& t = p->host[axis];
+  std::memcpy(lam, t.lam.data(), t.lam.size() * sizeof(double));
+  if (Q) std::memcpy(Q, t.Q.data(), t.Q.size() * sizeof(double));
+  return FFTFEM_OK;
+}
+
+int fftfem_axis_tables_host(int n, int64_t K, double* lam, double* Q) {
+  if (!lam || n < 1 || n > FFTFEM_MAX_ORDER || K < 2) return FFTFEM_EINVAL;
+  AxisTables t;
+  int rc = build_axis_tables(n, K, 1.0, 1.0, &t);
+  if (rc) return rc;
+  std::memcpy(lam, t.lam.data(), t.lam.size() * sizeof(double));
+  if (Q) std::memcpy(Q, t.Q.data(), t.Q.size() * sizeof(double));
+  return FFTFEM_OK;
+}
+
+int fftfem_element_matrices_host(int n, double* A, double* C) {
+  if (!A || !C || n < 1 || n > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
+  std::vector<double> a, c;
+  element_matrices(n, &a, &c);
+  std::memcpy(A, a.data(), a.size() * sizeof(double));
+  std::memcpy(C, c.data(), c.size() * sizeof(double));
+  return FFTFEM_OK;
+}
+
+int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in, double* out,
+                           int dtype, hipStream_t s) {
+  if (!p || !in || !out || axis < 0 || axis >= p->N || dir < -1 || dir > 1) return FFTFEM_EINVAL;
+  if (dtype != 0 && dtype != 1) return FFTFEM_EINVAL;
+  int mode = dir > 0 ? FWD : (dir < 0 ? INV : MID);
+  p->last = s;
+  if (dtype == 0)
+    return line_pass<double>(p, axis, mode, in, 1, out, 1, nullptr, nullptr, s, false, false);
+  return line_pass<float>(p, axis, mode, in, 1, out, 1, nullptr, nullptr, s, false, false);
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Internal declarations shared by the host plan builder, the C ABI and the
+// HIP kernels.  Not installed; the public interface is include/fftfem.h.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace fftfem {
+
+// Per-axis tables produced on the host by the plan builder.
+//
+// Channel convention for one line of M = nK - 1 dofs (Sect. 2-3 of the paper):
+//   nodal channel   x_j = y at node j, j = 1..K-1;
+//   even channel m  (m = 1..n/2):      y_{j-1/2,m} + y_{j-1/2,n-m}  (just y_{j-1/2,m} if 2m = n);
+//   odd channel m   (m = 1..(n-1)/2):  y_{j-1/2,m} - y_{j-1/2,n-m};   j = 1..K.
+// Frequency k = 1..K-1 couples the nodal DST-I value at k, the even channels'
+// DST-II value at k and the odd channels' DCT-II value at k; the bubble-only
+// modes (k = 0) couple the even channels' DST-II value at k = K (alternating
+// sum) and the odd channels' DCT-II value at k = 0 (plain sum).
+// Q[k] (n x n, row = channel, column = mode) holds C-orthonormal eigenvectors
+// of the projected pencil at frequency k, so that
+//   forward:  w_l = sum_c Q[k][c][l] * chan_c(k)      (coefficients (y, s~))
+//   inverse:  chan_c(k) = sum_l Q[k][c][l] * w_l.
+struct AxisTables {
+  int n = 0;
+  int64_t K = 0;
+  int64_t M = 0;
+  double coef = 0.0;          // diff * 4 (K/X)^2
+  std::vector<double> lam;    // M scaled eigenvalues, spectral order
+  std::vector<double> Q;      // K blocks of n*n (block 0: (n-1)x(n-1) in the leading corner)
+  std::vector<double> twf;    // K complex: exp(-2 pi i q / K)
+  std::vector<double> twm;    // K complex: exp(-i pi k / (2K))
+  std::vector<double> twd;    // K complex: exp(-i pi k / K)
+};
+
+// Builds the tables of one axis.  Returns 0 or a negative FFTFEM_* status.
+int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* out);
+
+// Reference-element matrices (n+1)^2, row-major, rounded from 113-bit values.
+void element_matrices(int n, std::vector<double>* A, std::vector<double>* C);
+
+inline int num_even(int n) { return n / 2; }
+inline int num_odd(int n) { return (n - 1) / 2; }
+
+}  // namespace fftfem

@@ -1,0 +1,62 @@
+// Kernel argument blocks and launchers shared by the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fftfem {
+
+enum { FWD = 0, INV = 1, MID = 2 };
+
+template <typename T>
+struct LineArgs {
+  const void* in;
+  void* out;
+  const double* upd;      // INV with update: out = upd + result (float64)
+  int in_f64, out_f64;
+  int K, log2K;
+  int64_t M, es, nlines;
+  int G;                  // lines per tile
+  const T* Q;             // K blocks of n*n
+  const T* twf;           // K complex exp(-2 pi i q/K)
+  const T* twm;           // K complex exp(-i pi k/(2K))
+  const T* twd;           // K complex exp(-i pi k/K)
+  const T* mu_self;       // M: diff_d 4/h_d^2 lambda along this axis
+  const T* mu_o[2];       // other axes
+  int64_t so[2], Mo[2];   // their strides and lengths
+  int nother;
+  T react;
+  double* partials;       // per-block (sum c^2, sum u^2) in update mode
+  const int* flag;        // nonzero: skip (refinement converged)
+};
+
+struct ApplyArgs {
+  const double* in1;
+  const double* in2;
+  const double* f;
+  void* o1;
+  double* o2;
+  int o1_f64;
+  int sub_f;
+  double c1[4], c2[4];
+  int64_t M, es, nlines;
+  int G, TL;
+  const double* Ael;
+  const double* Cel;
+  const int* flag;
+};
+
+
+template <typename T>
+hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                       hipStream_t s);
+hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int nparts, int iter, double tol, int* flag,
+                         double* stats, hipStream_t s);
+
+constexpr int kBlock = 256;        // threads per workgroup of every kernel
+constexpr int kMaxLineOrder = 9;   // element orders compiled into the line kernels
+
+}  // namespace fftfem

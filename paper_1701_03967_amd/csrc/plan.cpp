@@ -1,0 +1,417 @@
+// Host plan builder: the 1D eigenstructure of the nth-order FEM operators.
+//
+// Sect. 3, Theorem 1 of the paper: the eigenvectors of A v = lambda C v on
+// S_K^(n) with k >= 1 have nodal part sin(pi k j / K) and bubble part
+// p sin(pi k (j-1)/K) + (Pp) sin(pi k j / K); splitting p into even and odd
+// parts (Sect. 2) and using the sum-to-product identity of the proof of
+// Theorem 2 turns the bubble part into
+//   2 cos(psi) p_e sin(pi k (j-1/2)/K) - 2 sin(psi) p_o cos(pi k (j-1/2)/K),
+// psi = pi k / (2K).  Hence, for fixed k, every eigenvector lies in the
+// n-dimensional span of the "channel" vectors (nodal sine, even-channel
+// sines at element centres, odd-channel cosines at element centres).  This
+// module projects A and C onto that span in closed form (the sums over
+// elements of products of shifted sines reduce to K/2 times cosines/sines of
+// the phase differences), and solves the n x n symmetric-definite pencil
+// (Cholesky + cyclic Jacobi) for C-orthonormal eigenvectors.  The k = 0
+// (bubble-only) block is the same construction with the alternating and the
+// constant patterns of Theorem 1, item 2.
+//
+// All arithmetic is 113-bit (__float128): at K = 1024, n = 9 the smallest
+// eigenvalue (~2.4e-6) shares a pencil with entries ~1e3, and float64 would
+// lose about eight digits of it.  Results are rounded to float64 once.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "fftfem_internal.h"
+
+namespace fftfem {
+namespace {
+
+typedef __float128 q;
+
+const q kPi = 3.14159265358979323846264338327950288Q;
+
+q qabs(q x) { return x < 0 ? -x : x; }
+
+q qsqrt(q x) {
+  if (x <= 0) return 0;
+  q r = (q)std::sqrt((double)x);
+  for (int i = 0; i < 3; ++i) r = (r + x / r) / 2;
+  return r;
+}
+
+// sin and cos of pi * t for t in [0, 1/4], by Taylor series.
+void sincospi_small(q t, q* s, q* c) {
+  q x = kPi * t;
+  q x2 = x * x;
+  q term = x, ss = x;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x2 / (q)((2 * k) * (2 * k + 1));
+    ss += term;
+    if (qabs(term) < 1e-40Q) break;
+  }
+  term = 1;
+  q cc = 1;
+  for (int k = 1; k < 40; ++k) {
+    term *= -x2 / (q)((2 * k - 1) * (2 * k));
+    cc += term;
+    if (qabs(term) < 1e-40Q) break;
+  }
+  *s = ss;
+  *c = cc;
+}
+
+// sin and cos of pi * num / den with exact integer octant reduction.
+void sincospi(int64_t num, int64_t den, q* s, q* c) {
+  int64_t r = num % (2 * den);
+  if (r < 0) r += 2 * den;
+  q sgs = 1, sgc = 1;
+  if (r >= den) {  // pi + a
+    r -= den;
+    sgs = -1;
+    sgc = -1;
+  }
+  if (2 * r > den) {  // pi - a
+    r = den - r;
+    sgc = -sgc;
+  }
+  q ss, cc;
+  if (4 * r > den) {  // pi/2 - a, t = (den - 2r) / (2 den)
+    sincospi_small((q)(den - 2 * r) / (q)(2 * den), &cc, &ss);
+  } else {
+    sincospi_small((q)r / (q)den, &ss, &cc);
+  }
+  *s = sgs * ss;
+  *c = sgc * cc;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1].
+void gauss_legendre(int m, std::vector<q>* x, std::vector<q>* w) {
+  x->resize(m);
+  w->resize(m);
+  for (int i = 0; i < m; ++i) {
+    q z = (q)std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    q dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      q p0 = 1, p1 = z;
+      for (int k = 1; k < m; ++k) {
+        q p2 = ((2 * k + 1) * z * p1 - k * p0) / (q)(k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1);
+      q dz = p1 / dp;
+      z -= dz;
+      if (qabs(dz) < 1e-36Q) break;
+    }
+    (*x)[i] = z;
+    (*w)[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Element matrices on [-1, 1] for the Lagrange basis at -1 + 2k/n (Sect. 2),
+// integrated exactly by (n+1)-point Gauss-Legendre.
+void element_matrices_q(int n, std::vector<q>* A, std::vector<q>* C) {
+  std::vector<q> xn(n + 1), xg, wg;
+  for (int k = 0; k <= n; ++k) xn[k] = -1 + (q)(2 * k) / (q)n;
+  gauss_legendre(n + 1, &xg, &wg);
+  int m = n + 1;
+  std::vector<q> val((n + 1) * m), der((n + 1) * m);
+  for (int l = 0; l <= n; ++l) {
+    for (int g = 0; g < m; ++g) {
+      q x = xg[g];
+      q v = 1;
+      for (int j = 0; j <= n; ++j)
+        if (j != l) v *= (x - xn[j]) / (xn[l] - xn[j]);
+      q d = 0;
+      for (int j = 0; j <= n; ++j) {
+        if (j == l) continue;
+        q t = 1 / (xn[l] - xn[j]);
+        for (int p = 0; p <= n; ++p)
+          if (p != l && p != j) t *= (x - xn[p]) / (xn[l] - xn[p]);
+        d += t;
+      }
+      val[l * m + g] = v;
+      der[l * m + g] = d;
+    }
+  }
+  A->assign((n + 1) * (n + 1), 0);
+  C->assign((n + 1) * (n + 1), 0);
+  for (int i = 0; i <= n; ++i)
+    for (int j = 0; j <= n; ++j) {
+      q sa = 0, sc = 0;
+      for (int g = 0; g < m; ++g) {
+        sa += wg[g] * der[i * m + g] * der[j * m + g];
+        sc += wg[g] * val[i * m + g] * val[j * m + g];
+      }
+      (*A)[i * (n + 1) + j] = sa;
+      (*C)[i * (n + 1) + j] = sc;
+    }
+}
+
+// One term of a channel vector: local index, weight, trig kind, phase.
+struct Term {
+  int i;
+  int w;
+  bool is_cos;
+  int phase;  // -1, 0, +1 in units of psi
+};
+
+std::vector<std::vector<Term>> channel_terms(int n, bool k0) {
+  std::vector<std::vector<Term>> b;
+  if (!k0) b.push_back({{0, 1, false, -1}, {n, 1, false, +1}});
+  for (int m = 1; m <= num_even(n); ++m) {
+    if (2 * m == n)
+      b.push_back({{m, 1, false, 0}});
+    else
+      b.push_back({{m, 1, false, 0}, {n - m, 1, false, 0}});
+  }
+  for (int m = 1; m <= num_odd(n); ++m) b.push_back({{m, 1, true, 0}, {n - m, -1, true, 0}});
+  return b;
+}
+
+// Symmetric-definite pencil (Ma, Mc) of order r: eigenvalues ascending and
+// Mc-orthonormal eigenvectors V (column j = vector j), by Cholesky of Mc and
+// cyclic Jacobi on L^{-1} Ma L^{-T}.  Returns false on breakdown.
+bool pencil_eigen(int r, std::vector<q> Ma, std::vector<q> Mc, std::vector<q>* lam,
+                  std::vector<q>* V) {
+  std::vector<q> L(r * r, 0);
+  for (int j = 0; j < r; ++j) {
+    q s = Mc[j * r + j];
+    for (int k = 0; k < j; ++k) s -= L[j * r + k] * L[j * r + k];
+    if (!(s > 0)) return false;
+    L[j * r + j] = qsqrt(s);
+    for (int i = j + 1; i < r; ++i) {
+      q t = Mc[i * r + j];
+      for (int k = 0; k < j; ++k) t -= L[i * r + k] * L[j * r + k];
+      L[i * r + j] = t / L[j * r + j];
+    }
+  }
+  // H = L^{-1} Ma L^{-T}: first T = L^{-1} Ma (forward substitution per column)
+  std::vector<q> T(r * r), H(r * r);
+  for (int c = 0; c < r; ++c)
+    for (int i = 0; i < r; ++i) {
+      q s = Ma[i * r + c];
+      for (int k = 0; k < i; ++k) s -= L[i * r + k] * T[k * r + c];
+      T[i * r + c] = s / L[i * r + i];
+    }
+  // H = T L^{-T}  <=>  H^T = L^{-1} T^T
+  for (int c = 0; c < r; ++c)
+    for (int i = 0; i < r; ++i) {
+      q s = T[c * r + i];
+      for (int k = 0; k < i; ++k) s -= L[i * r + k] * H[c * r + k];
+      H[c * r + i] = s / L[i * r + i];
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < i; ++j) {
+      q a = (H[i * r + j] + H[j * r + i]) / 2;
+      H[i * r + j] = H[j * r + i] = a;
+    }
+  std::vector<q> W(r * r, 0);
+  for (int i = 0; i < r; ++i) W[i * r + i] = 1;
+  q norm = 0;
+  for (int i = 0; i < r * r; ++i) norm += H[i] * H[i];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    q off = 0;
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j)
+        if (i != j) off += H[i * r + j] * H[i * r + j];
+    if (off <= 1e-66Q * norm) break;
+    for (int p = 0; p < r - 1; ++p)
+      for (int s = p + 1; s < r; ++s) {
+        q apq = H[p * r + s];
+        if (apq == 0) continue;
+        q app = H[p * r + p], aqq = H[s * r + s];
+        q theta = (aqq - app) / (2 * apq);
+        q t = (theta >= 0 ? 1 : -1) / (qabs(theta) + qsqrt(theta * theta + 1));
+        q c = 1 / qsqrt(t * t + 1), sn = t * c;
+        for (int k = 0; k < r; ++k) {
+          q hkp = H[k * r + p], hks = H[k * r + s];
+          H[k * r + p] = c * hkp - sn * hks;
+          H[k * r + s] = sn * hkp + c * hks;
+        }
+        for (int k = 0; k < r; ++k) {
+          q hpk = H[p * r + k], hsk = H[s * r + k];
+          H[p * r + k] = c * hpk - sn * hsk;
+          H[s * r + k] = sn * hpk + c * hsk;
+        }
+        for (int k = 0; k < r; ++k) {
+          q wkp = W[k * r + p], wks = W[k * r + s];
+          W[k * r + p] = c * wkp - sn * wks;
+          W[k * r + s] = sn * wkp + c * wks;
+        }
+      }
+  }
+  // V = L^{-T} W (back substitution per column)
+  std::vector<q> Vt(r * r);
+  for (int c = 0; c < r; ++c)
+    for (int i = r - 1; i >= 0; --i) {
+      q s = W[i * r + c];
+      for (int k = i + 1; k < r; ++k) s -= L[k * r + i] * Vt[k * r + c];
+      Vt[i * r + c] = s / L[i * r + i];
+    }
+  std::vector<int> order(r);
+  for (int i = 0; i < r; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return H[a * r + a] < H[b * r + b]; });
+  lam->resize(r);
+  V->resize(r * r);
+  for (int j = 0; j < r; ++j) {
+    (*lam)[j] = H[order[j] * r + order[j]];
+    for (int i = 0; i < r; ++i) (*V)[i * r + j] = Vt[i * r + order[j]];
+  }
+  return true;
+}
+
+struct AxisJob {
+  int n;
+  int64_t K;
+  const std::vector<q>* A;
+  const std::vector<q>* C;
+  AxisTables* out;
+  bool ok;
+};
+
+// Projected pencil at frequency k (1..K-1) and its eigenpairs.
+bool frequency_block(int n, int64_t K, int64_t k, const std::vector<q>& A,
+                     const std::vector<q>& C, AxisTables* t) {
+  q sp, cp, s2p, c2p;
+  sincospi(k, 2 * K, &sp, &cp);  // psi = pi k / (2K)
+  sincospi(k, K, &s2p, &c2p);    // 2 psi
+  auto terms = channel_terms(n, false);
+  int r = n;
+  auto kap = [&](const Term& a, const Term& b) -> q {
+    int d = a.phase - b.phase;  // phase difference in units of psi
+    q cosd = d == 0 ? (q)1 : (d == 2 || d == -2 ? c2p : cp);
+    q sind = d == 0 ? (q)0 : (d == 2 ? s2p : d == -2 ? -s2p : d == 1 ? sp : -sp);
+    if (a.is_cos == b.is_cos) return cosd;
+    if (!a.is_cos) return sind;   // sum sin(x + a) cos(x + b) = (K/2) sin(a - b)
+    return -sind;                 // sum cos(x + a) sin(x + b) = (K/2) sin(b - a)
+  };
+  std::vector<q> Ma(r * r), Mc(r * r);
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      q sa = 0, sc = 0;
+      for (const Term& ta : terms[a])
+        for (const Term& tb : terms[b]) {
+          q f = (q)(ta.w * tb.w) * kap(ta, tb);
+          sa += f * A[ta.i * (n + 1) + tb.i];
+          sc += f * C[ta.i * (n + 1) + tb.i];
+        }
+      Ma[a * r + b] = sa * (q)K / 2;
+      Mc[a * r + b] = sc * (q)K / 2;
+    }
+  std::vector<q> lam, V;
+  if (!pencil_eigen(r, Ma, Mc, &lam, &V)) return false;
+  for (int l = 0; l < r; ++l) {
+    if (V[0 * r + l] < 0)
+      for (int c = 0; c < r; ++c) V[c * r + l] = -V[c * r + l];
+    t->lam[(n - 1) + (k - 1) * n + l] = (double)lam[l];
+  }
+  double* Qk = &t->Q[(size_t)k * n * n];
+  for (int c = 0; c < r; ++c)
+    for (int l = 0; l < r; ++l) Qk[c * n + l] = (double)V[c * r + l];
+  return true;
+}
+
+// Bubble-only block (k = 0): channels even m (alternating pattern) and odd m
+// (constant pattern); sum over the K elements gives the factor K.
+bool zero_block(int n, int64_t K, const std::vector<q>& A, const std::vector<q>& C,
+                AxisTables* t) {
+  int r = n - 1;
+  if (r == 0) return true;
+  auto terms = channel_terms(n, true);
+  int ne = num_even(n);
+  std::vector<q> Ma(r * r, 0), Mc(r * r, 0);
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      if ((a < ne) != (b < ne)) continue;  // even/odd blocks decouple (bisymmetry)
+      q sa = 0, sc = 0;
+      for (const Term& ta : terms[a])
+        for (const Term& tb : terms[b]) {
+          sa += (q)(ta.w * tb.w) * A[ta.i * (n + 1) + tb.i];
+          sc += (q)(ta.w * tb.w) * C[ta.i * (n + 1) + tb.i];
+        }
+      Ma[a * r + b] = sa * (q)K;
+      Mc[a * r + b] = sc * (q)K;
+    }
+  std::vector<q> lam, V;
+  if (!pencil_eigen(r, Ma, Mc, &lam, &V)) return false;
+  for (int l = 0; l < r; ++l) {
+    int big = 0;
+    for (int c = 1; c < r; ++c)
+      if (qabs(V[c * r + l]) > qabs(V[big * r + l]) * (1 + 1e-20Q)) big = c;
+    if (V[big * r + l] < 0)
+      for (int c = 0; c < r; ++c) V[c * r + l] = -V[c * r + l];
+    t->lam[l] = (double)lam[l];
+  }
+  for (int c = 0; c < r; ++c)
+    for (int l = 0; l < r; ++l) t->Q[c * n + l] = (double)V[c * r + l];
+  return true;
+}
+
+}  // namespace
+
+void element_matrices(int n, std::vector<double>* A, std::vector<double>* C) {
+  std::vector<q> Aq, Cq;
+  element_matrices_q(n, &Aq, &Cq);
+  A->resize(Aq.size());
+  C->resize(Cq.size());
+  for (size_t i = 0; i < Aq.size(); ++i) {
+    (*A)[i] = (double)Aq[i];
+    (*C)[i] = (double)Cq[i];
+  }
+}
+
+int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
+  const int kEINVAL = -1, kESPECTRUM = -4;
+  if (n < 1 || K < 2) return kEINVAL;
+  std::vector<q> A, C;
+  element_matrices_q(n, &A, &C);
+  t->n = n;
+  t->K = K;
+  t->M = (int64_t)n * K - 1;
+  t->coef = diff * 4.0 * ((double)K / X) * ((double)K / X);
+  t->lam.assign(t->M, 0.0);
+  t->Q.assign((size_t)K * n * n, 0.0);
+  if (!zero_block(n, K, A, C, t)) return kESPECTRUM;
+  unsigned hw = std::thread::hardware_concurrency();
+  int nthreads = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
+  if (K < 64) nthreads = 1;
+  std::vector<int> ok(nthreads, 1);
+  auto work = [&](int tid) {
+    for (int64_t k = 1 + tid; k < K; k += nthreads)
+      if (!frequency_block(n, K, k, A, C, t)) ok[tid] = 0;
+  };
+  if (nthreads == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int i = 0; i < nthreads; ++i) th.emplace_back(work, i);
+    for (auto& x : th) x.join();
+  }
+  for (int v : ok)
+    if (!v) return kESPECTRUM;
+  for (double v : t->lam)
+    if (!(v > 0) || !std::isfinite(v)) return kESPECTRUM;
+  t->twf.resize(2 * K);
+  t->twm.resize(2 * K);
+  t->twd.resize(2 * K);
+  for (int64_t k = 0; k < K; ++k) {
+    q s, c;
+    sincospi(2 * k, K, &s, &c);
+    t->twf[2 * k] = (double)c;
+    t->twf[2 * k + 1] = -(double)s;
+    sincospi(k, 2 * K, &s, &c);
+    t->twm[2 * k] = (double)c;
+    t->twm[2 * k + 1] = -(double)s;
+    sincospi(k, K, &s, &c);
+    t->twd[2 * k] = (double)c;
+    t->twd[2 * k + 1] = -(double)s;
+  }
+  return 0;
+}
+
+}  // namespace fftfem

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libfftfem.so (include/fftfem.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+Device arrays are torch tensors on a ROCm device (torch is used for memory
+and streams).  If the library has not been built this module raises on
+import of the library handle; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfftfem.so")
+
+FFTFEM_FP64, FFTFEM_FP32, FFTFEM_FP32_REFINE = 0, 1, 2
+MAX_DIMS, MAX_ITERS = 3, 16
+PRECISIONS = {"fp64": FFTFEM_FP64, "fp32": FFTFEM_FP32, "fp32_refine": FFTFEM_FP32_REFINE}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESPECTRUM", -5: "EINDEF",
+          -6: "ENOCONV", -7: "ENOTIMPL"}
+
+EXPORTS = [
+    "fftfem_plan", "fftfem_plan_ex", "fftfem_solve", "fftfem_apply_A", "fftfem_get_stats",
+    "fftfem_workspace_bytes", "fftfem_destroy", "fftfem_status_string", "fftfem_plan_tables",
+    "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
+]
+
+
+class FftfemError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int),
+        ("K", ctypes.c_int64 * MAX_DIMS),
+        ("n", ctypes.c_int),
+        ("diff", ctypes.c_double * MAX_DIMS),
+        ("react", ctypes.c_double),
+        ("X", ctypes.c_double * MAX_DIMS),
+        ("precision", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("nrhs", ctypes.c_int),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("rel_correction", ctypes.c_double * (MAX_ITERS + 1)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1701_03967_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        L.fftfem_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.c_int, dp, ctypes.c_double]
+        L.fftfem_plan_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Desc)]
+        L.fftfem_solve.argtypes = [vp, vp, vp, vp]
+        L.fftfem_apply_A.argtypes = [vp, vp, vp, vp]
+        L.fftfem_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.fftfem_workspace_bytes.argtypes = [vp]
+        L.fftfem_workspace_bytes.restype = ctypes.c_size_t
+        L.fftfem_destroy.argtypes = [vp]
+        L.fftfem_destroy.restype = None
+        L.fftfem_status_string.argtypes = [ctypes.c_int]
+        L.fftfem_status_string.restype = ctypes.c_char_p
+        L.fftfem_plan_tables.argtypes = [vp, ctypes.c_int, dp, dp]
+        L.fftfem_debug_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+        L.fftfem_axis_tables_host.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp]
+        L.fftfem_element_matrices_host.argtypes = [ctypes.c_int, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise FftfemError(rc, what)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def axis_tables_host(n: int, K: int):
+    """(lam, Q) of one axis computed on the host (no device needed)."""
+    lam = np.zeros(n * K - 1)
+    Q = np.zeros(K * n * n)
+    _check(lib().fftfem_axis_tables_host(n, K, _dptr(lam), _dptr(Q)), "axis_tables_host")
+    return lam, Q.reshape(K, n, n)
+
+
+def element_matrices_host(n: int):
+    A = np.zeros((n + 1) * (n + 1))
+    C = np.zeros((n + 1) * (n + 1))
+    _check(lib().fftfem_element_matrices_host(n, _dptr(A), _dptr(C)), "element_matrices_host")
+    return A.reshape(n + 1, n + 1), C.reshape(n + 1, n + 1)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _tptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan: fixed sizes, coefficients and precision mode."""
+
+    def __init__(self, K: Sequence[int], n: int, diff: Sequence[float], react: float = 0.0,
+                 X: Optional[Sequence[float]] = None, precision: str = "fp64",
+                 max_iter: int = 0, tol: float = 0.0, nrhs: int = 1):
+        d = Desc()
+        d.N = len(K)
+        for i, k in enumerate(K):
+            d.K[i] = int(k)
+            d.diff[i] = float(diff[i])
+            d.X[i] = float(X[i]) if X is not None else 0.0
+        d.n = int(n)
+        d.react = float(react)
+        d.precision = PRECISIONS[precision]
+        d.max_iter = int(max_iter)
+        d.tol = float(tol)
+        d.nrhs = int(nrhs)
+        h = ctypes.c_void_p()
+        _check(lib().fftfem_plan_ex(ctypes.byref(h), ctypes.byref(d)), "fftfem_plan_ex")
+        self._h = h
+        self.K = tuple(int(k) for k in K)
+        self.n = int(n)
+        self.nrhs = int(nrhs)
+        self.shape = tuple(self.n * k - 1 for k in self.K)
+        self.precision = precision
+
+    def close(self):
+        if self._h:
+            lib().fftfem_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _full_shape(self):
+        return ((self.nrhs,) if self.nrhs > 1 else ()) + self.shape
+
+    def _check_tensor(self, t, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and tuple(t.shape) == self._full_shape()):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape "
+                             f"{self._full_shape()}")
+
+    def solve(self, f, u=None, stream=None):
+        import torch
+        self._check_tensor(f, "f")
+        if u is None:
+            u = torch.empty_like(f)
+        self._check_tensor(u, "u")
+        _check(lib().fftfem_solve(self._h, _tptr(f), _tptr(u), _stream_ptr(stream)), "fftfem_solve")
+        return u
+
+    def apply_A(self, u, y=None, stream=None):
+        import torch
+        self._check_tensor(u, "u")
+        if y is None:
+            y = torch.empty_like(u)
+        self._check_tensor(y, "y")
+        _check(lib().fftfem_apply_A(self._h, _tptr(u), _tptr(y), _stream_ptr(stream)), "fftfem_apply_A")
+        return y
+
+    def stats(self):
+        s = Stats()
+        _check(lib().fftfem_get_stats(self._h, ctypes.byref(s)), "fftfem_get_stats")
+        return {"iterations": s.iterations, "converged": bool(s.converged),
+                "rel_correction": list(s.rel_correction)[:max(1, s.iterations + 1)]}
+
+    def tables(self, axis: int):
+        M = self.shape[axis]
+        K = self.K[axis]
+        lam = np.zeros(M)
+        Q = np.zeros(K * self.n * self.n)
+        _check(lib().fftfem_plan_tables(self._h, axis, _dptr(lam), _dptr(Q)), "fftfem_plan_tables")
+        return lam, Q.reshape(K, self.n, self.n)
+
+    def workspace_bytes(self) -> int:
+        return int(lib().fftfem_workspace_bytes(self._h))
+
+    def debug_transform(self, axis: int, direction: int, x, out=None, dtype: str = "fp64",
+                        stream=None):
+        import torch
+        self._check_tensor(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().fftfem_debug_transform(self._h, axis, direction, _tptr(x), _tptr(out),
+                                            0 if dtype == "fp64" else 1, _stream_ptr(stream)),
+               "fftfem_debug_transform")
+        return out
