@@ -153,6 +153,19 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
                            int dtype, hipStream_t s);
 
 /*
+ * Per-kernel timing, for measurement.  With timing enabled, every kernel a
+ * solve or apply launches is bracketed by HIP events recorded on the same
+ * stream (the events are created on first use; do not enable it under graph
+ * capture).  fftfem_get_timing synchronizes, and returns for up to `max`
+ * distinct kernels (in first-launch order) a NUL-terminated name of at most
+ * 31 characters in names[32*i], the mean duration in milliseconds and the
+ * number of launches since the previous call; it then clears the record.
+ * Returns the number of distinct kernels (>= 0) or a negative status.
+ */
+int fftfem_set_timing(fftfem_plan_t p, int enable);
+int fftfem_get_timing(fftfem_plan_t p, int max, char* names, double* avg_ms, int* count);
+
+/*
  * Host-only access to the plan arithmetic, for tests on machines without a
  * GPU (no device is touched).  fftfem_axis_tables_host: the lam and Q tables
  * of fftfem_plan_tables for one axis of n-th order elements on K elements.

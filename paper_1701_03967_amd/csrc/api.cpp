@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fftfem.h"
@@ -47,6 +48,16 @@ struct fftfem_plan_s {
   int lds_max = 65536;
   hipStream_t last = nullptr;
   std::vector<void*> allocs;
+  // per-kernel timing (measurement only)
+  bool timing = false;
+  struct Mark {
+    int name;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<std::string> names;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
 };
 
 namespace {
@@ -57,6 +68,47 @@ int from_hip(hipError_t e) {
   if (e == hipSuccess) return FFTFEM_OK;
   if (e == hipErrorOutOfMemory) return FFTFEM_ENOMEM;
   return FFTFEM_EHIP;
+}
+
+hipEvent_t take_event(fftfem_plan_t p) {
+  if (p->pool_used == p->pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->pool.push_back(e);
+  }
+  return p->pool[p->pool_used++];
+}
+
+// Brackets one launch with events when timing is on.
+struct Timed {
+  fftfem_plan_t p;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  int name = -1;
+  Timed(fftfem_plan_t p_, hipStream_t s_, const std::string& nm) : p(p_), s(s_) {
+    if (!p->timing) return;
+    for (size_t i = 0; i < p->names.size(); ++i)
+      if (p->names[i] == nm) name = (int)i;
+    if (name < 0) {
+      p->names.push_back(nm);
+      name = (int)p->names.size() - 1;
+    }
+    a = take_event(p);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(p);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    p->marks.push_back({name, a, b});
+  }
+};
+
+const char* mode_name(int mode, bool upd) {
+  if (mode == FWD) return "fwd";
+  if (mode == INV) return upd ? "inv_upd" : "inv";
+  return upd ? "mid_upd" : "mid";
 }
 
 int dev_alloc(fftfem_plan_t p, void** ptr, size_t bytes) {
@@ -170,6 +222,8 @@ int line_pass(fftfem_plan_t p, int axis, int mode, const void* in, int in_f64, v
   if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
   if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
+  Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +
+                    "_ax" + std::to_string(axis));
   return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
 }
 
@@ -205,6 +259,7 @@ int apply_pass(fftfem_plan_t p, int axis, const double* in1, const double* in2, 
   int64_t W = a.TL + 2 * p->n;
   size_t lds = (size_t)(in2 ? 2 : 1) * a.G * W * sizeof(double);
   int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
+  Timed tm(p, s, std::string("apply_ax") + std::to_string(axis));
   return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
 }
 
@@ -285,6 +340,7 @@ const char* fftfem_status_string(int st) {
 
 void fftfem_destroy(fftfem_plan_t p) {
   if (!p) return;
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
   delete p;
 }
@@ -484,6 +540,37 @@ int fftfem_get_stats(fftfem_plan_t p, fftfem_stats* out) {
 }
 
 size_t fftfem_workspace_bytes(const fftfem_plan_t p) { return p ? p->bytes : 0; }
+
+int fftfem_set_timing(fftfem_plan_t p, int enable) {
+  if (!p) return FFTFEM_EINVAL;
+  p->timing = enable != 0;
+  return FFTFEM_OK;
+}
+
+int fftfem_get_timing(fftfem_plan_t p, int max, char* names, double* avg_ms, int* count) {
+  if (!p || max < 0 || (max > 0 && (!names || !avg_ms || !count))) return FFTFEM_EINVAL;
+  int rc = from_hip(hipDeviceSynchronize());
+  if (rc) return rc;
+  std::vector<double> sum(p->names.size(), 0.0);
+  std::vector<int> cnt(p->names.size(), 0);
+  for (const auto& m : p->marks) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) return FFTFEM_EHIP;
+    sum[m.name] += ms;
+    cnt[m.name] += 1;
+  }
+  int nk = (int)p->names.size();
+  for (int i = 0; i < nk && i < max; ++i) {
+    std::memset(names + 32 * i, 0, 32);
+    std::strncpy(names + 32 * i, p->names[i].c_str(), 31);
+    avg_ms[i] = cnt[i] ? sum[i] / cnt[i] : 0.0;
+    count[i] = cnt[i];
+  }
+  p->marks.clear();
+  p->names.clear();
+  p->pool_used = 0;
+  return nk;
+}
 
 int fftfem_plan_tables(const fftfem_plan_t p, int axis, double* lam, double* Q) {
   if (!p || axis < 0 || axis >= p->N || !lam) return FFTFEM_EINVAL;

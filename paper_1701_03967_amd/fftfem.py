@@ -27,6 +27,7 @@ EXPORTS = [
     "fftfem_plan", "fftfem_plan_ex", "fftfem_solve", "fftfem_apply_A", "fftfem_get_stats",
     "fftfem_workspace_bytes", "fftfem_destroy", "fftfem_status_string", "fftfem_plan_tables",
     "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
+    "fftfem_set_timing", "fftfem_get_timing",
 ]
 
 
@@ -87,6 +88,9 @@ def lib():
         L.fftfem_debug_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
         L.fftfem_axis_tables_host.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp]
         L.fftfem_element_matrices_host.argtypes = [ctypes.c_int, dp, dp]
+        L.fftfem_set_timing.argtypes = [vp, ctypes.c_int]
+        L.fftfem_get_timing.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, dp,
+                                        ctypes.POINTER(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -207,6 +211,24 @@ class Plan:
         Q = np.zeros(K * self.n * self.n)
         _check(lib().fftfem_plan_tables(self._h, axis, _dptr(lam), _dptr(Q)), "fftfem_plan_tables")
         return lam, Q.reshape(K, self.n, self.n)
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().fftfem_set_timing(self._h, int(enable)), "fftfem_set_timing")
+
+    def get_timing(self):
+        """{kernel name: (mean ms, launches)} since the last call."""
+        mx = 64
+        names = ctypes.create_string_buffer(32 * mx)
+        avg = np.zeros(mx)
+        cnt = (ctypes.c_int * mx)()
+        nk = lib().fftfem_get_timing(self._h, mx, names, _dptr(avg), cnt)
+        if nk < 0:
+            _check(nk, "fftfem_get_timing")
+        out = {}
+        for i in range(min(nk, mx)):
+            nm = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (float(avg[i]), int(cnt[i]))
+        return out
 
     def workspace_bytes(self) -> int:
         return int(lib().fftfem_workspace_bytes(self._h))
