@@ -33,12 +33,14 @@ METRIC = "solve time & unknowns/s, n=9 2D/3D; FP32+refine vs FP64 at rel err ≤
 def kernel_bytes(name: str, size: int, N: int) -> float:
     """Algorithmic HBM bytes of one launch of a named kernel (one read and one
     write of every array it touches)."""
-    last = N - 1
-    ax = int(name.rsplit("_ax", 1)[1])
+    t = 4 if "32" in name.split("_")[0] else 8
+    if name.startswith("transpose"):
+        return size * 2 * t
     if name.startswith("apply"):
         return 0.0
-    fp32 = "32_" in name
-    t = 4 if fp32 else 8
+    last = N - 1
+    ax_s = name.rsplit("_ax", 1)[1]
+    ax = int(ax_s.rstrip("t"))
     if name.startswith("fwd"):
         rd = 8 if ax == last else t
         return size * (rd + t)

@@ -49,12 +49,13 @@ def build(verbose: bool = True) -> str:
     objs.append(api_o)
     if verbose:
         print(f"[build] api.cpp {dt:.1f}s", flush=True)
-    ker_o = os.path.join(BUILD, "kernels.o")
-    dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
-               "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, "kernels.hip"), "-o", ker_o])
-    objs.append(ker_o)
-    if verbose:
-        print(f"[build] kernels.hip {dt:.1f}s", flush=True)
+    for src in ("line.hip", "ops.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
+                   "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+        if verbose:
+            print(f"[build] {src} {dt:.1f}s", flush=True)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)

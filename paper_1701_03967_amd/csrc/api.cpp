@@ -38,6 +38,9 @@ struct fftfem_plan_s {
   double* Ael = nullptr;
   double* Cel = nullptr;
   float* W32 = nullptr;      // float32 workspace (float32 modes)
+  float* W32b = nullptr;     // second float32 workspace (transposed 2D schedule)
+  double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
+  bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   double* tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // operator-apply partial products
   int ntmp = 0;
   double* partials = nullptr;
@@ -159,16 +162,54 @@ int validate(const fftfem_desc* d) {
   return FFTFEM_OK;
 }
 
-// Lines per workgroup for a line pass: as many as fit the LDS budget, the
-// register-held contraction tasks (G * ceil(K/2) <= 1024) and 64.
+// Lines per workgroup for a line pass: a power of two with G * K <= 1024
+// (per-thread task registers), G lines of LDS within the budget (64 KB, or
+// one line when a line alone is larger), at most 64 and at most nlines.
+size_t line_lds(const fftfem_plan_s* p, int64_t K, size_t elt, bool pad = true) {
+  return (size_t)(1 + p->n / 2) * (K + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
+}
+
 int choose_G(const fftfem_plan_s* p, int64_t K, size_t elt, int64_t nlines) {
-  size_t per = (size_t)(1 + p->n / 2) * K * 2 * elt;
-  int64_t halfK = (K + 1) / 2;
-  size_t budget = std::max<size_t>(per, 65536);
+  size_t per = line_lds(p, K, elt);
+  size_t budget = std::max<size_t>(line_lds(p, K, elt, false), 65536);
   int G = 1;
-  while (G < 64 && (size_t)(2 * G) * per <= budget && 2 * G * halfK <= 1024 && 2 * G <= nlines)
+  while (G < 64 && (size_t)(2 * G) * per <= budget && 2 * G * K <= kLineTasks && 2 * G <= nlines)
     G *= 2;
   return G;
+}
+
+int ilog2i(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+// Geometry of one line pass: which axis' tables, the line length, the
+// element stride, the number of lines, and where the other axes' spectral
+// indices are found (for the division in a MID pass).
+struct Geom {
+  int axis = 0;
+  int64_t M = 0, es = 1, nlines = 0;
+  int nother = 0;
+  int oaxis[2] = {0, 0};
+  int64_t so[2] = {1, 1}, Mo[2] = {1, 1};
+};
+
+Geom natural_geom(const fftfem_plan_s* p, int axis, bool others) {
+  Geom g;
+  g.axis = axis;
+  g.M = p->M[axis];
+  g.es = p->stride[axis];
+  g.nlines = p->size / g.M;
+  if (others)
+    for (int e = 0; e < p->N; ++e)
+      if (e != axis) {
+        g.oaxis[g.nother] = e;
+        g.so[g.nother] = p->stride[e];
+        g.Mo[g.nother] = p->M[e];
+        ++g.nother;
+      }
+  return g;
 }
 
 template <typename T>
@@ -182,14 +223,12 @@ const float* tab<float>(const fftfem_plan_s* p, int axis, int which) {
   return p->dev[axis].f[which];
 }
 
-// One line pass along `axis`.  `others` selects whether the other axes'
-// denominators enter the MID division (false for the 1D debug transform).
+// One line pass.
 template <typename T>
-int line_pass(fftfem_plan_t p, int axis, int mode, const void* in, int in_f64, void* out,
-              int out_f64, const double* upd, const int* flag, hipStream_t s, bool others,
-              bool want_partials) {
+int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_f64, void* out,
+              int out_f64, const double* upd, const int* flag, hipStream_t s, bool want_partials) {
   LineArgs<T> a{};
-  const AxisTables& t = p->host[axis];
+  const AxisTables& t = p->host[gm.axis];
   a.in = in;
   a.out = out;
   a.upd = upd;
@@ -197,34 +236,38 @@ int line_pass(fftfem_plan_t p, int axis, int mode, const void* in, int in_f64, v
   a.out_f64 = out_f64;
   a.K = (int)t.K;
   a.log2K = ilog2(t.K);
-  a.M = t.M;
-  a.es = p->stride[axis];
-  a.nlines = p->size / t.M;
+  a.M = gm.M;
+  a.es = gm.es;
+  a.nlines = gm.nlines;
   a.G = choose_G(p, t.K, sizeof(T), a.nlines);
-  a.Q = tab<T>(p, axis, 0);
-  a.twf = tab<T>(p, axis, 1);
-  a.twm = tab<T>(p, axis, 2);
-  a.twd = tab<T>(p, axis, 3);
-  a.mu_self = tab<T>(p, axis, 4);
+  a.log2G = ilog2i(a.G);
+  a.Q = tab<T>(p, gm.axis, 0);
+  a.twf = tab<T>(p, gm.axis, 1);
+  a.twm = tab<T>(p, gm.axis, 2);
+  a.twd = tab<T>(p, gm.axis, 3);
+  a.mu_self = tab<T>(p, gm.axis, 4);
   a.react = (T)p->desc.react;
-  a.nother = 0;
-  if (others)
-    for (int e = 0; e < p->N; ++e)
-      if (e != axis) {
-        a.mu_o[a.nother] = tab<T>(p, e, 4);
-        a.so[a.nother] = p->stride[e];
-        a.Mo[a.nother] = p->M[e];
-        ++a.nother;
-      }
+  a.nother = gm.nother;
+  for (int e = 0; e < gm.nother; ++e) {
+    a.mu_o[e] = tab<T>(p, gm.oaxis[e], 4);
+    a.so[e] = gm.so[e];
+    a.Mo[e] = gm.Mo[e];
+  }
   a.partials = want_partials ? p->partials : nullptr;
   a.flag = flag;
-  size_t lds = (size_t)a.G * (1 + p->n / 2) * t.K * 2 * sizeof(T);
+  size_t lds = (size_t)a.G * line_lds(p, t.K, sizeof(T), a.G > 1);
   if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
   if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +
-                    "_ax" + std::to_string(axis));
+                    "_ax" + std::to_string(gm.axis) + (gm.es == 1 && gm.axis != p->N - 1 ? "t" : ""));
   return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
+}
+
+template <typename T>
+int transpose(fftfem_plan_t p, const T* in, T* out, int64_t R, int64_t C, hipStream_t s) {
+  Timed tm(p, s, std::string("transpose") + (sizeof(T) == 4 ? "32" : "64"));
+  return from_hip(launch_transpose<T>(in, out, p->size / (R * C), R, C, s));
 }
 
 // One operator pass along `axis` (see ApplyArgs in launch.h).
@@ -291,26 +334,46 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
 }
 
 // Forward on axes N-1..1, MID on axis 0, inverse on axes 1..N-1.
-// work: T array used in place between passes (may equal out when T is double).
+// work: T array used in place between passes (may equal out when T is double);
+// work2: second T array for the transposed 2D schedule.
 template <typename T>
-int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, double* out,
+int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* work2, double* out,
                     const double* upd, const int* flag, hipStream_t s, bool partials) {
   int N = p->N, rc;
   if (N == 1)
-    return line_pass<T>(p, 0, MID, in, in_f64, out, 1, upd, flag, s, true, partials);
-  rc = line_pass<T>(p, N - 1, FWD, in, in_f64, work, 0, nullptr, flag, s, true, false);
+    return line_pass<T>(p, natural_geom(p, 0, true), MID, in, in_f64, out, 1, upd, flag, s, partials);
+  rc = line_pass<T>(p, natural_geom(p, N - 1, true), FWD, in, in_f64, work, 0, nullptr, flag, s, false);
   if (rc) return rc;
   for (int d = N - 2; d >= 1; --d) {
-    rc = line_pass<T>(p, d, FWD, work, 0, work, 0, nullptr, flag, s, true, false);
+    rc = line_pass<T>(p, natural_geom(p, d, true), FWD, work, 0, work, 0, nullptr, flag, s, false);
     if (rc) return rc;
   }
-  rc = line_pass<T>(p, 0, MID, work, 0, work, 0, nullptr, flag, s, true, false);
-  if (rc) return rc;
+  if (N == 2 && p->tr2d) {
+    // axis 0 as contiguous lines of a transposed copy: (M0 x M1) -> (M1 x M0)
+    rc = transpose<T>(p, work, work2, p->M[0], p->M[1], s);
+    if (rc) return rc;
+    Geom g;
+    g.axis = 0;
+    g.M = p->M[0];
+    g.es = 1;
+    g.nlines = p->M[1];
+    g.nother = 1;
+    g.oaxis[0] = 1;
+    g.so[0] = p->M[0];
+    g.Mo[0] = p->M[1];
+    rc = line_pass<T>(p, g, MID, work2, 0, work2, 0, nullptr, flag, s, false);
+    if (rc) return rc;
+    rc = transpose<T>(p, work2, work, p->M[1], p->M[0], s);
+    if (rc) return rc;
+  } else {
+    rc = line_pass<T>(p, natural_geom(p, 0, true), MID, work, 0, work, 0, nullptr, flag, s, false);
+    if (rc) return rc;
+  }
   for (int d = 1; d <= N - 2; ++d) {
-    rc = line_pass<T>(p, d, INV, work, 0, work, 0, nullptr, flag, s, true, false);
+    rc = line_pass<T>(p, natural_geom(p, d, true), INV, work, 0, work, 0, nullptr, flag, s, false);
     if (rc) return rc;
   }
-  return line_pass<T>(p, N - 1, INV, work, 0, out, 1, upd, flag, s, true, partials);
+  return line_pass<T>(p, natural_geom(p, N - 1, true), INV, work, 0, out, 1, upd, flag, s, partials);
 }
 
 int64_t max_blocks_last_pass(const fftfem_plan_s* p, size_t elt) {
@@ -417,7 +480,13 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
     const AxisTables& t = p->host[i];
     std::vector<double> mu(t.lam.size());
     for (size_t c = 0; c < mu.size(); ++c) mu[c] = p->coef[i] * t.lam[c];
-    const std::vector<double>* src[5] = {&t.Q, &t.twf, &t.twm, &t.twd, &mu};
+    // Q in structure-of-arrays order for the kernels: (c, l, k) -> (c n + l) K + k
+    std::vector<double> qs(t.Q.size());
+    for (int64_t k = 0; k < t.K; ++k)
+      for (int c = 0; c < d.n; ++c)
+        for (int l = 0; l < d.n; ++l)
+          qs[(size_t)(c * d.n + l) * t.K + k] = t.Q[(size_t)k * d.n * d.n + c * d.n + l];
+    const std::vector<double>* src[5] = {&qs, &t.twf, &t.twm, &t.twd, &mu};
     for (int w = 0; w < 5 && !rc; ++w) {
       rc = upload<double>(p, &p->dev[i].d[w], *src[w]);
       if (!rc) rc = upload<float>(p, &p->dev[i].f[w], *src[w]);
@@ -430,8 +499,17 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
     if (!rc) rc = upload<double>(p, &p->Cel, C);
   }
   // workspace
+  size_t elt = d.precision == FFTFEM_FP64 ? sizeof(double) : sizeof(float);
+  if (d.N == 2) {
+    int G0 = choose_G(p, p->K[0], elt, p->size / p->M[0]);
+    p->tr2d = (size_t)G0 * elt < 64;
+  }
   if (!rc && d.precision != FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W32, (size_t)p->size * sizeof(float));
+  if (!rc && p->tr2d && d.precision != FFTFEM_FP64)
+    rc = dev_alloc(p, (void**)&p->W32b, (size_t)p->size * sizeof(float));
+  if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
+    rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
   p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 2 : 4);
   for (int i = 0; i < p->ntmp && !rc; ++i)
     rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
@@ -492,14 +570,14 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
     rc = from_hip(launch_reset(flag, st, kStatsLen, s));
     if (rc) break;
     if (p->desc.precision == FFTFEM_FP64) {
-      rc = transform_chain<double>(p, fr, 1, ur, ur, nullptr, nullptr, s, false);
+      rc = transform_chain<double>(p, fr, 1, ur, p->W64b, ur, nullptr, nullptr, s, false);
       continue;
     }
-    rc = transform_chain<float>(p, fr, 1, p->W32, ur, nullptr, nullptr, s, false);
+    rc = transform_chain<float>(p, fr, 1, p->W32, p->W32b, ur, nullptr, nullptr, s, false);
     if (rc || p->desc.precision == FFTFEM_FP32) continue;
     for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
       rc = operator_apply(p, ur, fr, p->W32, 0, flag, s);
-      if (!rc) rc = transform_chain<float>(p, p->W32, 0, p->W32, ur, ur, flag, s, true);
+      if (!rc) rc = transform_chain<float>(p, p->W32, 0, p->W32, p->W32b, ur, ur, flag, s, true);
       if (!rc)
         rc = from_hip(launch_reduce(p->partials, (int)max_blocks_last_pass(p, sizeof(float)), it,
                                     p->desc.tol, flag, st, s));
@@ -605,9 +683,9 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
   if (dtype != 0 && dtype != 1) return FFTFEM_EINVAL;
   int mode = dir > 0 ? FWD : (dir < 0 ? INV : MID);
   p->last = s;
-  if (dtype == 0)
-    return line_pass<double>(p, axis, mode, in, 1, out, 1, nullptr, nullptr, s, false, false);
-  return line_pass<float>(p, axis, mode, in, 1, out, 1, nullptr, nullptr, s, false, false);
+  Geom g = natural_geom(p, axis, false);
+  if (dtype == 0) return line_pass<double>(p, g, mode, in, 1, out, 1, nullptr, nullptr, s, false);
+  return line_pass<float>(p, g, mode, in, 1, out, 1, nullptr, nullptr, s, false);
 }
 
 }  // extern "C"

@@ -1,0 +1,188 @@
+// Batched in-place Stockham FFT in LDS, radix 16/8/4/2, for power-of-two K.
+//
+// Chunks of the butterfly range (NT * 16/R butterflies) always cover whole
+// buffers when K <= NT * 16.
+//
+// Stage with radix R after Ns points have been combined: butterfly j
+// (0 <= j < K/R) reads x[j + r K/R], r < R, multiplies input r by
+// exp(-+2 pi i r (j mod Ns) / (Ns R)), takes an R-point DFT and writes output
+// s to (j - j mod Ns) R + (j mod Ns) + s Ns.  Every thread first reads up to
+// 16/R butterflies into registers, the workgroup synchronizes, and then all
+// write: reads and writes of one pass always cover whole buffers, so the
+// stage can run in place.  Twiddles come from a table exp(-2 pi i q / K).
+#pragma once
+
+#include "device_common.h"
+
+namespace fftfem {
+
+// cos/sin of pi/8 and pi/4
+template <typename T>
+struct Rt {
+  static constexpr T c8 = (T)0.92387953251128675612818318939678829;
+  static constexpr T s8 = (T)0.38268343236508977172845998403039887;
+  static constexpr T h = (T)0.70710678118654752440084436210484904;
+};
+
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> mul_mi(C2<T> a) {
+  return INV ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(C2<T>& a, C2<T>& b) {
+  C2<T> s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+
+// 4-point DFT of (a, b, c, d) in place: outputs in natural order
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(C2<T>& a, C2<T>& b, C2<T>& c, C2<T>& d) {
+  C2<T> s02 = cadd(a, c), d02 = csub(a, c), s13 = cadd(b, d), d13 = mul_mi<T, INV>(csub(b, d));
+  a = cadd(s02, s13);
+  c = csub(s02, s13);
+  b = cadd(d02, d13);
+  d = csub(d02, d13);
+}
+
+// constant twiddle w_N^e for N in {8, 16}, forward sign; conjugated for INV
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> tw_mul16(C2<T> v, int e) {
+  // e in 0..15, w16^e = exp(-2 pi i e / 16)
+  const T c8 = Rt<T>::c8, s8 = Rt<T>::s8, h = Rt<T>::h;
+  C2<T> w;
+  switch (e & 15) {
+    case 0: return v;
+    case 1: w = {c8, -s8}; break;
+    case 2: w = {h, -h}; break;
+    case 3: w = {s8, -c8}; break;
+    case 4: return mul_mi<T, INV>(v);
+    case 5: w = {-s8, -c8}; break;
+    case 6: w = {-h, -h}; break;
+    case 7: w = {-c8, -s8}; break;
+    case 8: return C2<T>{-v.x, -v.y};
+    case 9: w = {-c8, s8}; break;
+    case 10: w = {-h, h}; break;
+    case 11: w = {-s8, c8}; break;
+    case 12: return mul_mi<T, !INV>(v);
+    case 13: w = {s8, c8}; break;
+    case 14: w = {h, h}; break;
+    default: w = {c8, s8}; break;
+  }
+  return INV ? cmulc(v, w) : cmul(v, w);
+}
+
+// In-register R-point DFT, natural order in and out.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_small(C2<T>* v) {
+  if constexpr (R == 2) {
+    dft2<T, INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<T, INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // r = r1 + 4 r2 (r1 < 4, r2 < 2); s = s2 + 2 s1
+    C2<T> y[4][2];
+#pragma unroll
+    for (int r1 = 0; r1 < 4; ++r1) {
+      y[r1][0] = cadd(v[r1], v[r1 + 4]);
+      y[r1][1] = csub(v[r1], v[r1 + 4]);
+      y[r1][1] = tw_mul16<T, INV>(y[r1][1], 2 * r1);  // w8^(r1 * 1)
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      C2<T> a = y[0][s2], b = y[1][s2], c = y[2][s2], d = y[3][s2];
+      dft4<T, INV>(a, b, c, d);
+      v[s2] = a;
+      v[s2 + 2] = b;
+      v[s2 + 4] = c;
+      v[s2 + 6] = d;
+    }
+  } else {
+    static_assert(R == 16, "radix");
+    // r = r1 + 4 r2, s = s2 + 4 s1
+    C2<T> y[4][4];
+#pragma unroll
+    for (int r1 = 0; r1 < 4; ++r1) {
+      C2<T> a = v[r1], b = v[r1 + 4], c = v[r1 + 8], d = v[r1 + 12];
+      dft4<T, INV>(a, b, c, d);
+      y[r1][0] = a;
+      y[r1][1] = tw_mul16<T, INV>(b, r1);
+      y[r1][2] = tw_mul16<T, INV>(c, 2 * r1);
+      y[r1][3] = tw_mul16<T, INV>(d, 3 * r1);
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      C2<T> a = y[0][s2], b = y[1][s2], c = y[2][s2], d = y[3][s2];
+      dft4<T, INV>(a, b, c, d);
+      v[s2] = a;
+      v[s2 + 4] = b;
+      v[s2 + 8] = c;
+      v[s2 + 12] = d;
+    }
+  }
+}
+
+template <typename T, int R, bool INV, int NT>
+__device__ __forceinline__ void fft_stage(C2<T>* buf, int nfft, int lk, int Ns, int lns,
+                                          const C2<T>* __restrict__ tw, int ls) {
+  constexpr int MAXB = 16 / R;
+  constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : (R == 8 ? 3 : 4));
+  const int K = 1 << lk;
+  const int lkr = lk - LR;  // log2(K/R)
+  const int KR = 1 << lkr;
+  const int total = nfft << lkr;
+  const int tid = threadIdx.x;
+  const int lts = lk - lns - LR;  // log2 of the twiddle stride K/(Ns R)
+  for (int base = 0; base < total; base += NT * MAXB) {
+    C2<T> v[MAXB][R];
+    int dst[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+      int b = base + t * NT + tid;
+      dst[t] = -1;
+      if (b < total) {
+        int f = b >> lkr, j = b & (KR - 1);
+        C2<T>* x = buf + f * ls;
+        int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t][r] = x[j + r * KR];
+        if (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            C2<T> w = tw[(r * k) << lts];
+            v[t][r] = INV ? cmulc(v[t][r], w) : cmul(v[t][r], w);
+          }
+        }
+        dft_small<T, R, INV>(v[t]);
+        dst[t] = f * ls + ((j - k) << LR) + k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t)
+      if (dst[t] >= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[dst[t] + r * Ns] = v[t][r];
+      }
+    __syncthreads();
+  }
+}
+
+// All stages: radix 16 while possible, then one of 8, 4 or 2.  Buffer f
+// starts at buf + f * ls (ls >= K complex values).
+template <typename T, bool INV, int NT>
+__device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls) {
+  int lns = 0, rem = lk;
+  while (rem >= 4) {
+    fft_stage<T, 16, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+    lns += 4;
+    rem -= 4;
+  }
+  if (rem == 3) fft_stage<T, 8, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+  if (rem == 2) fft_stage<T, 4, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+  if (rem == 1) fft_stage<T, 2, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+}
+
+}  // namespace fftfem

@@ -17,7 +17,7 @@ struct LineArgs {
   int in_f64, out_f64;
   int K, log2K;
   int64_t M, es, nlines;
-  int G;                  // lines per tile
+  int G, log2G;           // lines per tile (a power of two)
   const T* Q;             // K blocks of n*n
   const T* twf;           // K complex exp(-2 pi i q/K)
   const T* twm;           // K complex exp(-i pi k/(2K))
@@ -52,11 +52,14 @@ template <typename T>
 hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
                        hipStream_t s);
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);
 hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nparts, int iter, double tol, int* flag,
                          double* stats, hipStream_t s);
 
 constexpr int kBlock = 256;        // threads per workgroup of every kernel
+constexpr int kLineTasks = 1024;   // G * K limit of one line-kernel tile
 constexpr int kMaxLineOrder = 9;   // element orders compiled into the line kernels
 
 }  // namespace fftfem
