@@ -76,6 +76,39 @@ def apply_A(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], reac
     return y
 
 
+def apply_A_exact(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+                  X=None) -> np.ndarray:
+    """y = A u in exact rational arithmetic, returned correctly rounded to float64.
+
+    The float64 entries of u, diff, react and X are taken at their exact
+    binary values; the element matrices are the exact rationals of Sect. 2;
+    every product and sum is a Python Fraction.  Slow (object arrays): small
+    inputs only.  The reference for float64 results of an operator whose
+    stiffness rows cancel by a factor ~(nK)^2 on smooth inputs.
+    """
+    from fractions import Fraction
+    from .element import element_matrices_exact
+    Ae, Ce = element_matrices_exact(n)
+    A = np.array(Ae, dtype=object)
+    C = np.array(Ce, dtype=object)
+    N = len(K)
+    Xs = [1.0] * N if X is None else list(X)
+    coef = [Fraction(diff[d]) * 4 * (Fraction(K[d]) / Fraction(Xs[d])) ** 2 for d in range(N)]
+    uq = np.vectorize(Fraction, otypes=[object])(np.asarray(u, dtype=np.float64))
+    y = np.zeros(uq.shape, dtype=object)
+    for d in range(N):
+        t = uq
+        for e in range(N):
+            t = apply_elementwise(A if e == d else C, t, e)
+        y = y + coef[d] * t
+    if react != 0.0:
+        t = uq
+        for e in range(N):
+            t = apply_elementwise(C, t, e)
+        y = y + Fraction(react) * t
+    return np.vectorize(float, otypes=[np.float64])(y)
+
+
 class EigenSolver:
     """u = A^{-1} f by per-axis dense eigendecomposition, plus refinement."""
 

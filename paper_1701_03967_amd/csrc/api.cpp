@@ -40,11 +40,13 @@ struct fftfem_plan_s {
   float* W32 = nullptr;      // float32 workspace (float32 modes)
   float* W32b = nullptr;     // second float32 workspace (transposed 2D schedule)
   double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
+  double* W64r = nullptr;    // float64 residual (float32 + refinement, 1D)
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
-  double* tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // operator-apply partial products
+  double* tmp[8] = {};       // operator-apply partial products (double-double planes)
   int ntmp = 0;
   double* partials = nullptr;
   int npartials = 0;
+  int nparts_last = 0;       // partial sums written by the last update pass
   int* flags = nullptr;      // one per rhs
   double* stats = nullptr;   // (2 + FFTFEM_MAX_ITERS + 1) per rhs
   size_t bytes = 0;
@@ -226,14 +228,14 @@ const float* tab<float>(const fftfem_plan_s* p, int axis, int which) {
 // One line pass.
 template <typename T>
 int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_f64, void* out,
-              int out_f64, const double* upd, const int* flag, hipStream_t s, bool want_partials) {
+              int out_kind, const double* upd, const int* flag, hipStream_t s, bool want_partials) {
   LineArgs<T> a{};
   const AxisTables& t = p->host[gm.axis];
   a.in = in;
   a.out = out;
   a.upd = upd;
   a.in_f64 = in_f64;
-  a.out_f64 = out_f64;
+  a.out_kind = out_kind;
   a.K = (int)t.K;
   a.log2K = ilog2(t.K);
   a.M = gm.M;
@@ -259,6 +261,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
   if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
+  if (want_partials) p->nparts_last = (int)nblocks;
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +
                     "_ax" + std::to_string(gm.axis) + (gm.es == 1 && gm.axis != p->N - 1 ? "t" : ""));
   return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
@@ -270,18 +273,28 @@ int transpose(fftfem_plan_t p, const T* in, T* out, int64_t R, int64_t C, hipStr
   return from_hip(launch_transpose<T>(in, out, p->size / (R * C), R, C, s));
 }
 
-// One operator pass along `axis` (see ApplyArgs in launch.h).
-int apply_pass(fftfem_plan_t p, int axis, const double* in1, const double* in2, const double* f,
-               void* o1, int o1_f64, double* o2, const double c1[4], const double c2[4],
+// A double-double array: hi plane and lo plane (lo null: a float64 array).
+struct DDp {
+  const double* h;
+  const double* l;
+};
+
+// One operator pass along `axis` (see ApplyArgs in launch.h).  out1 kind:
+// 0 float, 1 double, 2 double-double (o1h, o1l).
+int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, void* o1h, double* o1l,
+               int o1_kind, double* o2h, double* o2l, const double c1[4], const double c2[4],
                const int* flag, hipStream_t s) {
   ApplyArgs a{};
-  a.in1 = in1;
-  a.in2 = in2;
+  a.in1[0] = in1.h;
+  a.in1[1] = in1.l;
+  a.in2[0] = in2.h;
+  a.in2[1] = in2.l;
   a.f = f;
-  a.o1 = o1;
-  a.o2 = o2;
-  a.o1_f64 = o1_f64;
-  a.sub_f = f != nullptr;
+  a.o1[0] = o1h;
+  a.o1[1] = o1l;
+  a.o1_kind = o1_kind;
+  a.o2[0] = o2h;
+  a.o2[1] = o2l;
   for (int i = 0; i < 4; ++i) {
     a.c1[i] = c1[i];
     a.c2[i] = c2 ? c2[i] : 0.0;
@@ -289,59 +302,83 @@ int apply_pass(fftfem_plan_t p, int axis, const double* in1, const double* in2, 
   a.M = p->M[axis];
   a.es = p->stride[axis];
   a.nlines = p->size / a.M;
+  const int planes = (in1.l ? 2 : 1) * (in2.h ? 2 : 1);
   if (a.es > 1) {
     a.G = 32;
-    a.TL = 64;
+    a.TL = planes > 2 ? 32 : 64;
   } else {
     a.G = 4;
     a.TL = 512;
   }
-  a.Ael = p->Ael;
-  a.Cel = p->Cel;
+  const int XX = (p->n + 1) * (p->n + 1);
+  a.Ael[0] = p->Ael;
+  a.Ael[1] = p->Ael + XX;
+  a.Cel[0] = p->Cel;
+  a.Cel[1] = p->Cel + XX;
   a.flag = flag;
   int64_t W = a.TL + 2 * p->n;
-  size_t lds = (size_t)(in2 ? 2 : 1) * a.G * W * sizeof(double);
+  size_t lds = (size_t)planes * a.G * W * sizeof(double);
   int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
   Timed tm(p, s, std::string("apply_ax") + std::to_string(axis));
   return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
 }
 
-// y = A u (out_f64) or r = f - A u, for one right-hand side.
-int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_f64,
+// y = A u (out_kind 1) or r = f - A u (f non-null; out_kind 0 stores it as
+// float), for one right-hand side.  Sum factorization over the axes, last
+// axis first, with double-double partial products:
+//   1D: c0 a u + react c u
+//   2D: pass axis 1: t = c u, s = a u;  pass axis 0: c0 a t + react c t + c1 c s
+//   3D: pass axis 2: t = c u, s = a u;
+//       pass axis 1: t2 = c t, s2 = c1 a t + react c t + c2 c s;
+//       pass axis 0: c0 a t2 + c s2
+int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_kind,
                    const int* flag, hipStream_t s) {
   const double* c = p->coef;
   double react = p->desc.react;
+  double** T = p->tmp;
+  const DDp none{nullptr, nullptr};
   int rc;
   if (p->N == 1) {
     double c1[4] = {c[0], react, 0, 0};
-    return apply_pass(p, 0, u, nullptr, f, out, out_f64, nullptr, c1, nullptr, flag, s);
+    return apply_pass(p, 0, {u, nullptr}, none, f, out, nullptr, out_kind, nullptr, nullptr, c1, nullptr,
+                      flag, s);
   }
-  if (p->N == 2) {
-    double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
-    rc = apply_pass(p, 1, u, nullptr, nullptr, p->tmp[0], 1, p->tmp[1], cC, cA, flag, s);
-    if (rc) return rc;
-    double c1[4] = {c[0], react, 0, c[1]};
-    return apply_pass(p, 0, p->tmp[0], p->tmp[1], f, out, out_f64, nullptr, c1, nullptr, flag, s);
-  }
-  double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
-  rc = apply_pass(p, 2, u, nullptr, nullptr, p->tmp[0], 1, p->tmp[1], cC, cA, flag, s);
+  const double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
+  rc = apply_pass(p, p->N - 1, {u, nullptr}, none, nullptr, T[0], T[1], 2, T[2], T[3], cC, cA, flag, s);
   if (rc) return rc;
+  if (p->N == 2) {
+    double c1[4] = {c[0], react, 0, c[1]};
+    return apply_pass(p, 0, {T[0], T[1]}, {T[2], T[3]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
+                      nullptr, flag, s);
+  }
   double c4[4] = {c[1], react, 0, c[2]};
-  rc = apply_pass(p, 1, p->tmp[0], p->tmp[1], nullptr, p->tmp[2], 1, p->tmp[3], cC, c4, flag, s);
+  rc = apply_pass(p, 1, {T[0], T[1]}, {T[2], T[3]}, nullptr, T[4], T[5], 2, T[6], T[7], cC, c4, flag, s);
   if (rc) return rc;
   double c1[4] = {c[0], 0, 0, 1};
-  return apply_pass(p, 0, p->tmp[2], p->tmp[3], f, out, out_f64, nullptr, c1, nullptr, flag, s);
+  return apply_pass(p, 0, {T[4], T[5]}, {T[6], T[7]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
+                    nullptr, flag, s);
 }
 
 // Forward on axes N-1..1, MID on axis 0, inverse on axes 1..N-1.
 // work: T array used in place between passes (may equal out when T is double);
 // work2: second T array for the transposed 2D schedule.
+// mid64 (N = 1, T = float): run the single pass in float64.  Refinement
+// residuals are dominated by the high-frequency rounding noise of the float32
+// iterate (amplified by the stiffness); float32 transforms of them leak a
+// fraction ~1e-7 of that noise into the lowest modes, which the division
+// amplifies by up to cond(A).  In 1D the one float64 pass removes the leak.
+// In 2D and 3D every forward pass before the division would have to run in
+// float64 to the same end, at about the cost of a float64 solve, so those
+// keep float32 and pay one more refinement step instead.
 template <typename T>
 int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* work2, double* out,
-                    const double* upd, const int* flag, hipStream_t s, bool partials) {
+                    const double* upd, const int* flag, hipStream_t s, bool partials, bool mid64 = false) {
   int N = p->N, rc;
-  if (N == 1)
+  if (N == 1) {
+    if (mid64 && sizeof(T) == 4)
+      return line_pass<double>(p, natural_geom(p, 0, true), MID, in, in_f64, out, 1, upd, flag, s, partials);
     return line_pass<T>(p, natural_geom(p, 0, true), MID, in, in_f64, out, 1, upd, flag, s, partials);
+  }
   rc = line_pass<T>(p, natural_geom(p, N - 1, true), FWD, in, in_f64, work, 0, nullptr, flag, s, false);
   if (rc) return rc;
   for (int d = N - 2; d >= 1; --d) {
@@ -494,7 +531,7 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
   }
   if (!rc) {
     std::vector<double> A, C;
-    element_matrices(d.n, &A, &C);
+    element_matrices_dd(d.n, &A, &C);
     rc = upload<double>(p, &p->Ael, A);
     if (!rc) rc = upload<double>(p, &p->Cel, C);
   }
@@ -508,9 +545,11 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
     rc = dev_alloc(p, (void**)&p->W32, (size_t)p->size * sizeof(float));
   if (!rc && p->tr2d && d.precision != FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W32b, (size_t)p->size * sizeof(float));
+  if (!rc && d.precision == FFTFEM_FP32_REFINE && d.N == 1)
+    rc = dev_alloc(p, (void**)&p->W64r, (size_t)p->size * sizeof(double));
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
-  p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 2 : 4);
+  p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 4 : 8);
   for (int i = 0; i < p->ntmp && !rc; ++i)
     rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
   if (!rc) {
@@ -576,11 +615,12 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
     rc = transform_chain<float>(p, fr, 1, p->W32, p->W32b, ur, nullptr, nullptr, s, false);
     if (rc || p->desc.precision == FFTFEM_FP32) continue;
     for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
-      rc = operator_apply(p, ur, fr, p->W32, 0, flag, s);
-      if (!rc) rc = transform_chain<float>(p, p->W32, 0, p->W32, p->W32b, ur, ur, flag, s, true);
-      if (!rc)
-        rc = from_hip(launch_reduce(p->partials, (int)max_blocks_last_pass(p, sizeof(float)), it,
-                                    p->desc.tol, flag, st, s));
+      // residual in float64 for the 1D float64 pass, float32 otherwise
+      const bool one = p->N == 1;
+      void* r = one ? (void*)p->W64r : (void*)p->W32;
+      rc = operator_apply(p, ur, fr, r, one ? 1 : 0, flag, s);
+      if (!rc) rc = transform_chain<float>(p, r, one ? 1 : 0, p->W32, p->W32b, ur, ur, flag, s, true, one);
+      if (!rc) rc = from_hip(launch_reduce(p->partials, p->nparts_last, it, p->desc.tol, flag, st, s));
     }
   }
   return rc;

@@ -44,10 +44,13 @@ template <typename T>
 __device__ __forceinline__ T load_in(const void* p, int f64, int64_t i) {
   return f64 ? (T)((const double*)p)[i] : ((const T*)p)[i];
 }
+// kind 0: T, 1: double, 2: float
 template <typename T>
-__device__ __forceinline__ void store_out(void* p, int f64, int64_t i, T v) {
-  if (f64)
+__device__ __forceinline__ void store_out(void* p, int kind, int64_t i, T v) {
+  if (kind == 1)
     ((double*)p)[i] = (double)v;
+  else if (kind == 2)
+    ((float*)p)[i] = (float)v;
   else
     ((T*)p)[i] = v;
 }

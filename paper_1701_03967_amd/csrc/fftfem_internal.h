@@ -40,6 +40,10 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* out);
 // Reference-element matrices (n+1)^2, row-major, rounded from 113-bit values.
 void element_matrices(int n, std::vector<double>* A, std::vector<double>* C);
 
+// The same matrices as unevaluated sums hi + lo of doubles: 2 (n+1)^2 values
+// each, the (n+1)^2 hi parts followed by the (n+1)^2 lo parts.
+void element_matrices_dd(int n, std::vector<double>* A, std::vector<double>* C);
+
 inline int num_even(int n) { return n / 2; }
 inline int num_odd(int n) { return (n - 1) / 2; }
 

@@ -14,7 +14,8 @@ struct LineArgs {
   const void* in;
   void* out;
   const double* upd;      // INV with update: out = upd + result (float64)
-  int in_f64, out_f64;
+  int in_f64;
+  int out_kind;           // 0: T, 1: double, 2: float
   int K, log2K;
   int64_t M, es, nlines;
   int G, log2G;           // lines per tile (a power of two)
@@ -31,19 +32,20 @@ struct LineArgs {
   const int* flag;        // nonzero: skip (refinement converged)
 };
 
+// One operator pass along an axis (see apply_kernel).  Inputs and the
+// outputs o2 and o1 (o1_kind 2) are double-double: [0] hi, [1] lo planes.
 struct ApplyArgs {
-  const double* in1;
-  const double* in2;
-  const double* f;
-  void* o1;
-  double* o2;
-  int o1_f64;
-  int sub_f;
+  const double* in1[2];   // lo may be null: a float64 input
+  const double* in2[2];   // hi null: one input; lo null iff in1 lo is null
+  const double* f;        // non-null: o1 = f - result
+  void* o1[2];
+  double* o2[2];          // null: no second output
+  int o1_kind;            // 0 float, 1 double, 2 double-double
   double c1[4], c2[4];
   int64_t M, es, nlines;
   int G, TL;
-  const double* Ael;
-  const double* Cel;
+  const double* Ael[2];   // element matrices, hi and lo parts
+  const double* Cel[2];
   const int* flag;
 };
 

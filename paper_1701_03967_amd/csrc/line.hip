@@ -242,7 +242,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
       acc_c += (double)v * (double)v;
       acc_u += u * u;
     } else {
-      store_out<T>(a.out, a.out_f64, idx, v);
+      store_out<T>(a.out, a.out_kind, idx, v);
     }
   };
   auto bulk_store = [&]() {

@@ -1,4 +1,4 @@
-// Operator apply (float64, for y = A u and the refinement residual), the
+// Operator apply (double-double, for y = A u and the refinement residual), the
 // refinement bookkeeping kernels and the tiled transpose (gfx950).
 #include "device_common.h"
 #include "launch.h"
@@ -9,41 +9,110 @@ namespace fftfem {
 extern __shared__ double2 fftfem_ops_lds[];
 
 // ---------------------------------------------------------------------------
-// 1D operator application along one axis (float64), for y = A u and the
-// refinement residual.  For output position g of a line (Sect. 2, the
-// element-by-element assembly of A and C):
-//   node (g+1) % n == 0:  sum_t X[n][t] v[g-n+t] + sum_t X[0][t] v[g+t]
-//   bubble l = g % n + 1: sum_t X[l][t] v[g-l+t]
-// with v = 0 outside the line (Dirichlet).  Two inputs and two outputs with
-// coefficient rows let one pass produce the sum-factorized partial products:
-//   o1 = c1[0] A in1 + c1[1] C in1 + c1[2] A in2 + c1[3] C in2   (o1 = f - that, if sub_f)
-//   o2 = c2[0] A in1 + c2[1] C in1 + c2[2] A in2 + c2[3] C in2
-template <int NORD>
-__device__ __forceinline__ void stencil(const double* __restrict__ v, int i, const double* X,
-                                        double& out) {
-  constexpr int n = NORD;
-  double s = 0;
-  if ((i + 1) % n == 0) {
-#pragma unroll
-    for (int t = 0; t <= n; ++t) s += X[n * (n + 1) + t] * v[i - n + t] + X[t] * v[i + t];
-  } else {
-    int l = i % n + 1;
-#pragma unroll
-    for (int t = 0; t <= n; ++t) s += X[l * (n + 1) + t] * v[i - l + t];
-  }
-  out = s;
+// Double-double arithmetic for the operator apply.  The stiffness part of A
+// is a second-difference operator whose norm exceeds its smallest eigenvalue
+// by about (nK)^2; a residual f - A u rounded at float64 (and float64-rounded
+// element matrices, whose rows then no longer sum to zero) leaves an error of
+// that size relative to the solution, far above what refinement must reach.
+// Every product and sum of the apply is therefore carried as an unevaluated
+// sum hi + lo of two doubles (error-free transformations), with the element
+// matrices rounded from 113-bit values into hi + lo pairs.  Contraction of
+// a * b + c into fma is disabled in these helpers: the error-free sums depend
+// on each operation being rounded on its own.
+struct dd {
+  double h, l;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
 }
 
-template <int NORD>
+// s += x * v, x and v given as hi + lo pairs (vl = 0 for a float64 input)
+template <bool LO>
+__device__ __forceinline__ void dd_fma(dd& s, double xh, double xl, double vh, double vl) {
+#pragma clang fp contract(off)
+  double p = xh * vh;
+  double e = __builtin_fma(xh, vh, -p);
+  if constexpr (LO) e = __builtin_fma(xh, vl, e);
+  e = __builtin_fma(xl, vh, e);
+  double t, err;
+  two_sum(s.h, p, t, err);
+  s.h = t;
+  s.l += err + e;
+}
+
+// s += c * x for a float64 scalar c
+__device__ __forceinline__ void dd_axpy(dd& s, double c, dd x) {
+#pragma clang fp contract(off)
+  double p = c * x.h;
+  double e = __builtin_fma(c, x.h, -p);
+  e = __builtin_fma(c, x.l, e);
+  double t, err;
+  two_sum(s.h, p, t, err);
+  s.h = t;
+  s.l += err + e;
+}
+
+__device__ __forceinline__ dd dd_norm(dd s) {
+#pragma clang fp contract(off)
+  double h = s.h + s.l;
+  return {h, s.l - (h - s.h)};
+}
+
+// One row of a 1D element-assembled matrix at position g of a line
+// (Sect. 2: element-by-element assembly of A and C).  With v = 0 outside
+// the line (Dirichlet):
+//   node (g+1) % n == 0:  sum_t X[n][t] v[g-n+t] + sum_t X[0][t] v[g+t]
+//   bubble l = g % n + 1: sum_t X[l][t] v[g-l+t]
+// The first sum of a node has the form of a bubble row with l = n, so all
+// lanes of a wave run it together and only the nodes' second sum diverges.
+// X holds (n+1)^2 hi values followed by (n+1)^2 lo values.
+template <int NORD, bool LO>
+__device__ __forceinline__ dd row_apply(const double* vh, const double* vl, int g, const double* X) {
+  constexpr int n = NORD;
+  constexpr int XX = (NORD + 1) * (NORD + 1);
+  const bool node = (g + 1) % n == 0;
+  const int l = node ? n : g % n + 1;
+  dd s{0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t <= n; ++t) {
+    int j = g - l + t;
+    dd_fma<LO>(s, X[l * (n + 1) + t], X[XX + l * (n + 1) + t], vh[j], LO ? vl[j] : 0.0);
+  }
+  if (node) {
+#pragma unroll
+    for (int t = 0; t <= n; ++t)
+      dd_fma<LO>(s, X[t], X[XX + t], vh[g + t], LO ? vl[g + t] : 0.0);
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// 1D operator pass along one axis.  With a and c the stiffness and mass rows
+// above, for each position of each line:
+//   o1 = c1[0] a(in1) + c1[1] c(in1) + c1[2] a(in2) + c1[3] c(in2)
+//        (o1 = f - that, when f is given)
+//   o2 = c2[0] a(in1) + c2[1] c(in1) + c2[2] a(in2) + c2[3] c(in2)
+// Chained along the axes these give the sum-factorized tensor operator.
+// Tiles: G lines x TL positions with an n-dof halo on each side, staged in
+// LDS as separate hi and lo planes.
+template <int NORD, bool LO>
 __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
+#pragma clang fp contract(off)
   if (a.flag && *a.flag) return;
   constexpr int n = NORD;
+  constexpr int XX = (NORD + 1) * (NORD + 1);
   double* sm = reinterpret_cast<double*>(fftfem_ops_lds);
-  __shared__ double Xa[(NORD + 1) * (NORD + 1)], Xc[(NORD + 1) * (NORD + 1)];
+  __shared__ double Xa[2 * XX], Xc[2 * XX];
   const int tid = threadIdx.x;
-  for (int i = tid; i < (n + 1) * (n + 1); i += kThreads) {
-    Xa[i] = a.Ael[i];
-    Xc[i] = a.Cel[i];
+  for (int i = tid; i < XX; i += kThreads) {
+    Xa[i] = a.Ael[0][i];
+    Xa[XX + i] = a.Ael[1][i];
+    Xc[i] = a.Cel[0][i];
+    Xc[XX + i] = a.Cel[1][i];
   }
   const int G = a.G, TL = a.TL, W = TL + 2 * n;
   const int64_t nseg = (a.M + TL - 1) / TL;
@@ -51,10 +120,13 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
   const int64_t lg = tile / nseg, seg = tile - lg * nseg;
   const int64_t l0 = lg * G, s0 = seg * TL;
   const bool lines_fast = a.es > 1;
-  const bool two = a.in2 != nullptr;
-  double* v1 = sm;
-  double* v2 = sm + G * W;
-  for (int t = tid; t < G * W; t += kThreads) {
+  const bool two = a.in2[0] != nullptr;
+  const int plane = G * W;
+  double* v1h = sm;
+  double* v1l = sm + plane;
+  double* v2h = sm + (LO ? 2 : 1) * plane;
+  double* v2l = v2h + plane;
+  for (int t = tid; t < plane; t += kThreads) {
     int g, i;
     if (lines_fast) {
       g = t % G;
@@ -65,17 +137,30 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
     }
     int64_t line = l0 + g;
     int64_t pos = s0 - n + i;
-    double x1 = 0, x2 = 0;
+    double x1h = 0, x1l = 0, x2h = 0, x2l = 0;
     if (line < a.nlines && pos >= 0 && pos < a.M) {
       int64_t outer = line / a.es, inner = line - outer * a.es;
       int64_t idx = outer * a.M * a.es + inner + pos * a.es;
-      x1 = a.in1[idx];
-      if (two) x2 = a.in2[idx];
+      x1h = a.in1[0][idx];
+      if (LO) x1l = a.in1[1][idx];
+      if (two) {
+        x2h = a.in2[0][idx];
+        if (LO) x2l = a.in2[1][idx];
+      }
     }
-    v1[g * W + i] = x1;
-    if (two) v2[g * W + i] = x2;
+    const int o = g * W + i;
+    v1h[o] = x1h;
+    if (LO) v1l[o] = x1l;
+    if (two) {
+      v2h[o] = x2h;
+      if (LO) v2l[o] = x2l;
+    }
   }
   __syncthreads();
+  // which of the four row products any output needs (uniform over the grid)
+  const bool needA1 = a.c1[0] != 0 || a.c2[0] != 0, needC1 = a.c1[1] != 0 || a.c2[1] != 0;
+  const bool needA2 = two && (a.c1[2] != 0 || a.c2[2] != 0);
+  const bool needC2 = two && (a.c1[3] != 0 || a.c2[3] != 0);
   for (int t = tid; t < G * TL; t += kThreads) {
     int g, i;
     if (lines_fast) {
@@ -88,26 +173,42 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
     int64_t line = l0 + g;
     int64_t pos = s0 + i;
     if (line >= a.nlines || pos >= a.M) continue;
-    // local index within the window: pos - (s0 - n); the stencil uses the
-    // position along the line for the node/bubble pattern
-    const double* w1 = v1 + g * W + n - s0;  // w1[pos] = window value at pos
-    double A1, C1, A2 = 0, C2v = 0;
-    stencil<NORD>(w1, (int)pos, Xa, A1);
-    stencil<NORD>(w1, (int)pos, Xc, C1);
-    if (two) {
-      const double* w2 = v2 + g * W + n - s0;
-      stencil<NORD>(w2, (int)pos, Xa, A2);
-      stencil<NORD>(w2, (int)pos, Xc, C2v);
-    }
+    // window pointers shifted so that index = position along the line
+    const int sh = g * W + n - (int)s0;
+    dd A1{0, 0}, C1{0, 0}, A2{0, 0}, C2v{0, 0};
+    if (needA1) A1 = row_apply<NORD, LO>(v1h + sh, v1l + sh, (int)pos, Xa);
+    if (needC1) C1 = row_apply<NORD, LO>(v1h + sh, v1l + sh, (int)pos, Xc);
+    if (needA2) A2 = row_apply<NORD, LO>(v2h + sh, v2l + sh, (int)pos, Xa);
+    if (needC2) C2v = row_apply<NORD, LO>(v2h + sh, v2l + sh, (int)pos, Xc);
     int64_t outer = line / a.es, inner = line - outer * a.es;
     int64_t idx = outer * a.M * a.es + inner + pos * a.es;
-    double r1 = a.c1[0] * A1 + a.c1[1] * C1 + a.c1[2] * A2 + a.c1[3] * C2v;
-    if (a.sub_f) r1 = a.f[idx] - r1;
-    if (a.o1_f64)
-      ((double*)a.o1)[idx] = r1;
-    else
-      ((float*)a.o1)[idx] = (float)r1;
-    if (a.o2) a.o2[idx] = a.c2[0] * A1 + a.c2[1] * C1 + a.c2[2] * A2 + a.c2[3] * C2v;
+    dd r{0, 0};
+    dd_axpy(r, a.c1[0], A1);
+    dd_axpy(r, a.c1[1], C1);
+    dd_axpy(r, a.c1[2], A2);
+    dd_axpy(r, a.c1[3], C2v);
+    if (a.f) {
+      double hh, e;
+      two_sum(a.f[idx], -r.h, hh, e);
+      r = {hh, e - r.l};
+    }
+    r = dd_norm(r);
+    if (a.o1_kind == 0) {
+      ((float*)a.o1[0])[idx] = (float)r.h;
+    } else {
+      ((double*)a.o1[0])[idx] = r.h;
+      if (a.o1_kind == 2) ((double*)a.o1[1])[idx] = r.l;
+    }
+    if (a.o2[0]) {
+      dd q{0, 0};
+      dd_axpy(q, a.c2[0], A1);
+      dd_axpy(q, a.c2[1], C1);
+      dd_axpy(q, a.c2[2], A2);
+      dd_axpy(q, a.c2[3], C2v);
+      q = dd_norm(q);
+      a.o2[0][idx] = q.h;
+      a.o2[1][idx] = q.l;
+    }
   }
 }
 
@@ -193,10 +294,14 @@ template hipError_t launch_transpose<float>(const float*, float*, int64_t, int64
 template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, int64_t, hipStream_t);
 
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s) {
+  const bool lo = a.in1[1] != nullptr;
   switch (n) {
-#define FFTFEM_CASE(N)                                                                       \
-  case N:                                                                                    \
-    hipLaunchKernelGGL((apply_kernel<N>), dim3(nblocks), dim3(kThreads), lds, s, a);         \
+#define FFTFEM_CASE(N)                                                                         \
+  case N:                                                                                      \
+    if (lo)                                                                                    \
+      hipLaunchKernelGGL((apply_kernel<N, true>), dim3(nblocks), dim3(kThreads), lds, s, a);   \
+    else                                                                                       \
+      hipLaunchKernelGGL((apply_kernel<N, false>), dim3(nblocks), dim3(kThreads), lds, s, a);  \
     return hipGetLastError();
     FFTFEM_CASE(1)
     FFTFEM_CASE(2)

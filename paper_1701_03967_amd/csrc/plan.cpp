@@ -365,6 +365,21 @@ void element_matrices(int n, std::vector<double>* A, std::vector<double>* C) {
   }
 }
 
+void element_matrices_dd(int n, std::vector<double>* A, std::vector<double>* C) {
+  std::vector<q> Aq, Cq;
+  element_matrices_q(n, &Aq, &Cq);
+  const size_t m = Aq.size();
+  A->assign(2 * m, 0.0);
+  C->assign(2 * m, 0.0);
+  for (size_t i = 0; i < m; ++i) {
+    double ah = (double)Aq[i], ch = (double)Cq[i];
+    (*A)[i] = ah;
+    (*A)[m + i] = (double)(Aq[i] - (q)ah);
+    (*C)[i] = ch;
+    (*C)[m + i] = (double)(Cq[i] - (q)ch);
+  }
+}
+
 int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
   const int kEINVAL = -1, kESPECTRUM = -4;
   if (n < 1 || K < 2) return kEINVAL;

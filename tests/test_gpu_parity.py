@@ -210,3 +210,65 @@ def test_workload_c1():
     fh = osolve.apply_A(v, p0.n, p0.K, p0.diff, p0.react)
     u = p.solve(dev(fh)).cpu().numpy()
     assert rel(u, v) < 1e-12
+
+
+def _smooth(n, K):
+    """Product of sines on the dof points: a smooth input on which the
+    stiffness rows cancel by a factor ~(nK)^2."""
+    u = np.ones(())
+    for d, k in enumerate(K):
+        x = fem1d.dof_positions(n, k)
+        u = np.multiply.outer(u, np.sin((d + 1) * np.pi * x))
+    return u
+
+
+APPLY_EXACT = [
+    (9, (128,), (1.0,), 0.0, "smooth"),
+    (9, (8, 16), (1.0, 1.0), 0.0, "smooth"),
+    (4, (16, 32), (1.0, 0.5), 3.0, "smooth"),
+    (3, (4, 8, 8), (1.0, 2.0, 0.5), 1.0, "smooth"),
+    (5, (4, 8), (1.0, 1.0), 0.0, "normal"),
+]
+
+
+@pytest.mark.parametrize("n,K,diff,react,kind", APPLY_EXACT)
+def test_apply_A_exact(n, K, diff, react, kind):
+    """The double-double apply against exact rational arithmetic: every
+    entry within about one float64 ulp of the exact value."""
+    say("apply_A exact", n, K, diff, react, kind)
+    fm = _fftfem()
+    shape = [n * k - 1 for k in K]
+    u = _smooth(n, K) if kind == "smooth" else inputs.draw_rhs(shape, 550 + n, "normal")
+    y_ex = osolve.apply_A_exact(u, n, K, diff, react)
+    p = fm.Plan(K, n, diff, react, precision="fp64")
+    y = p.apply_A(dev(u)).cpu().numpy()
+    err = np.abs(y - y_ex)
+    bound = 2.3e-16 * np.abs(y_ex) + 1e-24 * np.abs(y_ex).max()
+    assert np.all(err <= bound), float((err / (np.abs(y_ex) + 1e-300)).max())
+
+
+REFINE_LARGE = [
+    (9, (1024,), (1.0,), 0.0, "uniform"),
+    (9, (128, 256), (1.0, 1.0), 0.0, "uniform"),
+    (4, (256, 256), (1.0, 0.25), 0.0, "normal"),
+    (9, (8, 16, 32), (1.0, 2.0, 0.5), 0.0, "normal"),
+]
+
+
+@pytest.mark.parametrize("n,K,diff,react,kind", REFINE_LARGE)
+def test_refine_large_K(n, K, diff, react, kind):
+    """float32 transforms + double-double residual reach 1e-10 where the
+    operator's condition number is large (up to ~(nK)^2 = 8e7)."""
+    say("refine large K", n, K, diff, react, kind)
+    fm = _fftfem()
+    f = inputs.draw_rhs([n * k - 1 for k in K], 600 + n, kind)
+    u_ref = osolve.solve(f, n, K, diff, react)
+    fd = dev(f)
+    p = fm.Plan(K, n, diff, react, precision="fp64")
+    e64 = rel(p.solve(fd).cpu().numpy(), u_ref)
+    p = fm.Plan(K, n, diff, react, precision="fp32_refine", max_iter=4, tol=1e-13)
+    u = p.solve(fd).cpu().numpy()
+    er = rel(u, u_ref)
+    say("  fp64", e64, "refined", er, p.stats())
+    assert e64 < 1e-11
+    assert er < 1e-10

@@ -334,3 +334,38 @@ def test_workload_shapes():
     for p in b.problems:
         assert 2 <= p.n <= 8 and all(32 <= k <= 512 for k in p.K) and 1 <= p.nrhs <= 8
         assert abs(p.react - 1000.0) < 1e-9
+
+
+def _newton_cotes(n):
+    """Closed Newton-Cotes weights on [-1, 1] from the moment equations
+    sum_j w_j xi_j^m = int xi^m, m = 0..n (exact rationals)."""
+    from fractions import Fraction
+    xi = [Fraction(-1) + Fraction(2 * j, n) for j in range(n + 1)]
+    mom = [Fraction(2, m + 1) if m % 2 == 0 else Fraction(0) for m in range(n + 1)]
+    # Gaussian elimination on the Vandermonde system
+    rows = [[x ** m for x in xi] + [mom[m]] for m in range(n + 1)]
+    for c in range(n + 1):
+        piv = next(r for r in range(c, n + 1) if rows[r][c] != 0)
+        rows[c], rows[piv] = rows[piv], rows[c]
+        for r in range(n + 1):
+            if r != c and rows[r][c] != 0:
+                f = rows[r][c] / rows[c][c]
+                rows[r] = [a - f * b for a, b in zip(rows[r], rows[c])]
+    return [rows[j][-1] / rows[j][j] for j in range(n + 1)]
+
+
+@pytest.mark.parametrize("n,K", [(2, 4), (4, 8), (8, 4)])
+def test_exact_apply_galerkin_quadratic(n, K):
+    """Exact-arithmetic operator apply: for the interpolant of p = x(1-x)
+    (exact at degree <= n), integration by parts gives
+    (A u)_i = (2/h) int phi_i (-p'') = 2 W_i, W_i the closed Newton-Cotes
+    weight of dof i (a node collects the end weights of both elements).
+    Dof positions are dyadic, so u is exact in float64."""
+    x = fem1d.dof_positions(n, K)
+    u = x * (1.0 - x)
+    y = solve.apply_A_exact(u, n, (K,), (1.0,), 0.0)
+    w = _newton_cotes(n)
+    M = n * K - 1
+    W = [w[0] + w[n] if (g + 1) % n == 0 else w[g % n + 1] for g in range(M)]
+    expect = np.array([float(2 * v) for v in W])
+    assert np.array_equal(y, expect)
