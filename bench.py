@@ -56,6 +56,65 @@ def kernel_bytes(name: str, size: int, N: int) -> float:
     return 0.0
 
 
+KERNEL_SOURCES = ("line.hip", "fft.h", "device_common.h", "launch.h", "ops.hip", "api.cpp")
+
+
+def sources_sha256() -> str:
+    """Hash of the kernel sources and their launch code: counter summaries
+    taken on other sources no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_03967_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiler_kernel_name(name: str, n: int, N: int) -> str:
+    """Symbol of the line kernel that a per-pass timing name refers to."""
+    head = name.split("_ax")[0]
+    dtype = "double" if head.endswith("64") else "float"
+    mode = 0 if head.startswith("fwd") else (1 if head.startswith("inv") else 2)
+    upd = "true" if "upd" in head else "false"
+    ax = name.rsplit("_ax", 1)[1]
+    contiguous = ax.endswith("t") or int(ax.rstrip("t")) == N - 1
+    return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}>"
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or
+    None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("sources_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("kernel:"):
+                parts = [x.strip() for x in line[len("kernel:"):].split("|")]
+                kv = dict(x.split("=", 1) for x in parts[1:])
+                rows[parts[0]] = float(kv["bytes"])
+    if sha != sources_sha256():
+        return None
+    for k, v in rows.items():
+        if kernel in k:
+            return v
+    return None
+
+
+def copy_calibration(torch, nbytes: int):
+    """One plain device-to-device copy of nbytes (the counters' scale)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True):
     plan = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=precision,
                    max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12)
@@ -137,6 +196,8 @@ def main():
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,fp32,fp32_refine")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device copy of BYTES (profiler counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs one problem on one GPU; --gpus must be 1"}))
@@ -144,6 +205,8 @@ def main():
     import torch
     from paper_1701_03967_amd import fftfem as fm
     fm.lib()
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
 
     def run(name, full):
         w = inputs.WORKLOADS[name]
@@ -187,9 +250,12 @@ def main():
         by = kernel_bytes(name, prob.size, prob.N)
         if by > 0:
             gbs = by / (avg_ms * 1e-3) / 1e9
-            roof = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                    "bytes_per_launch": by, "avg_ms": avg_ms}
+            kname = profiler_kernel_name(name, prob.n, prob.N)
+            traffic = measured_traffic(args.workload, kname)
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                    "kernel": name, "symbol": kname, "bytes_per_launch": by, "avg_ms": avg_ms,
+                    "launches_per_step": cnt / args.steps}
     line = {
         "metric": METRIC,
         "value": value,

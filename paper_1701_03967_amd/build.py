@@ -34,7 +34,12 @@ def _run(cmd):
     return time.time() - t
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=()) -> str:
+    """Compile and link the library.  `defines` (``NAME=VALUE`` strings) are
+    passed to the kernel compiles, `lib` and `build_dir` place the outputs."""
+    BUILD = build_dir
+    LIB = lib
+    dflags = [f"-D{d}" for d in defines]
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     plan_o = os.path.join(BUILD, "plan.o")
@@ -51,7 +56,7 @@ def build(verbose: bool = True) -> str:
         print(f"[build] api.cpp {dt:.1f}s", flush=True)
     for src in ("line.hip", "ops.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS,
+        dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, *dflags,
                    "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
         if verbose:

@@ -38,6 +38,13 @@ namespace fftfem {
 // Dynamic LDS of the line kernels.
 extern __shared__ double2 fftfem_lds[];
 
+#ifndef FFTFEM_MINW64
+#define FFTFEM_MINW64 2
+#endif
+#ifndef FFTFEM_MINW32
+#define FFTFEM_MINW32 4
+#endif
+
 // Threads per line-kernel workgroup: 512 for float32; 256 for float64, whose
 // register footprint allows no more than eight waves per CU anyway.  Every
 // tile has G * K <= 1024 element tasks and G * K / 2 contraction tasks.
@@ -46,6 +53,9 @@ struct LineCfg {
   static constexpr int NT = sizeof(T) == 8 ? 256 : 512;
   static constexpr int TPT = 1024 / NT;  // element tasks per thread
   static constexpr int CPT = 512 / NT;   // contraction tasks per thread
+  // minimum waves per SIMD the register allocation must allow: two 256-thread
+  // float64 tiles per CU (<= 256 VGPRs), two 512-thread float32 tiles (<= 128)
+  static constexpr int MINW = sizeof(T) == 8 ? FFTFEM_MINW64 : FFTFEM_MINW32;
 };
 
 template <typename T>
@@ -142,38 +152,160 @@ __device__ __forceinline__ void channel_vec(T nodal, const T* at_k, const T* at_
 }
 
 // Q is stored structure-of-arrays: entry (c, l) of frequency k at
-// Q[(c * n + l) * K + k], so the lanes of a wave (consecutive k) read
-// consecutive addresses.  Block k = 0 is zero-padded to n x n.
-template <typename T, int NORD>
-__device__ __forceinline__ void contract_fwd(const T* __restrict__ Q, int K, int k, const T* ch, T* w) {
-#pragma unroll
-  for (int l = 0; l < NORD; ++l) w[l] = 0;
-#pragma unroll
-  for (int c = 0; c < NORD; ++c) {
-    T q[NORD];
-#pragma unroll
-    for (int l = 0; l < NORD; ++l) q[l] = Q[(c * NORD + l) * K + k];
-#pragma unroll
-    for (int l = 0; l < NORD; ++l) w[l] += q[l] * ch[c];
-  }
+// Q[(c n + l) K + k], so the lanes of a wave (consecutive k) read one
+// contiguous segment per entry.  The table is read through a buffer
+// resource: the row offset 8 (c n + l) K is a scalar operand and the lane
+// offset 8 k the only vector one (plain pointer arithmetic here gets
+// re-associated into per-load 64-bit vector addresses, issued one at a
+// time).  Reads past the table return 0 instead of faulting.  Block k = 0 is
+// zero-padded to n x n.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+template <typename T>
+__device__ __forceinline__ rsrc_t table_rsrc(const T* p, uint32_t count) {
+  // third descriptor word for the gfx9 family: raw 32-bit element format
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, count * (uint32_t)sizeof(T),
+                                           0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldq(rsrc_t r, uint32_t lane_off, uint32_t row_off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0));
 }
 
 template <typename T, int NORD>
-__device__ __forceinline__ void contract_inv(const T* __restrict__ Q, int K, int k, const T* w, T* ch) {
+__device__ __forceinline__ uint32_t qrow(int c, int l, int K) {
+  return (uint32_t)((c * NORD + l) * K) * (uint32_t)sizeof(T);
+}
+
+template <typename T, int NORD>
+__device__ __forceinline__ void contract_fwd(rsrc_t Q, int K, int k, const T* ch, T* w) {
+  const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int l = 0; l < NORD; ++l) w[l] = 0;
+#pragma unroll
+  for (int c = 0; c < NORD; ++c)
+#pragma unroll
+    for (int l = 0; l < NORD; ++l) w[l] += ldq<T>(Q, ko, qrow<T, NORD>(c, l, K)) * ch[c];
+}
+
+template <typename T, int NORD>
+__device__ __forceinline__ void contract_inv(rsrc_t Q, int K, int k, const T* w, T* ch) {
+  const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(T);
 #pragma unroll
   for (int c = 0; c < NORD; ++c) {
-    T q[NORD];
-#pragma unroll
-    for (int l = 0; l < NORD; ++l) q[l] = Q[(c * NORD + l) * K + k];
     T acc = 0;
 #pragma unroll
-    for (int l = 0; l < NORD; ++l) acc += q[l] * w[l];
+    for (int l = 0; l < NORD; ++l) acc += ldq<T>(Q, ko, qrow<T, NORD>(c, l, K)) * w[l];
     ch[c] = acc;
   }
 }
 
+// Contractions of the fused MID pass: the forward contraction, division and
+// inverse contraction of the two frequencies k and K - k of a task run as
+// two interleaved chains.  Left alone, the scheduler would issue the n^2
+// table loads of all four contractions up front (several hundred live
+// registers: one wave per SIMD, or spills).  Here the lane offset used by
+// row c + D goes through empty asm statements that also consume that
+// chain's accumulators after row c, so each chain has D rows in flight, and
+// a contraction's first rows wait for `dep` (the previous stage's result).
+template <typename V>
+__device__ __forceinline__ uint32_t after(uint32_t o, V v) {
+  __asm__ volatile("" : "+v"(o) : "v"(v));
+  return o;
+}
+
+// The same, tied to all n accumulators (the scheduler would otherwise finish
+// only the one the asm consumes and keep the other columns' inputs live).
+template <typename T, int NORD>
+__device__ __forceinline__ uint32_t after_all(uint32_t o, const T* v) {
+#pragma unroll
+  for (int l = 0; l < NORD; ++l) __asm__ volatile("" : "+v"(o) : "v"(v[l]));
+  return o;
+}
+
+#ifndef FFTFEM_MID_ROWS
+#define FFTFEM_MID_ROWS 2
+#endif
+
+template <typename T, int NORD>
+__device__ __forceinline__ void contract_fwd2(rsrc_t Q, int K, int ka, int kb, const T* cha,
+                                              const T* chb, T* wa, T* wb, T dep) {
+  constexpr int D = FFTFEM_MID_ROWS < NORD ? FFTFEM_MID_ROWS : NORD;
+  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
+  T qa[NORD][NORD], qb[NORD][NORD];
+  {
+    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int l = 0; l < NORD; ++l) {
+        qa[c][l] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
+        qb[c][l] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
+      }
+  }
+#pragma unroll
+  for (int l = 0; l < NORD; ++l) wa[l] = wb[l] = 0;
+#pragma unroll
+  for (int c = 0; c < NORD; ++c) {
+#pragma unroll
+    for (int l = 0; l < NORD; ++l) {
+      wa[l] += qa[c][l] * cha[c];
+      wb[l] += qb[c][l] * chb[c];
+    }
+    if (c + D < NORD) {
+      const uint32_t pa = after_all<T, NORD>(oa, wa), pb = after_all<T, NORD>(ob, wb);
+#pragma unroll
+      for (int l = 0; l < NORD; ++l) {
+        qa[c + D][l] = ldq<T>(Q, pa, qrow<T, NORD>(c + D, l, K));
+        qb[c + D][l] = ldq<T>(Q, pb, qrow<T, NORD>(c + D, l, K));
+      }
+    }
+  }
+}
+
+template <typename T, int NORD>
+__device__ __forceinline__ void contract_inv2(rsrc_t Q, int K, int ka, int kb, const T* wa,
+                                              const T* wb, T* cha, T* chb, T dep) {
+  constexpr int D = FFTFEM_MID_ROWS < NORD ? FFTFEM_MID_ROWS : NORD;
+  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
+  T qa[NORD][NORD], qb[NORD][NORD];
+  {
+    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int l = 0; l < NORD; ++l) {
+        qa[c][l] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
+        qb[c][l] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NORD; ++c) {
+    T acca = 0, accb = 0;
+#pragma unroll
+    for (int l = 0; l < NORD; ++l) {
+      acca += qa[c][l] * wa[l];
+      accb += qb[c][l] * wb[l];
+    }
+    cha[c] = acca;
+    chb[c] = accb;
+    if (c + D < NORD) {
+      const uint32_t pa = after(oa, acca), pb = after(ob, accb);
+#pragma unroll
+      for (int l = 0; l < NORD; ++l) {
+        qa[c + D][l] = ldq<T>(Q, pa, qrow<T, NORD>(c + D, l, K));
+        qb[c + D][l] = ldq<T>(Q, pb, qrow<T, NORD>(c + D, l, K));
+      }
+    }
+  }
+}
+
 template <typename T, int NORD, int MODE, bool UPD, bool LF>
-__global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
+__global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
   constexpr int kNT = LineCfg<T>::NT, kMaxTPT = LineCfg<T>::TPT, kMaxCPT = LineCfg<T>::CPT;
   if (a.flag && *a.flag) return;
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NB = 1 + P;
@@ -186,6 +318,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
   const int ls = K + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
   const int LS = NB * ls * 2;  // T slots per line
   const int64_t l0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) << lg;
+  const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)(K * n * n));
   const C2<T>* twf = reinterpret_cast<const C2<T>*>(a.twf);
   const C2<T>* twm = reinterpret_cast<const C2<T>*>(a.twm);
   const C2<T>* twd = reinterpret_cast<const C2<T>*>(a.twd);
@@ -266,14 +399,6 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
     }
   };
 
-  // per-line denominator base react + sum of the other axes' terms (MID)
-  __shared__ T bden[64];
-  if constexpr (MODE == MID) {
-    if (tid < G) {
-      int64_t line = l0 + tid;
-      bden[tid] = line < a.nlines ? other_den(a, line_base(a, line)) : (T)1;
-    }
-  }
   const int ntask = G << lk;         // element tasks (g, j')
   const int lkh = lk - 1;
   const int nctask = G << lkh;       // contraction tasks (g, kappa), kappa < K/2
@@ -331,109 +456,98 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
   }
 
   // ---------------- contraction per frequency pair -------------------------
-  // held across a barrier: spectral results (FWD), channel spectra (INV), or
-  // the nodal inverse inputs (MID)
-  T hw[kMaxCPT][2][NORD];
+  if constexpr (MODE == MID) {
+    // The nodal forward values of this thread's tasks are read first: the
+    // nodal inverse inputs of a task land in slots that other tasks read.
+    // After the barrier every task runs start to finish on its own (bubble
+    // slots are pair-local), so no per-task state outlives its iteration and
+    // the loop is not unrolled: the register footprint is that of one task.
+    T nf[kMaxCPT][2];
 #pragma unroll
-  for (int s = 0; s < kMaxCPT; ++s) {
-    int t = tid + s * kNT;
-    if (t >= nctask) continue;
-    int g = t >> lkh, kap = t & ((1 << lkh) - 1);
-    int kb = kap == 0 ? 0 : K - kap;
-    C2<T>* B = buf + g * NB * ls;
-    const T* rs = raw + g * LS;
-    T bd = (T)1;
-    if constexpr (MODE == MID) bd = bden[g];
-    T ca[NC], cb[NC];
-    if constexpr (MODE != INV) {
+    for (int s = 0; s < kMaxCPT; ++s) {
+      int t = tid + s * kNT;
+      nf[s][0] = nf[s][1] = (T)0;
+      if (t < nctask) {
+        int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+        const C2<T>* B = buf + g * NB * ls;
+        if (kap == 0) {
+          nf[s][1] = nodal_post<T>(B, K, K >> 1, twd, false);
+        } else {
+          nf[s][0] = nodal_post<T>(B, K, kap, twd, false);
+          nf[s][1] = nodal_post<T>(B, K, K - kap, twd, false);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < kMaxCPT; ++s) {
+      int t = tid + s * kNT;
+      if (t >= nctask) break;
+      T nfa = nf[0][0], nfb = nf[0][1];
+#pragma unroll
+      for (int u = 1; u < kMaxCPT; ++u)
+        if (s == u) {
+          nfa = nf[u][0];
+          nfb = nf[u][1];
+        }
+      int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+      int kb = kap == 0 ? 0 : K - kap;
+      C2<T>* B = buf + g * NB * ls;
+      // per-line denominator base: react + the other axes' terms
+      T bd = (T)1;
+      {
+        const int64_t line = l0 + g;
+        if (line < a.nlines) bd = other_den(a, line_base(a, line));
+      }
+      T ca[NC], cb[NC];
       if constexpr (NORD > 1) {
         if (kap != 0) bubble_post<T, NORD>(B, ls, kap, kb, twm, ca, cb);
       }
-    }
+      // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap (K/2 when kap = 0)
+      const int ka = kap, kbq = kap == 0 ? (K >> 1) : K - kap;
+      T cha[NORD], chb[NORD];
+      if (kap == 0) {
+        if constexpr (NORD > 1) {
+          bubble_post<T, NORD>(B, ls, 0, 0, twm, ca, cb);
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-      // fi = 0: k = kap (0 -> bubble block); fi = 1: k = K - kap (K/2 when kap = 0)
-      int k = fi == 0 ? kap : (kap == 0 ? (K >> 1) : K - kap);
-      if (fi == 1 && kap == 0 && K == 1) continue;
-      int r = k == 0 ? n - 1 : n;
-      int off = k == 0 ? 0 : n - 1 + (k - 1) * n;
-      T ch[NORD], w[NORD];
-      if constexpr (MODE != INV) {
-        if (kap == 0) {
-          // k = 0 (spectra at index 0) or k = K/2 (spectra at index K/2)
-          if constexpr (NORD > 1) bubble_post<T, NORD>(B, ls, k, k, twm, ca, cb);
+          for (int b = 0; b < NORD - 1; ++b) cha[b] = ca[b];
+          bubble_post<T, NORD>(B, ls, kbq, kbq, twm, ca, cb);
         }
-        if (k == 0) {
-#pragma unroll
-          for (int b = 0; b < NORD - 1; ++b) ch[b] = ca[b];
-          ch[NORD - 1] = 0;
-        } else if (kap == 0) {  // k = K/2
-          channel_vec<T, NORD>(nodal_post<T>(B, K, k, twd, false), ca, ca, ch);
-        } else if (fi == 0) {
-          channel_vec<T, NORD>(nodal_post<T>(B, K, k, twd, false), ca, cb, ch);
-        } else {
-          channel_vec<T, NORD>(nodal_post<T>(B, K, k, twd, false), cb, ca, ch);
-        }
-        if constexpr (MODE == MID && sizeof(T) == 4) {
-          // one load of Q_k for the forward contraction, the division and the inverse
-          T q[NORD][NORD];
-#pragma unroll
-          for (int c = 0; c < NORD; ++c)
-#pragma unroll
-            for (int l = 0; l < NORD; ++l) q[c][l] = a.Q[(c * NORD + l) * K + k];
-#pragma unroll
-          for (int l = 0; l < NORD; ++l) {
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < NORD; ++c) acc += q[c][l] * ch[c];
-            w[l] = l < r ? acc / (bd + a.mu_self[off + l]) : (T)0;
-          }
-#pragma unroll
-          for (int c = 0; c < NORD; ++c) {
-            T acc = 0;
-#pragma unroll
-            for (int l = 0; l < NORD; ++l) acc += q[c][l] * w[l];
-            hw[s][fi][c] = acc;
-          }
-          continue;
-        }
-        contract_fwd<T, NORD>(a.Q, K, k, ch, w);
-        if constexpr (MODE == MID) {
-#pragma unroll
-          for (int l = 0; l < NORD; ++l) w[l] = l < r ? w[l] / (bd + a.mu_self[off + l]) : (T)0;
-        }
+        cha[NORD - 1] = 0;
+        channel_vec<T, NORD>(nfb, ca, ca, chb);
       } else {
-#pragma unroll
-        for (int l = 0; l < NORD; ++l) w[l] = l < r ? rs[off + l] : (T)0;
+        channel_vec<T, NORD>(nfa, ca, cb, cha);
+        channel_vec<T, NORD>(nfb, cb, ca, chb);
       }
-      if constexpr (MODE == FWD) {
+      T wa[NORD], wb[NORD];
+      contract_fwd2<T, NORD>(qtab, K, ka, kbq, cha, chb, wa, wb, cha[0]);
+      {
+        const int ra = ka == 0 ? n - 1 : n;
+        const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
+        const int offb = n - 1 + (kbq - 1) * n;
 #pragma unroll
-        for (int l = 0; l < NORD; ++l) hw[s][fi][l] = w[l];
-        continue;
+        for (int l = 0; l < NORD; ++l) {
+          wa[l] = l < ra ? wa[l] / (bd + a.mu_self[offa + l]) : (T)0;
+          wb[l] = wb[l] / (bd + a.mu_self[offb + l]);
+        }
       }
-      contract_inv<T, NORD>(a.Q, K, k, w, ch);
-#pragma unroll
-      for (int c = 0; c < NORD; ++c) hw[s][fi][c] = ch[c];
-    }
-    if constexpr (MODE == MID) {
-      // bubble pre-twiddle now (pair-local); nodal after the barrier
+      T res[2][NORD];
+      contract_inv2<T, NORD>(qtab, K, ka, kbq, wa, wb, res[0], res[1], wa[0] + wb[0]);
+      // inverse inputs: bubble pre-twiddles (pair-local slots), nodal values
       if constexpr (NORD > 1) {
         T ya[NC], yb[NC];
         if (kap == 0) {
 #pragma unroll
-          for (int b = 0; b < NORD - 1; ++b) {
-            ya[b] = hw[s][0][b];  // index 0 of every channel (k = 0 block)
-          }
+          for (int b = 0; b < NORD - 1; ++b) ya[b] = res[0][b];  // index 0 of every channel (k = 0 block)
 #pragma unroll
-          for (int m = 1; m <= ne; ++m) yb[m - 1] = hw[s][1][m];
+          for (int m = 1; m <= ne; ++m) yb[m - 1] = res[1][m];
 #pragma unroll
-          for (int m = 1; m <= no; ++m) yb[ne + m - 1] = hw[s][1][ne + m];
+          for (int m = 1; m <= no; ++m) yb[ne + m - 1] = res[1][ne + m];
 #pragma unroll
           for (int p = 1; p <= P; ++p) {
             int b0 = 2 * (p - 1), b1 = b0 + 1;
             bool has1 = b1 < NORD - 1;
-            C2<T> v0 = {ya[b0], has1 ? ya[b1] : (T)0};
-            B[p * ls] = v0;
+            B[p * ls] = {ya[b0], has1 ? ya[b1] : (T)0};
             int h = K >> 1;
             C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
             C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
@@ -444,13 +558,13 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
           // of frequency k sit at K - k, odd channels at k
 #pragma unroll
           for (int m = 1; m <= ne; ++m) {
-            ya[m - 1] = hw[s][1][m];
-            yb[m - 1] = hw[s][0][m];
+            ya[m - 1] = res[1][m];
+            yb[m - 1] = res[0][m];
           }
 #pragma unroll
           for (int m = 1; m <= no; ++m) {
-            ya[ne + m - 1] = hw[s][0][ne + m];
-            yb[ne + m - 1] = hw[s][1][ne + m];
+            ya[ne + m - 1] = res[0][ne + m];
+            yb[ne + m - 1] = res[1][ne + m];
           }
 #pragma unroll
           for (int p = 1; p <= P; ++p) {
@@ -465,6 +579,59 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
           }
         }
       }
+      if (kap == 0) {
+        write_nodal_zeros(B, K);
+        write_nodal_inv(B, K, K >> 1, res[1][0]);
+      } else {
+        write_nodal_inv(B, K, kap, res[0][0]);
+        write_nodal_inv(B, K, K - kap, res[1][0]);
+      }
+    }
+    __syncthreads();
+    fft_all<T, true, kNT>(buf, G * NB, lk, twf, ls);
+  } else {
+  // held across a barrier: spectral results (FWD) or channel spectra (INV)
+  T hw[kMaxCPT][2][NORD];
+#pragma unroll
+  for (int s = 0; s < kMaxCPT; ++s) {
+    int t = tid + s * kNT;
+    if (t >= nctask) continue;
+    int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+    // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap (K/2 when kap = 0)
+    const int ka = kap, kbq = kap == 0 ? (K >> 1) : K - kap;
+    const int ra = ka == 0 ? n - 1 : n;
+    const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
+    const int offb = n - 1 + (kbq - 1) * n;
+    if constexpr (MODE == FWD) {
+      const C2<T>* B = buf + g * NB * ls;
+      T ca[NC], cb[NC], cha[NORD], chb[NORD];
+      if (kap == 0) {
+        if constexpr (NORD > 1) {
+          bubble_post<T, NORD>(B, ls, 0, 0, twm, ca, cb);
+#pragma unroll
+          for (int b = 0; b < NORD - 1; ++b) cha[b] = ca[b];
+          bubble_post<T, NORD>(B, ls, kbq, kbq, twm, ca, cb);
+        }
+        cha[NORD - 1] = 0;
+        channel_vec<T, NORD>(nodal_post<T>(B, K, kbq, twd, false), ca, ca, chb);
+      } else {
+        if constexpr (NORD > 1) bubble_post<T, NORD>(B, ls, kap, K - kap, twm, ca, cb);
+        channel_vec<T, NORD>(nodal_post<T>(B, K, ka, twd, false), ca, cb, cha);
+        channel_vec<T, NORD>(nodal_post<T>(B, K, kbq, twd, false), cb, ca, chb);
+      }
+      contract_fwd2<T, NORD>(qtab, K, ka, kbq, cha, chb, hw[s][0], hw[s][1], cha[0]);
+#pragma unroll
+      for (int l = 0; l < NORD; ++l)
+        if (l >= ra) hw[s][0][l] = 0;
+    } else {
+      const T* rs = raw + g * LS;
+      T wa[NORD], wb[NORD];
+#pragma unroll
+      for (int l = 0; l < NORD; ++l) {
+        wa[l] = l < ra ? rs[offa + l] : (T)0;
+        wb[l] = rs[offb + l];
+      }
+      contract_inv2<T, NORD>(qtab, K, ka, kbq, wa, wb, hw[s][0], hw[s][1], wa[0] + wb[0]);
     }
   }
   __syncthreads();
@@ -553,6 +720,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT) void line_kernel(LineArgs<T> a) {
     }
     __syncthreads();
     fft_all<T, true, kNT>(buf, G * NB, lk, twf, ls);
+  }
   }
 
   // ---------------- scatter: channels -> bubble vectors and nodes ----------

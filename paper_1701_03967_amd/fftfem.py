@@ -68,10 +68,13 @@ def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+        # FFTFEM_LIBRARY selects another build of the same library (e.g. one
+        # compiled with different kernel parameters)
+        path = os.environ.get("FFTFEM_LIBRARY", LIB_PATH)
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
                                "`python -m paper_1701_03967_amd.build`")
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
         L.fftfem_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.c_int, dp, ctypes.c_double]
         L.fftfem_plan_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Desc)]
