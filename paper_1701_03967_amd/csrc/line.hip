@@ -304,6 +304,60 @@ __device__ __forceinline__ void contract_inv2(rsrc_t Q, int K, int ka, int kb, c
   }
 }
 
+// Forward contraction, division and inverse contraction of the MID pass in
+// one sweep over the modes l: with q_l column l of Q_k,
+//   out = sum_l q_l (q_l . ch) / (bd + mu_l),
+// so each column is loaded once and used twice (half the table traffic of a
+// forward and a separate inverse contraction).  Two frequencies (chains a
+// and b) interleave.  Column l + 2 is loaded once column l's rank-1 update
+// is done (empty asm statements on the lane offset consume all outputs), so
+// at most three columns per chain are live and one is always in flight.
+// ra: number of modes of chain a (n - 1 for the bubble block k = 0, whose
+// column n - 1 is zero padding).
+template <typename T, int NORD>
+__device__ __forceinline__ void mid_apply2(rsrc_t Q, int K, int ka, int kb, const T* cha, const T* chb,
+                                           T* outa, T* outb, T bd, const T* __restrict__ mua,
+                                           const T* __restrict__ mub, int ra, T dep) {
+  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
+  T qa[NORD][NORD], qb[NORD][NORD];  // [column][row]; only three columns live at a time
+  {
+    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
+#pragma unroll
+    for (int l = 0; l < 2 && l < NORD; ++l)
+#pragma unroll
+      for (int c = 0; c < NORD; ++c) {
+        qa[l][c] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
+        qb[l][c] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NORD; ++c) outa[c] = outb[c] = 0;
+#pragma unroll
+  for (int l = 0; l < NORD; ++l) {
+    T sa = 0, sb = 0;
+#pragma unroll
+    for (int c = 0; c < NORD; ++c) {
+      sa += qa[l][c] * cha[c];
+      sb += qb[l][c] * chb[c];
+    }
+    const T ta = l < ra ? sa / (bd + mua[l]) : (T)0;
+    const T tb = sb / (bd + mub[l]);
+#pragma unroll
+    for (int c = 0; c < NORD; ++c) {
+      outa[c] += qa[l][c] * ta;
+      outb[c] += qb[l][c] * tb;
+    }
+    if (l + 2 < NORD) {
+      const uint32_t pa = after_all<T, NORD>(oa, outa), pb = after_all<T, NORD>(ob, outb);
+#pragma unroll
+      for (int c = 0; c < NORD; ++c) {
+        qa[l + 2][c] = ldq<T>(Q, pa, qrow<T, NORD>(c, l + 2, K));
+        qb[l + 2][c] = ldq<T>(Q, pb, qrow<T, NORD>(c, l + 2, K));
+      }
+    }
+  }
+}
+
 template <typename T, int NORD, int MODE, bool UPD, bool LF>
 __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
   constexpr int kNT = LineCfg<T>::NT, kMaxTPT = LineCfg<T>::TPT, kMaxCPT = LineCfg<T>::CPT;
@@ -519,20 +573,14 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
         channel_vec<T, NORD>(nfa, ca, cb, cha);
         channel_vec<T, NORD>(nfb, cb, ca, chb);
       }
-      T wa[NORD], wb[NORD];
-      contract_fwd2<T, NORD>(qtab, K, ka, kbq, cha, chb, wa, wb, cha[0]);
+      T res[2][NORD];
       {
         const int ra = ka == 0 ? n - 1 : n;
         const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
         const int offb = n - 1 + (kbq - 1) * n;
-#pragma unroll
-        for (int l = 0; l < NORD; ++l) {
-          wa[l] = l < ra ? wa[l] / (bd + a.mu_self[offa + l]) : (T)0;
-          wb[l] = wb[l] / (bd + a.mu_self[offb + l]);
-        }
+        mid_apply2<T, NORD>(qtab, K, ka, kbq, cha, chb, res[0], res[1], bd, a.mu_self + offa,
+                            a.mu_self + offb, ra, cha[0]);
       }
-      T res[2][NORD];
-      contract_inv2<T, NORD>(qtab, K, ka, kbq, wa, wb, res[0], res[1], wa[0] + wb[0]);
       // inverse inputs: bubble pre-twiddles (pair-local slots), nodal values
       if constexpr (NORD > 1) {
         T ya[NC], yb[NC];
