@@ -54,13 +54,33 @@ __device__ __forceinline__ void store_out(void* p, int kind, int64_t i, T v) {
   else
     ((T*)p)[i] = v;
 }
+// Complex FFT buffers in LDS are addressed through an XOR swizzle of the
+// slot index inside aligned 256-byte blocks: slot i lives at
+// i ^ ((i / B) mod B), B = 256 / sizeof(C2<T>).  Lanes that access slots B
+// apart (the strided writes of the first Stockham stages) then hit
+// different banks, while runs of consecutive slots stay conflict-free; the
+// map is a permutation of each block, so it needs no extra space.  Every
+// access to an FFT buffer goes through slot()/set_comp()/get_comp().
+template <typename T>
+__device__ __forceinline__ int swz(int i) {
+  constexpr int LB = sizeof(T) == 8 ? 4 : 5;
+  return i ^ ((i >> LB) & ((1 << LB) - 1));
+}
+template <typename T>
+__device__ __forceinline__ C2<T>& slot(C2<T>* b, int i) {
+  return b[swz<T>(i)];
+}
+template <typename T>
+__device__ __forceinline__ const C2<T>& slot(const C2<T>* b, int i) {
+  return b[swz<T>(i)];
+}
 template <typename T>
 __device__ __forceinline__ void set_comp(C2<T>* b, int idx, int comp, T v) {
-  reinterpret_cast<T*>(b + idx)[comp] = v;
+  reinterpret_cast<T*>(b + swz<T>(idx))[comp] = v;
 }
 template <typename T>
 __device__ __forceinline__ T get_comp(const C2<T>* b, int idx, int comp) {
-  return reinterpret_cast<const T*>(b + idx)[comp];
+  return reinterpret_cast<const T*>(b + swz<T>(idx))[comp];
 }
 
 }  // namespace fftfem

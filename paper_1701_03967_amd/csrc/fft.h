@@ -3,6 +3,9 @@
 // Chunks of the butterfly range (NT * 16/R butterflies) always cover whole
 // buffers when K <= NT * 16.
 //
+// Buffer slots are addressed through slot() (an XOR swizzle that spreads
+// the strided writes of the early stages over the LDS banks).
+//
 // Stage with radix R after Ns points have been combined: butterfly j
 // (0 <= j < K/R) reads x[j + r K/R], r < R, multiplies input r by
 // exp(-+2 pi i r (j mod Ns) / (Ns R)), takes an R-point DFT and writes output
@@ -137,17 +140,17 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, int nfft, int lk, int Ns, 
   const int lts = lk - lns - LR;  // log2 of the twiddle stride K/(Ns R)
   for (int base = 0; base < total; base += NT * MAXB) {
     C2<T> v[MAXB][R];
-    int dst[MAXB];
+    int dst[MAXB], fb[MAXB];
 #pragma unroll
     for (int t = 0; t < MAXB; ++t) {
       int b = base + t * NT + tid;
       dst[t] = -1;
       if (b < total) {
         int f = b >> lkr, j = b & (KR - 1);
-        C2<T>* x = buf + f * ls;
+        const C2<T>* x = buf + f * ls;
         int k = j & (Ns - 1);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[t][r] = x[j + r * KR];
+        for (int r = 0; r < R; ++r) v[t][r] = slot(x, j + r * KR);
         if (Ns > 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
@@ -156,7 +159,8 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, int nfft, int lk, int Ns, 
           }
         }
         dft_small<T, R, INV>(v[t]);
-        dst[t] = f * ls + ((j - k) << LR) + k;
+        fb[t] = f * ls;
+        dst[t] = ((j - k) << LR) + k;
       }
     }
     __syncthreads();
@@ -164,7 +168,7 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, int nfft, int lk, int Ns, 
     for (int t = 0; t < MAXB; ++t)
       if (dst[t] >= 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[dst[t] + r * Ns] = v[t][r];
+        for (int r = 0; r < R; ++r) slot(buf + fb[t], dst[t] + r * Ns) = v[t][r];
       }
     __syncthreads();
   }

@@ -48,9 +48,13 @@ extern __shared__ double2 fftfem_lds[];
 // Threads per line-kernel workgroup: 512 for float32; 256 for float64, whose
 // register footprint allows no more than eight waves per CU anyway.  Every
 // tile has G * K <= 1024 element tasks and G * K / 2 contraction tasks.
+#ifndef FFTFEM_NT64
+#define FFTFEM_NT64 256
+#endif
+
 template <typename T>
 struct LineCfg {
-  static constexpr int NT = sizeof(T) == 8 ? 256 : 512;
+  static constexpr int NT = sizeof(T) == 8 ? FFTFEM_NT64 : 512;
   static constexpr int TPT = 1024 / NT;  // element tasks per thread
   static constexpr int CPT = 512 / NT;   // contraction tasks per thread
   // minimum waves per SIMD the register allocation must allow: two 256-thread
@@ -83,7 +87,7 @@ __device__ __forceinline__ void bubble_post(const C2<T>* B, int ls, int ia, int 
   constexpr int P = NORD / 2;
 #pragma unroll
   for (int p = 1; p <= P; ++p) {
-    C2<T> Va = B[p * ls + ia], Vb = B[p * ls + ib];
+    C2<T> Va = slot(B + p * ls, ia), Vb = slot(B + p * ls, ib);
     C2<T> sm = {Va.x + Vb.x, Va.y - Vb.y};  // Va + conj(Vb)
     C2<T> df = {Va.x - Vb.x, Va.y + Vb.y};  // Va - conj(Vb)
     C2<T> wa = twm[ia], wb = twm[ib];
@@ -103,7 +107,7 @@ __device__ __forceinline__ void bubble_post(const C2<T>* B, int ls, int ia, int 
 template <typename T>
 __device__ __forceinline__ T nodal_post(const C2<T>* Z, int K, int k, const C2<T>* twd,
                                         bool conj_in) {
-  C2<T> zk = Z[k], zm = Z[K - k];
+  C2<T> zk = slot(Z, k), zm = slot(Z, K - k);
   if (conj_in) {
     zk.y = -zk.y;
     zm.y = -zm.y;
@@ -595,11 +599,11 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
           for (int p = 1; p <= P; ++p) {
             int b0 = 2 * (p - 1), b1 = b0 + 1;
             bool has1 = b1 < NORD - 1;
-            B[p * ls] = {ya[b0], has1 ? ya[b1] : (T)0};
+            slot(B + p * ls, 0) = {ya[b0], has1 ? ya[b1] : (T)0};
             int h = K >> 1;
             C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
             C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
-            B[p * ls + h] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
           }
         } else {
           // channel spectra at FFT index kap (ya) and kb (yb): even channels
@@ -620,10 +624,10 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
             bool has1 = b1 < NORD - 1;
             C2<T> va = herm<T>(ya[b0], yb[b0], kap, twm);
             C2<T> vb = has1 ? herm<T>(ya[b1], yb[b1], kap, twm) : C2<T>{0, 0};
-            B[p * ls + kap] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, kap) = {va.x - vb.y, va.y + vb.x};
             va = herm<T>(yb[b0], ya[b0], kb, twm);
             vb = has1 ? herm<T>(yb[b1], ya[b1], kb, twm) : C2<T>{0, 0};
-            B[p * ls + kb] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, kb) = {va.x - vb.y, va.y + vb.x};
           }
         }
       }
@@ -735,11 +739,11 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
           for (int p = 1; p <= P; ++p) {
             int b0 = 2 * (p - 1), b1 = b0 + 1;
             bool has1 = b1 < NORD - 1;
-            B[p * ls] = {ya[b0], has1 ? ya[b1] : (T)0};
+            slot(B + p * ls, 0) = {ya[b0], has1 ? ya[b1] : (T)0};
             int h = K >> 1;
             C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
             C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
-            B[p * ls + h] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
           }
         } else {
 #pragma unroll
@@ -758,10 +762,10 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
             bool has1 = b1 < NORD - 1;
             C2<T> va = herm<T>(ya[b0], yb[b0], kap, twm);
             C2<T> vb = has1 ? herm<T>(ya[b1], yb[b1], kap, twm) : C2<T>{0, 0};
-            B[p * ls + kap] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, kap) = {va.x - vb.y, va.y + vb.x};
             va = herm<T>(yb[b0], ya[b0], kb, twm);
             vb = has1 ? herm<T>(yb[b1], ya[b1], kb, twm) : C2<T>{0, 0};
-            B[p * ls + kb] = {va.x - vb.y, va.y + vb.x};
+            slot(B + p * ls, kb) = {va.x - vb.y, va.y + vb.x};
           }
         }
       }
