@@ -12,6 +12,7 @@ import os
 import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -54,13 +55,24 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
     objs.append(api_o)
     if verbose:
         print(f"[build] api.cpp {dt:.1f}s", flush=True)
-    for src in ("line.hip", "ops.hip"):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    # kernels: line.hip twice (element counts that are powers of two, and
+    # all others), ops.hip once; compiled in parallel
+    units = [("line.hip", "line_p2.o", ["-DFFTFEM_LINE_POW2=1"]),
+             ("line.hip", "line_any.o", ["-DFFTFEM_LINE_POW2=0"]),
+             ("ops.hip", "ops.o", [])]
+
+    def compile_unit(u):
+        src, o, extra = u
+        obj = os.path.join(BUILD, o)
         dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, *dflags,
-                   "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-        if verbose:
-            print(f"[build] {src} {dt:.1f}s", flush=True)
+                   *extra, "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
+        return obj, f"{src} -> {o}", dt
+
+    with ThreadPoolExecutor(max_workers=len(units)) as ex:
+        for obj, what, dt in ex.map(compile_unit, units):
+            objs.append(obj)
+            if verbose:
+                print(f"[build] {what} {dt:.1f}s", flush=True)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -20,9 +20,12 @@ using namespace fftfem;
 
 namespace {
 
+// Per-axis device tables: Q, twf, twm, twd, mu, and for K not a power of
+// two the Bluestein chirp, bhat and twl (null otherwise).
+constexpr int kNumTables = 8;
 struct DevTables {
-  double* d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // Q, twf, twm, twd, mu
-  float* f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* d[kNumTables] = {};
+  float* f[kNumTables] = {};
 };
 
 }  // namespace
@@ -164,13 +167,21 @@ int validate(const fftfem_desc* d) {
   return FFTFEM_OK;
 }
 
+// FFT buffer length of an axis: K, or the Bluestein length L.
+int64_t fft_len(int64_t K) {
+  if ((K & (K - 1)) == 0) return K;
+  int64_t L = 1;
+  while (L < 2 * K - 1) L *= 2;
+  return L;
+}
+
+size_t line_lds(const fftfem_plan_s* p, int64_t K, size_t elt, bool pad = true) {
+  return (size_t)(1 + p->n / 2) * (fft_len(K) + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
+}
+
 // Lines per workgroup for a line pass: a power of two with G * K <= 1024
 // (per-thread task registers), G lines of LDS within the budget (64 KB, or
 // one line when a line alone is larger), at most 64 and at most nlines.
-size_t line_lds(const fftfem_plan_s* p, int64_t K, size_t elt, bool pad = true) {
-  return (size_t)(1 + p->n / 2) * (K + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
-}
-
 int choose_G(const fftfem_plan_s* p, int64_t K, size_t elt, int64_t nlines) {
   size_t per = line_lds(p, K, elt);
   size_t budget = std::max<size_t>(line_lds(p, K, elt, false), 65536);
@@ -248,6 +259,11 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.twm = tab<T>(p, gm.axis, 2);
   a.twd = tab<T>(p, gm.axis, 3);
   a.mu_self = tab<T>(p, gm.axis, 4);
+  a.L = (int)t.L;
+  a.log2L = t.L ? ilog2(t.L) : 0;
+  a.chirp = tab<T>(p, gm.axis, 5);
+  a.bhat = tab<T>(p, gm.axis, 6);
+  a.twl = tab<T>(p, gm.axis, 7);
   a.react = (T)p->desc.react;
   a.nother = gm.nother;
   for (int e = 0; e < gm.nother; ++e) {
@@ -458,7 +474,7 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
     if (d.X[i] == 0) d.X[i] = 1.0;
   if (d.n > kMaxLineOrder) return FFTFEM_ENOTIMPL;
   for (int i = 0; i < d.N; ++i)
-    if (!is_pow2(d.K[i]) || d.K[i] > 2048) return FFTFEM_ENOTIMPL;
+    if (d.K[i] > (is_pow2(d.K[i]) ? 2048 : kLineTasks)) return FFTFEM_ENOTIMPL;
   fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
   if (!p) return FFTFEM_ENOMEM;
   p->desc = d;
@@ -523,8 +539,9 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
       for (int c = 0; c < d.n; ++c)
         for (int l = 0; l < d.n; ++l)
           qs[(size_t)(c * d.n + l) * t.K + k] = t.Q[(size_t)k * d.n * d.n + c * d.n + l];
-    const std::vector<double>* src[5] = {&qs, &t.twf, &t.twm, &t.twd, &mu};
-    for (int w = 0; w < 5 && !rc; ++w) {
+    const std::vector<double>* src[kNumTables] = {&qs, &t.twf, &t.twm, &t.twd, &mu, &t.chirp, &t.bhat, &t.twl};
+    for (int w = 0; w < kNumTables && !rc; ++w) {
+      if (src[w]->empty()) continue;
       rc = upload<double>(p, &p->dev[i].d[w], *src[w]);
       if (!rc) rc = upload<float>(p, &p->dev[i].f[w], *src[w]);
     }

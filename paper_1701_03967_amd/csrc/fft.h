@@ -189,4 +189,46 @@ __device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls) {
   if (rem == 1) fft_stage<T, 2, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
 }
 
+// Length-K DFT for K not a power of two (Bluestein's chirp-z): with
+// c_j = exp(-i pi j^2 / K), jk = (j^2 + k^2 - (k - j)^2) / 2 gives
+//   X_k = c_k sum_j (x_j c_j) conj(c_{k-j}),
+// a convolution computed as a cyclic one of length L >= 2K - 1 (a power of
+// two) with two Stockham FFTs and the precomputed spectrum of conj(c)
+// (bhat, already divided by L).  INV (exp(+2 pi i jk/K)): conjugated chirp
+// and spectrum.  Data in slots 0..K-1 of each buffer; slots up to L - 1 are
+// scratch.  Ends with a barrier.
+template <typename T, bool INV, int NT>
+__device__ void bluestein(C2<T>* buf, int nfft, int K, int lL, const C2<T>* __restrict__ chirp,
+                          const C2<T>* __restrict__ bhat, const C2<T>* tw, int ls) {
+  const int L = 1 << lL;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (nfft << lL); i += NT) {
+    const int f = i >> lL, j = i & (L - 1);
+    C2<T>& v = slot(buf + f * ls, j);
+    if (j < K) {
+      const C2<T> c = chirp[j];
+      v = INV ? cmulc(v, c) : cmul(v, c);
+    } else {
+      v = C2<T>{0, 0};
+    }
+  }
+  __syncthreads();
+  fft_all<T, false, NT>(buf, nfft, lL, tw, ls);
+  for (int i = tid; i < (nfft << lL); i += NT) {
+    const int f = i >> lL, j = i & (L - 1);
+    C2<T>& v = slot(buf + f * ls, j);
+    const C2<T> b = bhat[j];
+    v = INV ? cmulc(v, b) : cmul(v, b);
+  }
+  __syncthreads();
+  fft_all<T, true, NT>(buf, nfft, lL, tw, ls);
+  for (int i = tid; i < nfft * K; i += NT) {
+    const int f = i / K, j = i - f * K;
+    C2<T>& v = slot(buf + f * ls, j);
+    const C2<T> c = chirp[j];
+    v = INV ? cmulc(v, c) : cmul(v, c);
+  }
+  __syncthreads();
+}
+
 }  // namespace fftfem

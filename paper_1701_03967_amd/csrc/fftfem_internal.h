@@ -32,6 +32,11 @@ struct AxisTables {
   std::vector<double> twf;    // K complex: exp(-2 pi i q / K)
   std::vector<double> twm;    // K complex: exp(-i pi k / (2K))
   std::vector<double> twd;    // K complex: exp(-i pi k / K)
+  // K not a power of two: Bluestein's chirp-z tables (L = 0 otherwise)
+  int64_t L = 0;              // power of two >= 2K - 1
+  std::vector<double> chirp;  // K complex: exp(-i pi j^2 / K)
+  std::vector<double> bhat;   // L complex: DFT_L of the conjugate chirp, / L
+  std::vector<double> twl;    // L complex: exp(-2 pi i q / L)
 };
 
 // Builds the tables of one axis.  Returns 0 or a negative FFTFEM_* status.

@@ -23,6 +23,10 @@ struct LineArgs {
   const T* twf;           // K complex exp(-2 pi i q/K)
   const T* twm;           // K complex exp(-i pi k/(2K))
   const T* twd;           // K complex exp(-i pi k/K)
+  int L, log2L;           // K not a power of two: Bluestein length (else 0)
+  const T* chirp;         // K complex exp(-i pi j^2/K)
+  const T* bhat;          // L complex, spectrum of the conjugate chirp / L
+  const T* twl;           // L complex exp(-2 pi i q/L)
   const T* mu_self;       // M: diff_d 4/h_d^2 lambda along this axis
   const T* mu_o[2];       // other axes
   int64_t so[2], Mo[2];   // their strides and lengths
@@ -50,9 +54,20 @@ struct ApplyArgs {
 };
 
 
+// Line-pass launchers, one per object built from line.hip: element counts
+// that are powers of two, and all others (a.L != 0).
 template <typename T>
-hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
-                       hipStream_t s);
+hipError_t launch_line_p2(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_line_any(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                           hipStream_t s);
+template <typename T>
+inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                              hipStream_t s) {
+  return a.L == 0 ? launch_line_p2<T>(n, mode, upd, a, nblocks, lds, s)
+                  : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
+}
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);

@@ -362,7 +362,29 @@ __device__ __forceinline__ void mid_apply2(rsrc_t Q, int K, int ka, int kb, cons
   }
 }
 
-template <typename T, int NORD, int MODE, bool UPD, bool LF>
+// This file is compiled twice: with FFTFEM_LINE_POW2=1 for element counts K
+// that are powers of two (shift/mask index arithmetic, Stockham FFTs) and
+// with 0 for all other K (divisions, Bluestein DFTs).  The flag is a
+// template argument of the kernels, so the two objects define different
+// symbols.
+#ifndef FFTFEM_LINE_POW2
+#define FFTFEM_LINE_POW2 1
+#endif
+constexpr bool kLinePow2 = FFTFEM_LINE_POW2 != 0;
+
+// Length-K DFTs of the nfft buffers of a tile: Stockham for K a power of
+// two, Bluestein otherwise.
+template <typename T, bool INV, int NT, bool P2>
+__device__ __forceinline__ void line_dft(const LineArgs<T>& a, C2<T>* buf, int nfft, int ls) {
+  if constexpr (P2) {
+    fft_all<T, INV, NT>(buf, nfft, a.log2K, reinterpret_cast<const C2<T>*>(a.twf), ls);
+  } else {
+    bluestein<T, INV, NT>(buf, nfft, a.K, a.log2L, reinterpret_cast<const C2<T>*>(a.chirp),
+                          reinterpret_cast<const C2<T>*>(a.bhat), reinterpret_cast<const C2<T>*>(a.twl), ls);
+  }
+}
+
+template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
 __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
   constexpr int kNT = LineCfg<T>::NT, kMaxTPT = LineCfg<T>::TPT, kMaxCPT = LineCfg<T>::CPT;
   if (a.flag && *a.flag) return;
@@ -373,7 +395,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
   const int tid = threadIdx.x;
   const int K = a.K, lk = a.log2K, lg = a.log2G, G = 1 << lg;
   const int M = n * K - 1;
-  const int ls = K + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
+  const int ls = (a.L ? a.L : K) + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
   const int LS = NB * ls * 2;  // T slots per line
   const int64_t l0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) << lg;
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)(K * n * n));
@@ -457,9 +479,33 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     }
   };
 
-  const int ntask = G << lk;         // element tasks (g, j')
+  // element tasks (g, j'), j' < K, and contraction tasks (g, kappa),
+  // kappa < ceil(K/2): kappa >= 1 pairs the frequencies kappa and K - kappa,
+  // kappa = 0 is the bubble block (and frequency K/2 when K is even)
+  constexpr bool pow2 = P2;
+  const int kh = (K + 1) >> 1;
   const int lkh = lk - 1;
-  const int nctask = G << lkh;       // contraction tasks (g, kappa), kappa < K/2
+  const int ntask = G * K;
+  const int nctask = G * kh;
+  auto esplit = [&](int t, int& g, int& jp) {
+    if constexpr (pow2) {
+      g = t >> lk;
+      jp = t & (K - 1);
+    } else {
+      g = t / K;
+      jp = t - g * K;
+    }
+  };
+  auto csplit = [&](int t, int& g, int& kap) {
+    if constexpr (pow2) {
+      g = t >> lkh;
+      kap = t & ((1 << lkh) - 1);
+    } else {
+      g = t / kh;
+      kap = t - g * kh;
+    }
+  };
+  const bool keven = (K & 1) == 0;  // frequency K/2 exists
 
   if constexpr (MODE == FWD || MODE == MID) {
     bulk_load(a.in, a.in_f64);
@@ -470,7 +516,8 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxTPT; ++s) {
       int t = tid + s * kNT;
       if (t < ntask) {
-        int g = t >> lk, jp = t & (K - 1);
+        int g, jp;
+        esplit(t, g, jp);
         const T* r = raw + g * LS + jp * n;
         T y[NORD];
 #pragma unroll
@@ -489,7 +536,8 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxTPT; ++s) {
       int t = tid + s * kNT;
       if (t < ntask) {
-        int g = t >> lk, jp = t & (K - 1);
+        int g, jp;
+        esplit(t, g, jp);
         C2<T>* Z = buf + g * NB * ls;
         if (jp < K - 1) {
           int j = jp + 1;
@@ -507,7 +555,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       }
     }
     __syncthreads();
-    fft_all<T, false, kNT>(buf, G * NB, lk, twf, ls);
+    line_dft<T, false, kNT, P2>(a, buf, G * NB, ls);
   } else {
     bulk_load(a.in, a.in_f64);
     __syncthreads();
@@ -526,10 +574,11 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       int t = tid + s * kNT;
       nf[s][0] = nf[s][1] = (T)0;
       if (t < nctask) {
-        int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+        int g, kap;
+        csplit(t, g, kap);
         const C2<T>* B = buf + g * NB * ls;
         if (kap == 0) {
-          nf[s][1] = nodal_post<T>(B, K, K >> 1, twd, false);
+          if (keven) nf[s][1] = nodal_post<T>(B, K, K >> 1, twd, false);
         } else {
           nf[s][0] = nodal_post<T>(B, K, kap, twd, false);
           nf[s][1] = nodal_post<T>(B, K, K - kap, twd, false);
@@ -548,7 +597,8 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
           nfa = nf[u][0];
           nfb = nf[u][1];
         }
-      int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+      int g, kap;
+        csplit(t, g, kap);
       int kb = kap == 0 ? 0 : K - kap;
       C2<T>* B = buf + g * NB * ls;
       // per-line denominator base: react + the other axes' terms
@@ -561,8 +611,10 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       if constexpr (NORD > 1) {
         if (kap != 0) bubble_post<T, NORD>(B, ls, kap, kb, twm, ca, cb);
       }
-      // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap (K/2 when kap = 0)
-      const int ka = kap, kbq = kap == 0 ? (K >> 1) : K - kap;
+      // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap
+      // (K/2 when kap = 0; for odd K, kap = 0 has no second frequency and
+      // chain b runs on the bubble block again, its result unused)
+      const int ka = kap, kbq = kap == 0 ? (keven ? (K >> 1) : 0) : K - kap;
       T cha[NORD], chb[NORD];
       if (kap == 0) {
         if constexpr (NORD > 1) {
@@ -581,7 +633,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       {
         const int ra = ka == 0 ? n - 1 : n;
         const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
-        const int offb = n - 1 + (kbq - 1) * n;
+        const int offb = kbq == 0 ? 0 : n - 1 + (kbq - 1) * n;
         mid_apply2<T, NORD>(qtab, K, ka, kbq, cha, chb, res[0], res[1], bd, a.mu_self + offa,
                             a.mu_self + offb, ra, cha[0]);
       }
@@ -600,10 +652,12 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
             int b0 = 2 * (p - 1), b1 = b0 + 1;
             bool has1 = b1 < NORD - 1;
             slot(B + p * ls, 0) = {ya[b0], has1 ? ya[b1] : (T)0};
-            int h = K >> 1;
-            C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
-            C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
-            slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
+            if (keven) {
+              int h = K >> 1;
+              C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
+              C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
+              slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
+            }
           }
         } else {
           // channel spectra at FFT index kap (ya) and kb (yb): even channels
@@ -633,14 +687,14 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       }
       if (kap == 0) {
         write_nodal_zeros(B, K);
-        write_nodal_inv(B, K, K >> 1, res[1][0]);
+        if (keven) write_nodal_inv(B, K, K >> 1, res[1][0]);
       } else {
         write_nodal_inv(B, K, kap, res[0][0]);
         write_nodal_inv(B, K, K - kap, res[1][0]);
       }
     }
     __syncthreads();
-    fft_all<T, true, kNT>(buf, G * NB, lk, twf, ls);
+    line_dft<T, true, kNT, P2>(a, buf, G * NB, ls);
   } else {
   // held across a barrier: spectral results (FWD) or channel spectra (INV)
   T hw[kMaxCPT][2][NORD];
@@ -648,12 +702,16 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
   for (int s = 0; s < kMaxCPT; ++s) {
     int t = tid + s * kNT;
     if (t >= nctask) continue;
-    int g = t >> lkh, kap = t & ((1 << lkh) - 1);
-    // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap (K/2 when kap = 0)
-    const int ka = kap, kbq = kap == 0 ? (K >> 1) : K - kap;
+    int g, kap;
+        csplit(t, g, kap);
+    // frequencies of the task: ka = kap (0: the bubble block), kb = K - kap
+    // (K/2 when kap = 0; for odd K, kap = 0 has no second frequency and
+    // chain b runs on the bubble block again, its result unused)
+    const bool hasb = kap != 0 || keven;
+    const int ka = kap, kbq = kap == 0 ? (keven ? (K >> 1) : 0) : K - kap;
     const int ra = ka == 0 ? n - 1 : n;
     const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
-    const int offb = n - 1 + (kbq - 1) * n;
+    const int offb = kbq == 0 ? 0 : n - 1 + (kbq - 1) * n;
     if constexpr (MODE == FWD) {
       const C2<T>* B = buf + g * NB * ls;
       T ca[NC], cb[NC], cha[NORD], chb[NORD];
@@ -665,7 +723,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
           bubble_post<T, NORD>(B, ls, kbq, kbq, twm, ca, cb);
         }
         cha[NORD - 1] = 0;
-        channel_vec<T, NORD>(nodal_post<T>(B, K, kbq, twd, false), ca, ca, chb);
+        channel_vec<T, NORD>(hasb ? nodal_post<T>(B, K, kbq, twd, false) : (T)0, ca, ca, chb);
       } else {
         if constexpr (NORD > 1) bubble_post<T, NORD>(B, ls, kap, K - kap, twm, ca, cb);
         channel_vec<T, NORD>(nodal_post<T>(B, K, ka, twd, false), ca, cb, cha);
@@ -681,7 +739,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
 #pragma unroll
       for (int l = 0; l < NORD; ++l) {
         wa[l] = l < ra ? rs[offa + l] : (T)0;
-        wb[l] = rs[offb + l];
+        wb[l] = hasb ? rs[offb + l] : (T)0;
       }
       contract_inv2<T, NORD>(qtab, K, ka, kbq, wa, wb, hw[s][0], hw[s][1], wa[0] + wb[0]);
     }
@@ -694,12 +752,13 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxCPT; ++s) {
       int t = tid + s * kNT;
       if (t >= nctask) continue;
-      int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+      int g, kap;
+        csplit(t, g, kap);
       T* rs = raw + g * LS;
 #pragma unroll
       for (int fi = 0; fi < 2; ++fi) {
         int k = fi == 0 ? kap : (kap == 0 ? (K >> 1) : K - kap);
-        if (fi == 1 && kap == 0 && K == 1) continue;
+        if (fi == 1 && kap == 0 && !keven) continue;
         int r = k == 0 ? n - 1 : n;
         int off = k == 0 ? 0 : n - 1 + (k - 1) * n;
 #pragma unroll
@@ -716,12 +775,13 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxCPT; ++s) {
       int t = tid + s * kNT;
       if (t >= nctask) continue;
-      int g = t >> lkh, kap = t & ((1 << lkh) - 1);
+      int g, kap;
+        csplit(t, g, kap);
       int kb = kap == 0 ? 0 : K - kap;
       C2<T>* B = buf + g * NB * ls;
       if (kap == 0) {
         write_nodal_zeros(B, K);
-        write_nodal_inv(B, K, K >> 1, hw[s][1][0]);
+        if (keven) write_nodal_inv(B, K, K >> 1, hw[s][1][0]);
       } else {
         write_nodal_inv(B, K, kap, hw[s][0][0]);
         write_nodal_inv(B, K, K - kap, hw[s][1][0]);
@@ -740,10 +800,12 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
             int b0 = 2 * (p - 1), b1 = b0 + 1;
             bool has1 = b1 < NORD - 1;
             slot(B + p * ls, 0) = {ya[b0], has1 ? ya[b1] : (T)0};
-            int h = K >> 1;
-            C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
-            C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
-            slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
+            if (keven) {
+              int h = K >> 1;
+              C2<T> va = herm<T>(yb[b0], yb[b0], h, twm);
+              C2<T> vb = has1 ? herm<T>(yb[b1], yb[b1], h, twm) : C2<T>{0, 0};
+              slot(B + p * ls, h) = {va.x - vb.y, va.y + vb.x};
+            }
           }
         } else {
 #pragma unroll
@@ -771,7 +833,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       }
     }
     __syncthreads();
-    fft_all<T, true, kNT>(buf, G * NB, lk, twf, ls);
+    line_dft<T, true, kNT, P2>(a, buf, G * NB, ls);
   }
   }
 
@@ -782,7 +844,8 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxTPT; ++s) {
       int t = tid + s * kNT;
       if (t < ntask) {
-        int g = t >> lk, jp = t & (K - 1);
+        int g, jp;
+        esplit(t, g, jp);
         const C2<T>* Z = buf + g * NB * ls;
         hv[s][n - 1] = jp < K - 1 ? nodal_post<T>(Z, K, jp + 1, twd, true) : (T)0;
         int q = (jp & 1) ? K - 1 - (jp >> 1) : (jp >> 1);
@@ -807,7 +870,8 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
     for (int s = 0; s < kMaxTPT; ++s) {
       int t = tid + s * kNT;
       if (t < ntask) {
-        int g = t >> lk, jp = t & (K - 1);
+        int g, jp;
+        esplit(t, g, jp);
         T* r = raw + g * LS + jp * n;
 #pragma unroll
         for (int m = 0; m < n - 1; ++m) r[m] = hv[s][m];
@@ -845,11 +909,13 @@ static void allow_lds(F* fn, size_t lds) {
 template <typename T, int NORD, int MODE, bool UPD>
 static hipError_t go(bool lf, const LineArgs<T>& a, int nblocks, size_t lds, hipStream_t s) {
   if (lf) {
-    allow_lds(line_kernel<T, NORD, MODE, UPD, true>, lds);
-    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, true>), dim3(nblocks), dim3(LineCfg<T>::NT), lds, s, a);
+    allow_lds(line_kernel<T, NORD, MODE, UPD, true, kLinePow2>, lds);
+    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, true, kLinePow2>), dim3(nblocks), dim3(LineCfg<T>::NT),
+                       lds, s, a);
   } else {
-    allow_lds(line_kernel<T, NORD, MODE, UPD, false>, lds);
-    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, false>), dim3(nblocks), dim3(LineCfg<T>::NT), lds, s, a);
+    allow_lds(line_kernel<T, NORD, MODE, UPD, false, kLinePow2>, lds);
+    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, false, kLinePow2>), dim3(nblocks), dim3(LineCfg<T>::NT),
+                       lds, s, a);
   }
   return hipGetLastError();
 }
@@ -864,9 +930,15 @@ static hipError_t launch_line_n(int mode, bool upd, const LineArgs<T>& a, int nb
   return upd ? go<T, NORD, MID, true>(lf, a, nblocks, lds, s) : go<T, NORD, MID, false>(lf, a, nblocks, lds, s);
 }
 
+#if FFTFEM_LINE_POW2
+#define FFTFEM_LAUNCH_LINE launch_line_p2
+#else
+#define FFTFEM_LAUNCH_LINE launch_line_any
+#endif
+
 template <typename T>
-hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
-                       hipStream_t s) {
+hipError_t FFTFEM_LAUNCH_LINE(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                              hipStream_t s) {
   switch (n) {
 #define FFTFEM_CASE(N) \
   case N:              \
@@ -886,7 +958,8 @@ hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblo
   }
 }
 
-template hipError_t launch_line<float>(int, int, bool, const LineArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_line<double>(int, int, bool, const LineArgs<double>&, int, size_t, hipStream_t);
+template hipError_t FFTFEM_LAUNCH_LINE<float>(int, int, bool, const LineArgs<float>&, int, size_t, hipStream_t);
+template hipError_t FFTFEM_LAUNCH_LINE<double>(int, int, bool, const LineArgs<double>&, int, size_t,
+                                               hipStream_t);
 
 }  // namespace fftfem

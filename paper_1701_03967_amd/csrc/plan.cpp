@@ -411,6 +411,69 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
     if (!v) return kESPECTRUM;
   for (double v : t->lam)
     if (!(v > 0) || !std::isfinite(v)) return kESPECTRUM;
+  if (K & (K - 1)) {
+    // Bluestein tables for a length-K DFT: chirp c_j = exp(-i pi j^2 / K)
+    // (argument reduced exactly: j^2 mod 2K), and the spectrum of the
+    // conjugate chirp b (b_m = conj(c_m) at m and L - m, |m| < K, zero
+    // elsewhere) over L >= 2K - 1 points, divided by L.
+    int64_t L = 1;
+    while (L < 2 * K - 1) L *= 2;
+    t->L = L;
+    t->chirp.resize(2 * K);
+    std::vector<long double> br(L, 0.0L), bi(L, 0.0L);
+    for (int64_t j = 0; j < K; ++j) {
+      q sn, cs;
+      sincospi((j * j) % (2 * K), K, &sn, &cs);
+      t->chirp[2 * j] = (double)cs;
+      t->chirp[2 * j + 1] = -(double)sn;
+      br[j] = (long double)cs;
+      bi[j] = (long double)sn;
+      if (j > 0) {
+        br[L - j] = (long double)cs;
+        bi[L - j] = (long double)sn;
+      }
+    }
+    // iterative radix-2 FFT (exp(-2 pi i/L)) in extended precision
+    std::vector<long double> wr(L / 2), wi(L / 2);
+    for (int64_t m = 0; m < L / 2; ++m) {
+      q sn, cs;
+      sincospi(2 * m, L, &sn, &cs);
+      wr[m] = (long double)cs;
+      wi[m] = -(long double)sn;
+    }
+    for (int64_t i = 1, j = 0; i < L; ++i) {
+      int64_t bit = L >> 1;
+      for (; j & bit; bit >>= 1) j ^= bit;
+      j ^= bit;
+      if (i < j) {
+        std::swap(br[i], br[j]);
+        std::swap(bi[i], bi[j]);
+      }
+    }
+    for (int64_t len = 2; len <= L; len *= 2) {
+      const int64_t step = L / len;
+      for (int64_t i0 = 0; i0 < L; i0 += len)
+        for (int64_t m = 0; m < len / 2; ++m) {
+          long double xr = br[i0 + m + len / 2], xi = bi[i0 + m + len / 2];
+          long double tr = xr * wr[m * step] - xi * wi[m * step];
+          long double ti = xr * wi[m * step] + xi * wr[m * step];
+          br[i0 + m + len / 2] = br[i0 + m] - tr;
+          bi[i0 + m + len / 2] = bi[i0 + m] - ti;
+          br[i0 + m] += tr;
+          bi[i0 + m] += ti;
+        }
+    }
+    t->bhat.resize(2 * L);
+    t->twl.resize(2 * L);
+    for (int64_t m = 0; m < L; ++m) {
+      t->bhat[2 * m] = (double)(br[m] / (long double)L);
+      t->bhat[2 * m + 1] = (double)(bi[m] / (long double)L);
+      q sn, cs;
+      sincospi(2 * m, L, &sn, &cs);
+      t->twl[2 * m] = (double)cs;
+      t->twl[2 * m + 1] = -(double)sn;
+    }
+  }
   t->twf.resize(2 * K);
   t->twm.resize(2 * K);
   t->twd.resize(2 * K);

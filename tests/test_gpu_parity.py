@@ -272,3 +272,34 @@ def test_refine_large_K(n, K, diff, react, kind):
     say("  fp64", e64, "refined", er, p.stats())
     assert e64 < 1e-11
     assert er < 1e-10
+
+
+# Element counts that are not powers of two (Bluestein DFTs, odd K without
+# a K/2 frequency, one-element-wide tiles)
+CASES_ANYK = [
+    (1, (7,), (1.0,), 1.0),
+    (2, (3,), (1.0,), 0.0),
+    (3, (12,), (2.0,), 5.0),
+    (5, (33,), (1.0,), 0.0),
+    (9, (100,), (1.0,), 0.0),
+    (3, (5, 12), (1.0, 0.5), 0.0),
+    (8, (37, 64), (1.0, 2.0), 1000.0),
+    (2, (33, 17), (0.7, 1.3), 0.0),
+    (5, (100, 7), (1.0, 1.0), 1.0),
+    (2, (3, 5, 6), (1.0, 2.0, 0.5), 0.0),
+    (4, (9, 6, 11), (1.0, 1.0, 1.0), 2.0),
+]
+
+
+@pytest.mark.parametrize("n,K,diff,react", CASES_ANYK)
+def test_solve_any_K(n, K, diff, react):
+    say("any K", n, K, diff, react)
+    fm = _fftfem()
+    f = inputs.draw_rhs([n * k - 1 for k in K], 700 + n, "normal")
+    u_ref = osolve.solve(f, n, K, diff, react)
+    fd = dev(f)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-5), ("fp32_refine", 1e-10)):
+        p = fm.Plan(K, n, diff, react, precision=prec, max_iter=4, tol=1e-13)
+        e = rel(p.solve(fd).cpu().numpy(), u_ref)
+        say("  ", prec, e)
+        assert e < tol, prec
