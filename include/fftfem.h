@@ -166,6 +166,39 @@ int fftfem_set_timing(fftfem_plan_t p, int enable);
 int fftfem_get_timing(fftfem_plan_t p, int max, char* names, double* avg_ms, int* count);
 
 /*
+ * Batches of independent problems (the implicit time step of many small
+ * heat problems in Sect. 4 is one use): count problems, each with its own
+ * descriptor (any N, K, n, diff, react, precision, nrhs), solved together.
+ *
+ * fftfem_plan_batch builds one plan per problem (tables of equal (n, K)
+ * axes are computed once per axis length within a plan; every plan owns its
+ * device tables and workspace).  flags: FFTFEM_BATCH_TUNE measures, on the
+ * first solve, the lines per tile and the largest FFT radix of every
+ * float32 two-dimensional line pass kind in the batch (kept process-wide for
+ * later plans of the same kind).  EINVAL for count < 1 or a null pointer;
+ * otherwise the status of the first descriptor that fails fftfem_plan_ex.
+ *
+ * fftfem_solve_batch: f[i] and u[i] are device arrays of problem i (its
+ * nrhs right-hand sides, as in fftfem_solve; u[i] must not overlap f[i]).
+ * The first call (and any call with different pointers) records every
+ * problem's schedule, groups all problems' passes of one kind at one
+ * position of the schedule into one launch, and captures the launches
+ * into a graph on an internal stream; each call then launches that graph
+ * on s.  Right-hand sides of one problem run one after another (they share
+ * the problem's workspace); problems run side by side.  Asynchronous on s;
+ * calls that overlap on one batch race.  fftfem_batch_get_stats synchronizes
+ * s of the last solve and returns problem i's statistics of its last
+ * right-hand side, like fftfem_get_stats.
+ */
+typedef struct fftfem_batch_s* fftfem_batch_t;
+#define FFTFEM_BATCH_TUNE 1
+int fftfem_plan_batch(fftfem_batch_t* out, int count, const fftfem_desc* descs, int flags);
+int fftfem_solve_batch(fftfem_batch_t b, const double* const* f, double* const* u, hipStream_t s);
+int fftfem_batch_get_stats(fftfem_batch_t b, int i, fftfem_stats* out);
+size_t fftfem_batch_workspace_bytes(const fftfem_batch_t b);
+void fftfem_destroy_batch(fftfem_batch_t b);
+
+/*
  * Host-only access to the plan arithmetic, for tests on machines without a
  * GPU (no device is touched).  fftfem_axis_tables_host: the lam and Q tables
  * of fftfem_plan_tables for one axis of n-th order elements on K elements.

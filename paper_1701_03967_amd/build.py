@@ -49,17 +49,18 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
     objs.append(plan_o)
     if verbose:
         print(f"[build] plan.cpp {dt:.1f}s", flush=True)
-    api_o = os.path.join(BUILD, "api.o")
-    dt = _run([HIPCC, "-O2", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
-               "-c", os.path.join(CSRC, "api.cpp"), "-o", api_o])
-    objs.append(api_o)
-    if verbose:
-        print(f"[build] api.cpp {dt:.1f}s", flush=True)
-    # kernels: line.hip twice (element counts that are powers of two, and
-    # all others), ops.hip once; compiled in parallel
-    units = [("line.hip", "line_p2.o", ["-DFFTFEM_LINE_POW2=1"]),
-             ("line.hip", "line_any.o", ["-DFFTFEM_LINE_POW2=0"]),
-             ("ops.hip", "ops.o", [])]
+    for src in ("api.cpp", "batch.cpp"):
+        obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        dt = _run([HIPCC, "-O2", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
+                   "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+        if verbose:
+            print(f"[build] {src} {dt:.1f}s", flush=True)
+    # kernels: line.hip four times (element counts that are powers of two or
+    # not, float32 or float64), ops.hip once; compiled in parallel
+    units = [("line.hip", f"line_{kind}_{real}.o", [f"-DFFTFEM_LINE_POW2={p2}", f"-DFFTFEM_LINE_REAL={real}"])
+             for kind, p2 in (("p2", 1), ("any", 0)) for real in ("float", "double")]
+    units.append(("ops.hip", "ops.o", []))
 
     def compile_unit(u):
         src, o, extra = u

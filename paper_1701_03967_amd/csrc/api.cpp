@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,7 @@
 #include "fftfem.h"
 #include "fftfem_internal.h"
 #include "launch.h"
+#include "record.h"
 
 using namespace fftfem;
 
@@ -55,6 +57,12 @@ struct fftfem_plan_s {
   size_t bytes = 0;
   int lds_max = 65536;
   hipStream_t last = nullptr;
+  // batched execution: launches are recorded (with their schedule position)
+  // instead of issued while rec is set
+  Recorder* rec = nullptr;
+  int phase = 0;
+  // timing runs of the tuner: forced lines per tile and FFT radix (0: none)
+  int Gforce = 0, lrforce = 0;
   std::vector<void*> allocs;
   // per-kernel timing (measurement only)
   bool timing = false;
@@ -175,6 +183,11 @@ int64_t fft_len(int64_t K) {
   return L;
 }
 
+// Tuned parameters are shared by element counts with the same FFT length
+// (K itself, or the Bluestein length) and kind of transform.
+int64_t tune_class_of(int64_t K) { return 2 * fft_len(K) + ((K & (K - 1)) ? 1 : 0); }
+
+
 size_t line_lds(const fftfem_plan_s* p, int64_t K, size_t elt, bool pad = true) {
   return (size_t)(1 + p->n / 2) * (fft_len(K) + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
 }
@@ -189,6 +202,62 @@ int choose_G(const fftfem_plan_s* p, int64_t K, size_t elt, int64_t nlines) {
   while (G < 64 && (size_t)(2 * G) * per <= budget && 2 * G * K <= kLineTasks && 2 * G <= nlines)
     G *= 2;
   return G;
+}
+
+}  // namespace
+
+// ---- tuned line-pass parameters (process-wide) ----------------------------
+bool TuneKey::operator<(const TuneKey& o) const {
+  if (elt != o.elt) return elt < o.elt;
+  if (n != o.n) return n < o.n;
+  if (mode != o.mode) return mode < o.mode;
+  if (lf != o.lf) return lf < o.lf;
+  return K < o.K;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+}  // namespace
+
+namespace fftfem {
+
+void tune_set(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  g_tune[k] = v;
+}
+
+bool tune_get(const TuneKey& k, TuneVal* v) {
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  if (g_tune.empty()) return false;
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void plan_set_recorder(fftfem_plan_t p, Recorder* r) { p->rec = r; }
+void plan_set_stream(fftfem_plan_t p, hipStream_t s) { p->last = s; }
+int64_t tune_class(int64_t K) { return tune_class_of(K); }
+
+}  // namespace fftfem
+
+namespace {
+
+template <typename A>
+void record(fftfem_plan_t p, int kind, std::initializer_list<int> key, const A& args, int64_t nblocks,
+            size_t lds) {
+  Rec r;
+  r.phase = p->phase;
+  r.kind = kind;
+  int i = 0;
+  for (int k : key) r.key[i++] = k;
+  for (; i < 5; ++i) r.key[i] = 0;
+  r.args.resize(sizeof(A));
+  std::memcpy(r.args.data(), &args, sizeof(A));
+  r.nblocks = (int)nblocks;
+  r.lds = lds;
+  p->rec->recs.push_back(std::move(r));
 }
 
 int ilog2i(int x) {
@@ -253,6 +322,19 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.es = gm.es;
   a.nlines = gm.nlines;
   a.G = choose_G(p, t.K, sizeof(T), a.nlines);
+  a.lrmax = 4;
+  {
+    TuneVal tv;
+    const bool lf = gm.es > 1;
+    if (p->Gforce) {
+      a.G = p->Gforce;
+      a.lrmax = p->lrforce;
+    } else if (tune_get(TuneKey{(int)sizeof(T), p->n, mode, lf ? 1 : 0, tune_class(t.K)}, &tv)) {
+      a.G = tv.G;
+      a.lrmax = tv.lrmax;
+    }
+    while (a.G > 1 && (a.G > a.nlines || (int64_t)a.G * t.K > kLineTasks)) a.G /= 2;
+  }
   a.log2G = ilog2i(a.G);
   a.Q = tab<T>(p, gm.axis, 0);
   a.twf = tab<T>(p, gm.axis, 1);
@@ -278,6 +360,11 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
   if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
   if (want_partials) p->nparts_last = (int)nblocks;
+  if (p->rec) {
+    record(p, sizeof(T) == 4 ? REC_LINE32 : REC_LINE64,
+           {p->n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, a.L == 0 ? 1 : 0}, a, nblocks, lds);
+    return FFTFEM_OK;
+  }
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +
                     "_ax" + std::to_string(gm.axis) + (gm.es == 1 && gm.axis != p->N - 1 ? "t" : ""));
   return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
@@ -285,6 +372,13 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
 
 template <typename T>
 int transpose(fftfem_plan_t p, const T* in, T* out, int64_t R, int64_t C, hipStream_t s) {
+  if (p->rec) {
+    TransposeJob j{in, out, R, C, (R + 63) / 64, (C + 63) / 64};
+    const int64_t batch = p->size / (R * C);
+    if (batch != 1) return FFTFEM_ENOTIMPL;
+    record(p, sizeof(T) == 4 ? REC_TR32 : REC_TR64, {}, j, j.ntr * j.ntc, 0);
+    return FFTFEM_OK;
+  }
   Timed tm(p, s, std::string("transpose") + (sizeof(T) == 4 ? "32" : "64"));
   return from_hip(launch_transpose<T>(in, out, p->size / (R * C), R, C, s));
 }
@@ -335,6 +429,10 @@ int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, voi
   int64_t W = a.TL + 2 * p->n;
   size_t lds = (size_t)planes * a.G * W * sizeof(double);
   int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
+  if (p->rec) {
+    record(p, REC_APPLY, {p->n, in1.l ? 1 : 0}, a, nblocks, lds);
+    return FFTFEM_OK;
+  }
   Timed tm(p, s, std::string("apply_ax") + std::to_string(axis));
   return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
 }
@@ -348,12 +446,13 @@ int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, voi
 //       pass axis 1: t2 = c t, s2 = c1 a t + react c t + c2 c s;
 //       pass axis 0: c0 a t2 + c s2
 int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_kind,
-                   const int* flag, hipStream_t s) {
+                   const int* flag, hipStream_t s, int ph = 0) {
   const double* c = p->coef;
   double react = p->desc.react;
   double** T = p->tmp;
   const DDp none{nullptr, nullptr};
   int rc;
+  p->phase = ph;
   if (p->N == 1) {
     double c1[4] = {c[0], react, 0, 0};
     return apply_pass(p, 0, {u, nullptr}, none, f, out, nullptr, out_kind, nullptr, nullptr, c1, nullptr,
@@ -362,6 +461,7 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   const double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
   rc = apply_pass(p, p->N - 1, {u, nullptr}, none, nullptr, T[0], T[1], 2, T[2], T[3], cC, cA, flag, s);
   if (rc) return rc;
+  p->phase = ph + 1;
   if (p->N == 2) {
     double c1[4] = {c[0], react, 0, c[1]};
     return apply_pass(p, 0, {T[0], T[1]}, {T[2], T[3]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
@@ -370,6 +470,7 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   double c4[4] = {c[1], react, 0, c[2]};
   rc = apply_pass(p, 1, {T[0], T[1]}, {T[2], T[3]}, nullptr, T[4], T[5], 2, T[6], T[7], cC, c4, flag, s);
   if (rc) return rc;
+  p->phase = ph + 2;
   double c1[4] = {c[0], 0, 0, 1};
   return apply_pass(p, 0, {T[4], T[5]}, {T[6], T[7]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
                     nullptr, flag, s);
@@ -386,10 +487,17 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
 // In 2D and 3D every forward pass before the division would have to run in
 // float64 to the same end, at about the cost of a float64 solve, so those
 // keep float32 and pay one more refinement step instead.
+// Schedule positions (phase = ph + slot) of a chain's passes: 0 forward
+// along axis N-1, N-1-d forward along axis d (0 < d < N-1), N-1 and N+1 the
+// transposes around the middle pass N, N+1+d inverse along axis d.
+constexpr int chain_slots(int N) { return 2 * N + 2; }
+
 template <typename T>
 int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* work2, double* out,
-                    const double* upd, const int* flag, hipStream_t s, bool partials, bool mid64 = false) {
+                    const double* upd, const int* flag, hipStream_t s, bool partials, bool mid64 = false,
+                    int ph = 0) {
   int N = p->N, rc;
+  p->phase = ph;
   if (N == 1) {
     if (mid64 && sizeof(T) == 4)
       return line_pass<double>(p, natural_geom(p, 0, true), MID, in, in_f64, out, 1, upd, flag, s, partials);
@@ -398,11 +506,13 @@ int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* wor
   rc = line_pass<T>(p, natural_geom(p, N - 1, true), FWD, in, in_f64, work, 0, nullptr, flag, s, false);
   if (rc) return rc;
   for (int d = N - 2; d >= 1; --d) {
+    p->phase = ph + N - 1 - d;
     rc = line_pass<T>(p, natural_geom(p, d, true), FWD, work, 0, work, 0, nullptr, flag, s, false);
     if (rc) return rc;
   }
   if (N == 2 && p->tr2d) {
     // axis 0 as contiguous lines of a transposed copy: (M0 x M1) -> (M1 x M0)
+    p->phase = ph + N - 1;
     rc = transpose<T>(p, work, work2, p->M[0], p->M[1], s);
     if (rc) return rc;
     Geom g;
@@ -414,19 +524,42 @@ int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* wor
     g.oaxis[0] = 1;
     g.so[0] = p->M[0];
     g.Mo[0] = p->M[1];
+    p->phase = ph + N;
     rc = line_pass<T>(p, g, MID, work2, 0, work2, 0, nullptr, flag, s, false);
     if (rc) return rc;
+    p->phase = ph + N + 1;
     rc = transpose<T>(p, work2, work, p->M[1], p->M[0], s);
     if (rc) return rc;
   } else {
+    p->phase = ph + N;
     rc = line_pass<T>(p, natural_geom(p, 0, true), MID, work, 0, work, 0, nullptr, flag, s, false);
     if (rc) return rc;
   }
   for (int d = 1; d <= N - 2; ++d) {
+    p->phase = ph + N + 1 + d;
     rc = line_pass<T>(p, natural_geom(p, d, true), INV, work, 0, work, 0, nullptr, flag, s, false);
     if (rc) return rc;
   }
+  p->phase = ph + 2 * N;
   return line_pass<T>(p, natural_geom(p, N - 1, true), INV, work, 0, out, 1, upd, flag, s, partials);
+}
+
+// Geometry of the tuner's passes (float32 2D plans): 0 forward along axis 1,
+// 1 the middle pass along axis 0 (on the transposed copy when the solve
+// uses one), 2 inverse along axis 1.
+Geom tune_geom(fftfem_plan_t p, int pass) {
+  if (pass != 1) return natural_geom(p, p->N - 1, true);
+  if (!p->tr2d) return natural_geom(p, 0, true);
+  Geom g;
+  g.axis = 0;
+  g.M = p->M[0];
+  g.es = 1;
+  g.nlines = p->M[1];
+  g.nother = 1;
+  g.oaxis[0] = 1;
+  g.so[0] = p->M[0];
+  g.Mo[0] = p->M[1];
+  return g;
 }
 
 int64_t max_blocks_last_pass(const fftfem_plan_s* p, size_t elt) {
@@ -461,7 +594,11 @@ void fftfem_destroy(fftfem_plan_t p) {
   delete p;
 }
 
-int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
+int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) { return plan_create(out, din, nullptr); }
+
+}  // extern "C"
+
+int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* cache) {
   if (!out) return FFTFEM_EINVAL;
   *out = nullptr;
   int rc = validate(din);
@@ -498,12 +635,15 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
     auto it = seen.find(d.K[i]);
     if (it != seen.end()) {
       p->host[i] = p->host[it->second];
+    } else if (cache && cache->get(d.n, d.K[i], &p->host[i])) {
+      seen[d.K[i]] = i;
     } else {
       rc = build_axis_tables(d.n, d.K[i], 1.0, 1.0, &p->host[i]);
       if (rc) {
         delete p;
         return rc;
       }
+      if (cache) cache->put(d.n, d.K[i], p->host[i]);
       seen[d.K[i]] = i;
     }
     p->coef[i] = d.diff[i] * 4.0 * ((double)d.K[i] / d.X[i]) * ((double)d.K[i] / d.X[i]);
@@ -570,8 +710,8 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
   for (int i = 0; i < p->ntmp && !rc; ++i)
     rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
   if (!rc) {
-    p->npartials = (int)std::max<int64_t>(max_blocks_last_pass(p, sizeof(float)),
-                                          max_blocks_last_pass(p, sizeof(double)));
+    // one tile per line at most (tuned or forced lines per tile may be 1)
+    p->npartials = (int)(p->size / p->M[d.N - 1]);
     rc = dev_alloc(p, (void**)&p->partials, (size_t)p->npartials * 2 * sizeof(double));
   }
   if (!rc) rc = dev_alloc(p, (void**)&p->flags, (size_t)p->nrhs * sizeof(int));
@@ -588,6 +728,8 @@ int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* din) {
   *out = p;
   return FFTFEM_OK;
 }
+
+extern "C" {
 
 int fftfem_plan(fftfem_plan_t* out, int N, const int64_t* K, int n, const double* diff,
                 double react) {
@@ -623,21 +765,41 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
     double* ur = u + (size_t)r * p->size;
     int* flag = p->flags + r;
     double* st = p->stats + (size_t)r * kStatsLen;
-    rc = from_hip(launch_reset(flag, st, kStatsLen, s));
+    // schedule positions: reset, the chain, then per refinement step the
+    // operator passes, the chain and the convergence test (right-hand sides
+    // in sequence: they share the workspace)
+    const int N = p->N, SC = chain_slots(N), per_it = N + SC + 1;
+    const int base = r * (1 + SC + p->desc.max_iter * per_it);
+    p->phase = base;
+    if (p->rec) {
+      ResetJob j{flag, st, kStatsLen};
+      record(p, REC_RESET, {}, j, 1, 0);
+    } else {
+      rc = from_hip(launch_reset(flag, st, kStatsLen, s));
+    }
     if (rc) break;
     if (p->desc.precision == FFTFEM_FP64) {
-      rc = transform_chain<double>(p, fr, 1, ur, p->W64b, ur, nullptr, nullptr, s, false);
+      rc = transform_chain<double>(p, fr, 1, ur, p->W64b, ur, nullptr, nullptr, s, false, false, base + 1);
       continue;
     }
-    rc = transform_chain<float>(p, fr, 1, p->W32, p->W32b, ur, nullptr, nullptr, s, false);
+    rc = transform_chain<float>(p, fr, 1, p->W32, p->W32b, ur, nullptr, nullptr, s, false, false, base + 1);
     if (rc || p->desc.precision == FFTFEM_FP32) continue;
     for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
+      const int pit = base + 1 + SC + (it - 1) * per_it;
       // residual in float64 for the 1D float64 pass, float32 otherwise
-      const bool one = p->N == 1;
+      const bool one = N == 1;
       void* r = one ? (void*)p->W64r : (void*)p->W32;
-      rc = operator_apply(p, ur, fr, r, one ? 1 : 0, flag, s);
-      if (!rc) rc = transform_chain<float>(p, r, one ? 1 : 0, p->W32, p->W32b, ur, ur, flag, s, true, one);
-      if (!rc) rc = from_hip(launch_reduce(p->partials, p->nparts_last, it, p->desc.tol, flag, st, s));
+      rc = operator_apply(p, ur, fr, r, one ? 1 : 0, flag, s, pit);
+      if (!rc)
+        rc = transform_chain<float>(p, r, one ? 1 : 0, p->W32, p->W32b, ur, ur, flag, s, true, one, pit + N);
+      if (rc) break;
+      p->phase = pit + N + SC;
+      if (p->rec) {
+        ReduceJob j{p->partials, p->nparts_last, it, p->desc.tol, flag, st};
+        record(p, REC_REDUCE, {}, j, 1, 0);
+      } else {
+        rc = from_hip(launch_reduce(p->partials, p->nparts_last, it, p->desc.tol, flag, st, s));
+      }
     }
   }
   return rc;
@@ -746,3 +908,56 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
 }
 
 }  // extern "C"
+
+namespace fftfem {
+
+int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info) {
+  if (!p || !info || pass < 0 || pass > 2) return FFTFEM_EINVAL;
+  if (p->N != 2 || p->desc.precision == FFTFEM_FP64) return FFTFEM_ENOTIMPL;
+  const Geom g = tune_geom(p, pass);
+  const int64_t K = p->K[g.axis];
+  info->n = p->n;
+  info->mode = pass == 0 ? FWD : (pass == 1 ? MID : INV);
+  info->lf = g.es > 1 ? 1 : 0;
+  info->K = K;
+  int G = 1;
+  while (G < 64 && 2 * G * K <= kLineTasks && 2 * G <= g.nlines &&
+         (size_t)(2 * G) * line_lds(p, K, sizeof(float)) <= (size_t)p->lds_max)
+    G *= 2;
+  info->Gmax = G;
+  return FFTFEM_OK;
+}
+
+int plan_time_pass(fftfem_plan_t p, int pass, int G, int lrmax, int reps, hipStream_t s, float* ms) {
+  PassInfo info;
+  int rc = plan_pass_info(p, pass, &info);
+  if (rc) return rc;
+  if (G < 1 || G > info.Gmax || (G & (G - 1)) || lrmax < 2 || lrmax > 4 || reps < 1) return FFTFEM_EINVAL;
+  const Geom g = tune_geom(p, pass);
+  float* buf = (pass == 1 && p->tr2d) ? p->W32b : p->W32;
+  hipEvent_t a = nullptr, b = nullptr;
+  if ((rc = from_hip(hipEventCreate(&a)))) return rc;
+  if ((rc = from_hip(hipEventCreate(&b)))) {
+    (void)hipEventDestroy(a);
+    return rc;
+  }
+  p->Gforce = G;
+  p->lrforce = lrmax;
+  Recorder* saved = p->rec;
+  p->rec = nullptr;
+  rc = line_pass<float>(p, g, info.mode, buf, 0, buf, 0, nullptr, nullptr, s, false);  // warm-up
+  if (!rc) rc = from_hip(hipEventRecord(a, s));
+  for (int i = 0; i < reps && !rc; ++i)
+    rc = line_pass<float>(p, g, info.mode, buf, 0, buf, 0, nullptr, nullptr, s, false);
+  if (!rc) rc = from_hip(hipEventRecord(b, s));
+  if (!rc) rc = from_hip(hipEventSynchronize(b));
+  if (!rc) rc = from_hip(hipEventElapsedTime(ms, a, b));
+  if (!rc) *ms /= reps;
+  p->rec = saved;
+  p->Gforce = p->lrforce = 0;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+}  // namespace fftfem

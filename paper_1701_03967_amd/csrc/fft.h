@@ -174,18 +174,29 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, int nfft, int lk, int Ns, 
   }
 }
 
-// All stages: radix 16 while possible, then one of 8, 4 or 2.  Buffer f
-// starts at buf + f * ls (ls >= K complex values).
+// All stages: the largest radix up to 2^lrmax (16, 8 or 4) while possible,
+// then one stage of a smaller radix.  Buffer f starts at buf + f * ls
+// (ls >= K complex values).
 template <typename T, bool INV, int NT>
-__device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls) {
+__device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls, int lrmax = 4) {
   int lns = 0, rem = lk;
-  while (rem >= 4) {
-    fft_stage<T, 16, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
-    lns += 4;
-    rem -= 4;
+  if (lrmax >= 4)
+    while (rem >= 4) {
+      fft_stage<T, 16, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+      lns += 4;
+      rem -= 4;
+    }
+  if (lrmax >= 3)
+    while (rem >= 3) {
+      fft_stage<T, 8, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+      lns += 3;
+      rem -= 3;
+    }
+  while (rem >= 2) {
+    fft_stage<T, 4, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
+    lns += 2;
+    rem -= 2;
   }
-  if (rem == 3) fft_stage<T, 8, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
-  if (rem == 2) fft_stage<T, 4, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
   if (rem == 1) fft_stage<T, 2, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
 }
 
@@ -199,7 +210,7 @@ __device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls) {
 // scratch.  Ends with a barrier.
 template <typename T, bool INV, int NT>
 __device__ void bluestein(C2<T>* buf, int nfft, int K, int lL, const C2<T>* __restrict__ chirp,
-                          const C2<T>* __restrict__ bhat, const C2<T>* tw, int ls) {
+                          const C2<T>* __restrict__ bhat, const C2<T>* tw, int ls, int lrmax) {
   const int L = 1 << lL;
   const int tid = threadIdx.x;
   for (int i = tid; i < (nfft << lL); i += NT) {
@@ -213,7 +224,7 @@ __device__ void bluestein(C2<T>* buf, int nfft, int K, int lL, const C2<T>* __re
     }
   }
   __syncthreads();
-  fft_all<T, false, NT>(buf, nfft, lL, tw, ls);
+  fft_all<T, false, NT>(buf, nfft, lL, tw, ls, lrmax);
   for (int i = tid; i < (nfft << lL); i += NT) {
     const int f = i >> lL, j = i & (L - 1);
     C2<T>& v = slot(buf + f * ls, j);
@@ -221,7 +232,7 @@ __device__ void bluestein(C2<T>* buf, int nfft, int K, int lL, const C2<T>* __re
     v = INV ? cmulc(v, b) : cmul(v, b);
   }
   __syncthreads();
-  fft_all<T, true, NT>(buf, nfft, lL, tw, ls);
+  fft_all<T, true, NT>(buf, nfft, lL, tw, ls, lrmax);
   for (int i = tid; i < nfft * K; i += NT) {
     const int f = i / K, j = i - f * K;
     C2<T>& v = slot(buf + f * ls, j);

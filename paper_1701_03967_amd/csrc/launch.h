@@ -19,6 +19,7 @@ struct LineArgs {
   int K, log2K;
   int64_t M, es, nlines;
   int G, log2G;           // lines per tile (a power of two)
+  int lrmax;              // log2 of the largest FFT radix (4, 3 or 2; 0: 4)
   const T* Q;             // K blocks of n*n
   const T* twf;           // K complex exp(-2 pi i q/K)
   const T* twm;           // K complex exp(-i pi k/(2K))
@@ -53,6 +54,55 @@ struct ApplyArgs {
   const int* flag;
 };
 
+
+// Jobs of the grouped operator, transpose and bookkeeping launches.
+struct TransposeJob {
+  const void* in;
+  void* out;
+  int64_t R, C, ntr, ntc;
+};
+struct ResetJob {
+  int* flag;
+  double* stats;
+  int nstats;
+};
+struct ReduceJob {
+  const double* partials;
+  int nparts, iter;
+  double tol;
+  int* flag;
+  double* stats;
+};
+// jobs: ApplyArgs or TransposeJob array (see launch_line's GroupedLaunch)
+struct GroupedOps {
+  const void* jobs;
+  const int* job_of;
+  const int* start;
+  int nblocks;
+  size_t lds;
+};
+hipError_t launch_apply_grouped(int n, bool lo, const GroupedOps& g, hipStream_t s);
+template <typename T>
+hipError_t launch_transpose_grouped(const GroupedOps& g, hipStream_t s);
+hipError_t launch_reset_grouped(const ResetJob* jobs, int njobs, hipStream_t s);
+hipError_t launch_reduce_grouped(const ReduceJob* jobs, int njobs, hipStream_t s);
+
+// A grouped launch: nblocks blocks over a device array of jobs; block b runs
+// tile b - start[j] of job j = job_of[b] (start has one entry per job plus
+// the total).  lds: the largest per-job tile.
+template <typename T>
+struct GroupedLaunch {
+  const LineArgs<T>* jobs;
+  const int* job_of;
+  const int* start;
+  int nblocks;
+  size_t lds;
+};
+
+template <typename T>
+hipError_t launch_line_grouped_p2(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
+template <typename T>
+hipError_t launch_line_grouped_any(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
 
 // Line-pass launchers, one per object built from line.hip: element counts
 // that are powers of two, and all others (a.L != 0).

@@ -362,7 +362,7 @@ __device__ __forceinline__ void mid_apply2(rsrc_t Q, int K, int ka, int kb, cons
   }
 }
 
-// This file is compiled twice: with FFTFEM_LINE_POW2=1 for element counts K
+// This file is compiled four times: with FFTFEM_LINE_POW2=1 for element counts K
 // that are powers of two (shift/mask index arithmetic, Stockham FFTs) and
 // with 0 for all other K (divisions, Bluestein DFTs).  The flag is a
 // template argument of the kernels, so the two objects define different
@@ -370,22 +370,30 @@ __device__ __forceinline__ void mid_apply2(rsrc_t Q, int K, int ka, int kb, cons
 #ifndef FFTFEM_LINE_POW2
 #define FFTFEM_LINE_POW2 1
 #endif
+// and once per precision (FFTFEM_LINE_REAL: float or double)
+#ifndef FFTFEM_LINE_REAL
+#define FFTFEM_LINE_REAL double
+#endif
 constexpr bool kLinePow2 = FFTFEM_LINE_POW2 != 0;
 
 // Length-K DFTs of the nfft buffers of a tile: Stockham for K a power of
 // two, Bluestein otherwise.
 template <typename T, bool INV, int NT, bool P2>
 __device__ __forceinline__ void line_dft(const LineArgs<T>& a, C2<T>* buf, int nfft, int ls) {
+  const int lrmax = a.lrmax ? a.lrmax : 4;
   if constexpr (P2) {
-    fft_all<T, INV, NT>(buf, nfft, a.log2K, reinterpret_cast<const C2<T>*>(a.twf), ls);
+    fft_all<T, INV, NT>(buf, nfft, a.log2K, reinterpret_cast<const C2<T>*>(a.twf), ls, lrmax);
   } else {
     bluestein<T, INV, NT>(buf, nfft, a.K, a.log2L, reinterpret_cast<const C2<T>*>(a.chirp),
-                          reinterpret_cast<const C2<T>*>(a.bhat), reinterpret_cast<const C2<T>*>(a.twl), ls);
+                          reinterpret_cast<const C2<T>*>(a.bhat), reinterpret_cast<const C2<T>*>(a.twl), ls,
+                          lrmax);
   }
 }
 
+// Body of a line pass for tile `bid` of `nblk` tiles (the launch, or one job
+// of a grouped launch).
 template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
-__global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
+__device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nblk) {
   constexpr int kNT = LineCfg<T>::NT, kMaxTPT = LineCfg<T>::TPT, kMaxCPT = LineCfg<T>::CPT;
   if (a.flag && *a.flag) return;
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NB = 1 + P;
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
   const int M = n * K - 1;
   const int ls = (a.L ? a.L : K) + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
   const int LS = NB * ls * 2;  // T slots per line
-  const int64_t l0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) << lg;
+  const int64_t l0 = (int64_t)xcd_remap(bid, nblk) << lg;
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)(K * n * n));
   const C2<T>* twf = reinterpret_cast<const C2<T>*>(a.twf);
   const C2<T>* twm = reinterpret_cast<const C2<T>*>(a.twm);
@@ -894,10 +902,24 @@ __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(
       __syncthreads();
     }
     if (tid == 0) {
-      a.partials[2 * blockIdx.x] = red[0][0];
-      a.partials[2 * blockIdx.x + 1] = red[1][0];
+      a.partials[2 * bid] = red[0][0];
+      a.partials[2 * bid + 1] = red[1][0];
     }
   }
+}
+
+template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
+__global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
+  line_body<T, NORD, MODE, UPD, LF, P2>(a, blockIdx.x, gridDim.x);
+}
+
+// Grouped launch: block b runs tile b - start[j] of job j = job_of[b].
+template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
+__global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel_grouped(
+    const LineArgs<T>* __restrict__ jobs, const int* __restrict__ job_of, const int* __restrict__ start) {
+  const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
+  const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
+  line_body<T, NORD, MODE, UPD, LF, P2>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
 }
 
 template <typename F>
@@ -930,11 +952,57 @@ static hipError_t launch_line_n(int mode, bool upd, const LineArgs<T>& a, int nb
   return upd ? go<T, NORD, MID, true>(lf, a, nblocks, lds, s) : go<T, NORD, MID, false>(lf, a, nblocks, lds, s);
 }
 
+template <typename T, int NORD, int MODE, bool UPD>
+static hipError_t go_grouped(bool lf, const GroupedLaunch<T>& g, hipStream_t s) {
+  if (lf) {
+    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, true, kLinePow2>, g.lds);
+    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, true, kLinePow2>), dim3(g.nblocks),
+                       dim3(LineCfg<T>::NT), g.lds, s, g.jobs, g.job_of, g.start);
+  } else {
+    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, false, kLinePow2>, g.lds);
+    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, false, kLinePow2>), dim3(g.nblocks),
+                       dim3(LineCfg<T>::NT), g.lds, s, g.jobs, g.job_of, g.start);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int NORD>
+static hipError_t grouped_n(int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s) {
+  if (mode == FWD) return go_grouped<T, NORD, FWD, false>(lf, g, s);
+  if (mode == INV) return upd ? go_grouped<T, NORD, INV, true>(lf, g, s) : go_grouped<T, NORD, INV, false>(lf, g, s);
+  return upd ? go_grouped<T, NORD, MID, true>(lf, g, s) : go_grouped<T, NORD, MID, false>(lf, g, s);
+}
+
 #if FFTFEM_LINE_POW2
 #define FFTFEM_LAUNCH_LINE launch_line_p2
+#define FFTFEM_LAUNCH_GROUPED launch_line_grouped_p2
 #else
 #define FFTFEM_LAUNCH_LINE launch_line_any
+#define FFTFEM_LAUNCH_GROUPED launch_line_grouped_any
 #endif
+
+template <typename T>
+hipError_t FFTFEM_LAUNCH_GROUPED(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s) {
+  switch (n) {
+#define FFTFEM_CASE(N) \
+  case N:              \
+    return grouped_n<T, N>(mode, upd, lf, g, s);
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+template hipError_t FFTFEM_LAUNCH_GROUPED<FFTFEM_LINE_REAL>(int, int, bool, bool,
+                                                            const GroupedLaunch<FFTFEM_LINE_REAL>&, hipStream_t);
 
 template <typename T>
 hipError_t FFTFEM_LAUNCH_LINE(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
@@ -958,8 +1026,7 @@ hipError_t FFTFEM_LAUNCH_LINE(int n, int mode, bool upd, const LineArgs<T>& a, i
   }
 }
 
-template hipError_t FFTFEM_LAUNCH_LINE<float>(int, int, bool, const LineArgs<float>&, int, size_t, hipStream_t);
-template hipError_t FFTFEM_LAUNCH_LINE<double>(int, int, bool, const LineArgs<double>&, int, size_t,
-                                               hipStream_t);
+template hipError_t FFTFEM_LAUNCH_LINE<FFTFEM_LINE_REAL>(int, int, bool, const LineArgs<FFTFEM_LINE_REAL>&, int,
+                                                         size_t, hipStream_t);
 
 }  // namespace fftfem

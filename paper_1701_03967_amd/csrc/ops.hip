@@ -100,7 +100,7 @@ __device__ __forceinline__ dd row_apply(const double* vh, const double* vl, int 
 // Tiles: G lines x TL positions with an n-dof halo on each side, staged in
 // LDS as separate hi and lo planes.
 template <int NORD, bool LO>
-__global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, int bid, int nblk) {
 #pragma clang fp contract(off)
   if (a.flag && *a.flag) return;
   constexpr int n = NORD;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
   }
   const int G = a.G, TL = a.TL, W = TL + 2 * n;
   const int64_t nseg = (a.M + TL - 1) / TL;
-  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t tile = xcd_remap(bid, nblk);
   const int64_t lg = tile / nseg, seg = tile - lg * nseg;
   const int64_t l0 = lg * G, s0 = seg * TL;
   const bool lines_fast = a.es > 1;
@@ -212,17 +212,39 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
   }
 }
 
+template <int NORD, bool LO>
+__global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
+  apply_body<NORD, LO>(a, blockIdx.x, gridDim.x);
+}
+
+// Grouped launch: block b runs tile b - start[j] of job j = job_of[b].
+template <int NORD, bool LO>
+__global__ __launch_bounds__(kThreads) void apply_kernel_grouped(const ApplyArgs* __restrict__ jobs,
+                                                                 const int* __restrict__ job_of,
+                                                                 const int* __restrict__ start) {
+  const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
+  const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
+  apply_body<NORD, LO>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
+}
+
 // ---------------------------------------------------------------------------
 // Refinement bookkeeping.  stats layout (doubles): [0] iterations applied,
 // [1] converged flag, [2 + i] relative correction of iteration i.
-__global__ void reset_kernel(int* flag, double* stats, int nstats) {
+__device__ __forceinline__ void reset_body(int* flag, double* stats, int nstats) {
   int i = threadIdx.x;
   if (i == 0) *flag = 0;
   for (int j = i; j < nstats; j += blockDim.x) stats[j] = 0;
 }
 
-__global__ void reduce_kernel(const double* partials, int nparts, int iter, double tol,
-                              int* flag, double* stats) {
+__global__ void reset_kernel(int* flag, double* stats, int nstats) { reset_body(flag, stats, nstats); }
+
+__global__ void reset_kernel_grouped(const ResetJob* __restrict__ jobs) {
+  const ResetJob& j = jobs[blockIdx.x];
+  reset_body(j.flag, j.stats, j.nstats);
+}
+
+__device__ __forceinline__ void reduce_body(const double* partials, int nparts, int iter, double tol, int* flag,
+                                            double* stats) {
   if (*flag) return;
   __shared__ double r0[kThreads], r1[kThreads];
   int tid = threadIdx.x;
@@ -252,16 +274,26 @@ __global__ void reduce_kernel(const double* partials, int nparts, int iter, doub
   }
 }
 
+__global__ void reduce_kernel(const double* partials, int nparts, int iter, double tol, int* flag,
+                              double* stats) {
+  reduce_body(partials, nparts, iter, tol, flag, stats);
+}
+
+__global__ void reduce_kernel_grouped(const ReduceJob* __restrict__ jobs) {
+  const ReduceJob& j = jobs[blockIdx.x];
+  reduce_body(j.partials, j.nparts, j.iter, j.tol, j.flag, j.stats);
+}
+
 // ---------------------------------------------------------------------------
 // Out-of-place transpose of a batch of R x C matrices: out[b][c][r] = in[b][r][c].
 // 64 x 64 tiles through LDS (one padding column against bank conflicts);
 // every global access is a contiguous 256-thread segment.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                             int64_t R, int64_t C, int64_t ntr, int64_t ntc) {
+__device__ __forceinline__ void transpose_body(const T* __restrict__ in, T* __restrict__ out, int64_t R,
+                                               int64_t C, int64_t ntr, int64_t ntc, int blk, int nblk) {
   constexpr int TS = 64;
   __shared__ T tile[TS][TS + 1];
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t bid = xcd_remap(blk, nblk);
   const int64_t per = ntr * ntc;
   const int64_t b = bid / per;
   const int64_t rem = bid - b * per;
@@ -281,6 +313,68 @@ __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict
     int64_t c = c0 + ty + i, r = r0 + tx;
     if (r < R && c < C) dst[c * R + r] = tile[tx][ty + i];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                             int64_t R, int64_t C, int64_t ntr, int64_t ntc) {
+  transpose_body<T>(in, out, R, C, ntr, ntc, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void transpose_kernel_grouped(const TransposeJob* __restrict__ jobs,
+                                                                     const int* __restrict__ job_of,
+                                                                     const int* __restrict__ start) {
+  const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
+  const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
+  const TransposeJob& t = jobs[j];
+  transpose_body<T>((const T*)t.in, (T*)t.out, t.R, t.C, t.ntr, t.ntc, (int)blockIdx.x - b0, b1 - b0);
+}
+
+template <typename T>
+hipError_t launch_transpose_grouped(const GroupedOps& g, hipStream_t s) {
+  hipLaunchKernelGGL((transpose_kernel_grouped<T>), dim3(g.nblocks), dim3(kThreads), 0, s,
+                     (const TransposeJob*)g.jobs, g.job_of, g.start);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose_grouped<float>(const GroupedOps&, hipStream_t);
+template hipError_t launch_transpose_grouped<double>(const GroupedOps&, hipStream_t);
+
+hipError_t launch_apply_grouped(int n, bool lo, const GroupedOps& g, hipStream_t s) {
+  const ApplyArgs* jobs = (const ApplyArgs*)g.jobs;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                                 \
+  case N:                                                                                              \
+    if (lo)                                                                                            \
+      hipLaunchKernelGGL((apply_kernel_grouped<N, true>), dim3(g.nblocks), dim3(kThreads), g.lds, s, jobs, \
+                         g.job_of, g.start);                                                           \
+    else                                                                                               \
+      hipLaunchKernelGGL((apply_kernel_grouped<N, false>), dim3(g.nblocks), dim3(kThreads), g.lds, s,     \
+                         jobs, g.job_of, g.start);                                                     \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reset_grouped(const ResetJob* jobs, int njobs, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel_grouped, dim3(njobs), dim3(64), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_grouped(const ReduceJob* jobs, int njobs, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel_grouped, dim3(njobs), dim3(kThreads), 0, s, jobs);
+  return hipGetLastError();
 }
 
 template <typename T>

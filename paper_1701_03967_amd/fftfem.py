@@ -28,7 +28,10 @@ EXPORTS = [
     "fftfem_workspace_bytes", "fftfem_destroy", "fftfem_status_string", "fftfem_plan_tables",
     "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
     "fftfem_set_timing", "fftfem_get_timing",
+    "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
+    "fftfem_destroy_batch",
 ]
+BATCH_TUNE = 1
 
 
 class FftfemError(RuntimeError):
@@ -94,6 +97,13 @@ def lib():
         L.fftfem_set_timing.argtypes = [vp, ctypes.c_int]
         L.fftfem_get_timing.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, dp,
                                         ctypes.POINTER(ctypes.c_int)]
+        L.fftfem_plan_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(Desc), ctypes.c_int]
+        L.fftfem_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.fftfem_batch_get_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.fftfem_batch_workspace_bytes.argtypes = [vp]
+        L.fftfem_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.fftfem_destroy_batch.argtypes = [vp]
+        L.fftfem_destroy_batch.restype = None
         _lib = L
     return _lib
 
@@ -133,6 +143,85 @@ def _stream_ptr(stream):
 
 def _tptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(K: Sequence[int], n: int, diff: Sequence[float], react: float = 0.0,
+              X: Optional[Sequence[float]] = None, precision: str = "fp64", max_iter: int = 0,
+              tol: float = 0.0, nrhs: int = 1) -> "Desc":
+    d = Desc()
+    d.N = len(K)
+    for i, k in enumerate(K):
+        d.K[i] = int(k)
+        d.diff[i] = float(diff[i])
+        d.X[i] = float(X[i]) if X is not None else 0.0
+    d.n = int(n)
+    d.react = float(react)
+    d.precision = PRECISIONS[precision]
+    d.max_iter = int(max_iter)
+    d.tol = float(tol)
+    d.nrhs = int(nrhs)
+    return d
+
+
+def _stats_dict(s):
+    return {"iterations": s.iterations, "converged": bool(s.converged),
+            "rel_correction": list(s.rel_correction)[:max(1, s.iterations + 1)]}
+
+
+class Batch:
+    """Independent problems solved together (one graph launch per solve).
+
+    problems: sequence of dicts with the Plan arguments (K, n, diff, react,
+    precision, max_iter, tol, nrhs).  tune: measure line-pass parameters on
+    the first solve.
+    """
+
+    def __init__(self, problems, tune: bool = False):
+        descs = (Desc * len(problems))()
+        self.shapes = []
+        for i, pr in enumerate(problems):
+            descs[i] = make_desc(**pr)
+            nrhs = int(pr.get("nrhs", 1))
+            shape = tuple(int(pr["n"]) * int(k) - 1 for k in pr["K"])
+            self.shapes.append(((nrhs,) if nrhs > 1 else ()) + shape)
+        h = ctypes.c_void_p()
+        _check(lib().fftfem_plan_batch(ctypes.byref(h), len(problems), descs, BATCH_TUNE if tune else 0),
+               "fftfem_plan_batch")
+        self._h = h
+        self.count = len(problems)
+
+    def close(self):
+        if self._h:
+            lib().fftfem_destroy_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, fs, us, stream=None):
+        """fs, us: lists of contiguous float64 device tensors (problem shapes)."""
+        import torch
+        if len(fs) != self.count or len(us) != self.count:
+            raise ValueError("one f and one u tensor per problem")
+        for t, shp in zip(list(fs) + list(us), self.shapes * 2):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.is_contiguous() and tuple(t.shape) == shp):
+                raise ValueError(f"expected a contiguous float64 device tensor of shape {shp}")
+        fp = (ctypes.c_void_p * self.count)(*[t.data_ptr() for t in fs])
+        up = (ctypes.c_void_p * self.count)(*[t.data_ptr() for t in us])
+        _check(lib().fftfem_solve_batch(self._h, fp, up, _stream_ptr(stream)), "fftfem_solve_batch")
+        return us
+
+    def stats(self, i: int):
+        s = Stats()
+        _check(lib().fftfem_batch_get_stats(self._h, int(i), ctypes.byref(s)), "fftfem_batch_get_stats")
+        return _stats_dict(s)
+
+    def workspace_bytes(self) -> int:
+        return int(lib().fftfem_batch_workspace_bytes(self._h))
 
 
 class Plan:

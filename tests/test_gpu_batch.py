@@ -1,0 +1,113 @@
+"""GPU parity of batched solves (independent problems of uneven sizes, orders
+and right-hand-side counts in one graph launch) against the oracle and
+against single-plan solves of the same problems."""
+import numpy as np
+import pytest
+
+from oracle import solve as osolve
+from paper_1701_03967_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1701_03967_amd import fftfem
+    fftfem.lib()
+    return fftfem
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def small_batch(count=12, seed=11, precision="fp32_refine"):
+    """A seeded batch drawn like the heat-step workload but small enough for
+    the dense oracle: n in 2..8, K per axis in 3..40 (powers of two and
+    not), diff in [0.5, 2], react = 1/tau, 1..4 right-hand sides."""
+    draw = inputs.draw_batch(count=count, seed=seed, n_range=(2, 8), k_range=(3, 40), nrhs_range=(1, 4))
+    probs = []
+    for p in draw.problems:
+        probs.append(dict(K=p.K, n=p.n, diff=p.diff, react=p.react, precision=precision,
+                          max_iter=4, tol=1e-13, nrhs=p.nrhs))
+    return draw, probs
+
+
+def rhs_tensors(draw):
+    fs = []
+    for i, p in enumerate(draw.problems):
+        f = inputs.batch_rhs(draw, i)
+        if p.nrhs == 1:
+            f = f[0]
+        fs.append(torch.from_numpy(np.ascontiguousarray(f)).cuda())
+    return fs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_refine", 1e-10), ("fp64", 1e-11)])
+def test_batch_vs_oracle_and_single(fm, precision, tol):
+    draw, probs = small_batch(precision=precision)
+    say("batch", precision, [(p["n"], p["K"], p["nrhs"]) for p in probs])
+    fs = rhs_tensors(draw)
+    us = [torch.empty_like(f) for f in fs]
+    b = fm.Batch(probs)
+    b.solve(fs, us)
+    torch.cuda.synchronize()
+    for i, (pr, f, u) in enumerate(zip(probs, fs, us)):
+        fh = f.cpu().numpy().reshape((pr["nrhs"],) + tuple(pr["n"] * k - 1 for k in pr["K"]))
+        uh = u.cpu().numpy().reshape(fh.shape)
+        for r in range(pr["nrhs"]):
+            ref = osolve.solve(fh[r], pr["n"], pr["K"], pr["diff"], pr["react"])
+            e = rel(uh[r], ref)
+            assert e < tol, (i, r, e)
+        # the grouped launches run the single-plan kernels with the same tiles
+        p1 = fm.Plan(**pr)
+        u1 = p1.solve(f)
+        torch.cuda.synchronize()
+        assert torch.equal(u1, u), i
+        if precision == "fp32_refine":
+            st = b.stats(i)
+            assert st["converged"], (i, st)
+
+
+def test_batch_replay_and_new_pointers(fm):
+    draw, probs = small_batch(count=8, seed=12)
+    fs = rhs_tensors(draw)
+    us = [torch.empty_like(f) for f in fs]
+    b = fm.Batch(probs)
+    b.solve(fs, us)
+    first = [u.clone() for u in us]
+    for u in us:
+        u.fill_(float("nan"))
+    b.solve(fs, us)  # graph replay
+    torch.cuda.synchronize()
+    for a, c in zip(first, us):
+        assert torch.equal(a, c)
+    us2 = [torch.empty_like(f) for f in fs]  # new pointers: recorded again
+    fs2 = [2.0 * f for f in fs]
+    b.solve(fs2, us2)
+    torch.cuda.synchronize()
+    for a, c in zip(first, us2):
+        assert rel(c.cpu().numpy(), 2.0 * a.cpu().numpy()) < 1e-12
+
+
+def test_batch_tuned(fm):
+    draw, probs = small_batch(count=10, seed=13)
+    say("tuned batch", [(p["n"], p["K"], p["nrhs"]) for p in probs])
+    fs = rhs_tensors(draw)
+    us = [torch.empty_like(f) for f in fs]
+    b = fm.Batch(probs, tune=True)
+    b.solve(fs, us)
+    torch.cuda.synchronize()
+    for i, (pr, f, u) in enumerate(zip(probs, fs, us)):
+        fh = f.cpu().numpy().reshape((pr["nrhs"],) + tuple(pr["n"] * k - 1 for k in pr["K"]))
+        uh = u.cpu().numpy().reshape(fh.shape)
+        for r in range(pr["nrhs"]):
+            ref = osolve.solve(fh[r], pr["n"], pr["K"], pr["diff"], pr["react"])
+            assert rel(uh[r], ref) < 1e-10, (i, r)
