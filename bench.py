@@ -70,7 +70,7 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def profiler_kernel_name(name: str, n: int, N: int) -> str:
+def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     """Symbol of the line kernel that a per-pass timing name refers to."""
     head = name.split("_ax")[0]
     dtype = "double" if head.endswith("64") else "float"
@@ -78,7 +78,8 @@ def profiler_kernel_name(name: str, n: int, N: int) -> str:
     upd = "true" if "upd" in head else "false"
     ax = name.rsplit("_ax", 1)[1]
     contiguous = ax.endswith("t") or int(ax.rstrip("t")) == N - 1
-    return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}>"
+    pow2 = "true" if K & (K - 1) == 0 else "false"
+    return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}, {pow2}>"
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -187,6 +188,70 @@ def cpu_baseline(prob, budget_s: float = 20.0):
             "seconds_per_solve": total}
 
 
+def run_batch(args, torch, fm):
+    """The batched heat-step workload: 512 independent 2D problems (n in 2..8,
+    K per axis in 32..512, diff in [0.5, 2], react = 1/tau = 1000, 1..8
+    right-hand sides), float32 transforms with float64 refinement, solved
+    in one graph launch; line-pass parameters tuned on the first solve.
+    Right-hand sides: N(0,1), drawn on the device per problem from a seeded
+    generator (the problem parameters come from the seeded workload draw)."""
+    draw = inputs.draw_batch(count=args.batch_count)
+    probs = [dict(K=p.K, n=p.n, diff=p.diff, react=p.react, precision="fp32_refine",
+                  max_iter=args.batch_iters, tol=1e-12, nrhs=p.nrhs) for p in draw.problems]
+    total = sum(p.nrhs * p.size for p in draw.problems)
+    t0 = time.perf_counter()
+    b = fm.Batch(probs, tune=not args.no_tune)
+    t_plan = time.perf_counter() - t0
+    fs, us = [], []
+    for i, p in enumerate(draw.problems):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(draw.seeds[i])
+        shape = ((p.nrhs,) if p.nrhs > 1 else ()) + p.shape
+        fs.append(torch.randn(shape, generator=g, dtype=torch.float64, device="cuda"))
+        us.append(torch.empty_like(fs[-1]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.solve(fs, us)  # records, tunes, captures the graph, then runs it
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    print(f"[bench] batch: {len(probs)} problems, {total} unknowns, plan {t_plan:.1f}s, "
+          f"first solve (record + tune + capture) {t_first:.1f}s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        b.solve(fs, us)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        b.solve(fs, us)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    its = [b.stats(i)["iterations"] for i in range(len(probs))]
+    conv = sum(b.stats(i)["converged"] for i in range(len(probs)))
+    line = {
+        "metric": "batched solve: unknowns/s over all problems and right-hand sides",
+        "value": total / (ms * 1e-3),
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"c5_batch_{len(probs)}_2d_heat_step", "problems": len(probs),
+                   "unknowns": total, "react": draw.problems[0].react, "precision": "fp32_refine",
+                   "max_iter": args.batch_iters, "tuned": not args.no_tune},
+        "plan_s": t_plan, "first_solve_s": t_first,
+        "refinement": {"iterations_min": min(its), "iterations_max": max(its), "converged": conv},
+        "workspace_bytes": b.workspace_bytes(),
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +261,9 @@ def main():
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,fp32,fp32_refine")
+    ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
+    ap.add_argument("--batch-iters", type=int, default=3, help="c5_batch: refinement steps")
+    ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
     args = ap.parse_args()
@@ -207,6 +275,9 @@ def main():
     fm.lib()
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration)
+    if args.workload == "c5_batch":
+        run_batch(args, torch, fm)
+        return
 
     def run(name, full):
         w = inputs.WORKLOADS[name]
@@ -250,7 +321,8 @@ def main():
         by = kernel_bytes(name, prob.size, prob.N)
         if by > 0:
             gbs = by / (avg_ms * 1e-3) / 1e9
-            kname = profiler_kernel_name(name, prob.n, prob.N)
+            ax = int(name.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in name else 0
+            kname = profiler_kernel_name(name, prob.n, prob.N, prob.K[ax])
             traffic = measured_traffic(args.workload, kname)
             roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,

@@ -111,3 +111,45 @@ def test_batch_tuned(fm):
         for r in range(pr["nrhs"]):
             ref = osolve.solve(fh[r], pr["n"], pr["K"], pr["diff"], pr["react"])
             assert rel(uh[r], ref) < 1e-10, (i, r)
+
+
+def test_c5_full_batch_sampled(fm):
+    """The full batched heat-step workload (512 problems, 5.2e9 unknowns over
+    all right-hand sides) in the launch configuration of the benchmark
+    (float32 + refinement, tuned).  The oracle solves every problem of the
+    draw whose element counts are both <= 128 (its first two right-hand
+    sides, drawn by the seeded host generator); every problem must report
+    convergence."""
+    draw = inputs.draw_batch()
+    probs = [dict(K=p.K, n=p.n, diff=p.diff, react=p.react, precision="fp32_refine", max_iter=3,
+                  tol=1e-12, nrhs=p.nrhs) for p in draw.problems]
+    sample = [i for i, p in enumerate(draw.problems) if max(p.K) <= 128]
+    say("c5 full batch, oracle sample", [(i, draw.problems[i].n, draw.problems[i].K) for i in sample])
+    assert len(sample) >= 3
+    fs, us, host = [], [], {}
+    for i, p in enumerate(draw.problems):
+        shape = ((p.nrhs,) if p.nrhs > 1 else ()) + p.shape
+        if i in sample:
+            fh = inputs.batch_rhs(draw, i)
+            host[i] = fh
+            fs.append(torch.from_numpy(np.ascontiguousarray(fh.reshape(shape))).cuda())
+        else:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(draw.seeds[i])
+            fs.append(torch.randn(shape, generator=g, dtype=torch.float64, device="cuda"))
+        us.append(torch.empty_like(fs[-1]))
+    b = fm.Batch(probs, tune=True)
+    b.solve(fs, us)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        assert b.stats(i)["converged"], i
+    for i in sample:
+        p = draw.problems[i]
+        uh = us[i].cpu().numpy().reshape((p.nrhs,) + p.shape)
+        for r in range(min(p.nrhs, 2)):
+            ref = osolve.solve(host[i][r], p.n, p.K, p.diff, p.react)
+            e = rel(uh[r], ref)
+            say("  problem", i, "rhs", r, e)
+            assert e < 1e-10, (i, r, e)
+    del fs, us, b
+    torch.cuda.empty_cache()
