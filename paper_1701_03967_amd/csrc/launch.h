@@ -18,6 +18,8 @@ struct LineArgs {
   int out_kind;           // 0: T, 1: double, 2: float
   int K, log2K;
   int64_t M, es, nlines;
+  int64_t ies, oes;       // contiguous tiles only: nonzero = element stride of a
+                          // transposed input / output (element i of line l at l + i ies)
   int G, log2G;           // lines per tile (a power of two)
   int lrmax;              // log2 of the largest FFT radix (4, 3 or 2; 0: 4)
   const T* Q;             // K blocks of n*n

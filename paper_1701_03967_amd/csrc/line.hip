@@ -434,6 +434,28 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         }
       }
     } else {
+      // ies != 0: element i of line l at l + i ies (a transposed layout)
+      if (a.ies) {
+        for (int g = 0; g < G; ++g) {
+          const int64_t line = l0 + g;
+          if (line >= a.nlines) break;
+          T* dst = raw + g * LS;
+          for (int i0 = tid; i0 < M; i0 += 4 * kNT) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int i = i0 + u * kNT;
+              v[u] = i < M ? load_in<T>(src, f64, line + (int64_t)i * a.ies) : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int i = i0 + u * kNT;
+              if (i < M) dst[i] = v[u];
+            }
+          }
+        }
+        return;
+      }
       for (int g = 0; g < G; ++g) {
         const int64_t line = l0 + g;
         if (line >= a.nlines) break;
@@ -477,6 +499,16 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         for (int i = tid >> lg; i < M; i += step) put(base + (int64_t)i * a.es, srcl[i]);
       }
     } else {
+      // oes != 0: element i of line l to l + i oes (a transposed layout)
+      if (a.oes) {
+        for (int g = 0; g < G; ++g) {
+          const int64_t line = l0 + g;
+          if (line >= a.nlines) break;
+          const T* srcl = raw + g * LS;
+          for (int i = tid; i < M; i += kNT) put(line + (int64_t)i * a.oes, srcl[i]);
+        }
+        return;
+      }
       for (int g = 0; g < G; ++g) {
         const int64_t line = l0 + g;
         if (line >= a.nlines) break;
