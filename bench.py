@@ -116,9 +116,11 @@ def copy_calibration(torch, nbytes: int):
     del a, b
 
 
-def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True):
+def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=False):
     plan = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=precision,
                    max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12)
+    if tune and prob.N == 2:
+        plan.tune()  # measured line-pass parameters, before the untimed warm-up
     u = torch.empty_like(f)
     for _ in range(warmup):
         plan.solve(f, u)
@@ -264,6 +266,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
     ap.add_argument("--batch-iters", type=int, default=3, help="c5_batch: refinement steps")
     ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
+    ap.add_argument("--tune", action="store_true", help="2D workloads: measure line-pass parameters first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
     args = ap.parse_args()
@@ -290,7 +293,7 @@ def main():
         kts = {}
         for mode in args.modes.split(","):
             steps = args.steps if full else max(5, args.steps // 3)
-            plan, u, ms, kt, st = time_mode(fm, torch, prob, f, mode, steps, args.warmup)
+            plan, u, ms, kt, st = time_mode(fm, torch, prob, f, mode, steps, args.warmup, tune=args.tune)
             sols[mode] = u.clone()
             kts[mode] = kt
             rec = {"ms": ms, "unknowns_per_s": prob.size / (ms * 1e-3)}
@@ -344,7 +347,7 @@ def main():
         "config": {"workload": args.workload, "N": prob.N, "n": prob.n, "K": list(prob.K),
                    "diff": list(prob.diff), "react": prob.react, "unknowns": prob.size,
                    "mode": best_mode, "rhs": inputs.WORKLOADS[args.workload].rhs,
-                   "seed": inputs.WORKLOADS[args.workload].seed},
+                   "seed": inputs.WORKLOADS[args.workload].seed, "tuned": bool(args.tune)},
         "modes": {m: res[m] for m in res if m != "unknowns"},
         "roofline": roof,
     }

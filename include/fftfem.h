@@ -174,7 +174,7 @@ int fftfem_get_timing(fftfem_plan_t p, int max, char* names, double* avg_ms, int
  * axes are computed once per axis length within a plan; every plan owns its
  * device tables and workspace).  flags: FFTFEM_BATCH_TUNE measures, on the
  * first solve, the lines per tile and the largest FFT radix of every
- * float32 two-dimensional line pass kind in the batch (kept process-wide for
+ * two-dimensional line pass kind in the batch (kept process-wide for
  * later plans of the same kind).  EINVAL for count < 1 or a null pointer;
  * otherwise the status of the first descriptor that fails fftfem_plan_ex.
  *
@@ -197,6 +197,18 @@ int fftfem_solve_batch(fftfem_batch_t b, const double* const* f, double* const* 
 int fftfem_batch_get_stats(fftfem_batch_t b, int i, fftfem_stats* out);
 size_t fftfem_batch_workspace_bytes(const fftfem_batch_t b);
 void fftfem_destroy_batch(fftfem_batch_t b);
+
+/*
+ * fftfem_tune: the measurement FFTFEM_BATCH_TUNE makes, for the line passes
+ * of one two-dimensional plan (float32, float32 with refinement or float64):
+ * each pass (forward along the last axis, the middle pass, inverse) is timed
+ * on the plan's own scratch, in the layout its solve uses, for every
+ * admissible lines per tile and largest FFT radix (16, 8, 4); the fastest
+ * is kept process-wide and used by every later solve of plans of that kind.
+ * Synchronizes s.  ENOTIMPL for plans that are not two-dimensional, EINVAL
+ * for a null plan, EHIP on a runtime error.
+ */
+int fftfem_tune(fftfem_plan_t p, hipStream_t s);
 
 /*
  * Host-only access to the plan arithmetic, for tests on machines without a

@@ -574,11 +574,15 @@ int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* wor
   return line_pass<T>(p, natural_geom(p, N - 1, true), INV, work, 0, out, 1, upd, flag, s, partials);
 }
 
-// Geometry of the tuner's passes (float32 2D plans): 0 forward along axis 1,
-// 1 the middle pass along axis 0 (on the transposed copy when the solve
-// uses one), 2 inverse along axis 1.
+// Geometry of the tuner's passes (2D plans), as the solve runs them: 0
+// forward along axis 1, 1 the middle pass along axis 0 (on the transposed
+// copy when the solve uses one), 2 inverse along axis 1.
 Geom tune_geom(fftfem_plan_t p, int pass) {
-  if (pass != 1) return natural_geom(p, p->N - 1, true);
+  if (pass != 1) {
+    Geom g = natural_geom(p, p->N - 1, true);
+    if (pass == 0 && p->trfused) g.oes = p->M[0];
+    return g;
+  }
   if (!p->tr2d) return natural_geom(p, 0, true);
   Geom g;
   g.axis = 0;
@@ -589,6 +593,7 @@ Geom tune_geom(fftfem_plan_t p, int pass) {
   g.oaxis[0] = 1;
   g.so[0] = p->M[0];
   g.Mo[0] = p->M[1];
+  if (p->trfused) g.oes = p->M[1];
   return g;
 }
 
@@ -947,16 +952,17 @@ namespace fftfem {
 
 int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info) {
   if (!p || !info || pass < 0 || pass > 2) return FFTFEM_EINVAL;
-  if (p->N != 2 || p->desc.precision == FFTFEM_FP64) return FFTFEM_ENOTIMPL;
+  if (p->N != 2) return FFTFEM_ENOTIMPL;
   const Geom g = tune_geom(p, pass);
   const int64_t K = p->K[g.axis];
+  info->elt = p->desc.precision == FFTFEM_FP64 ? (int)sizeof(double) : (int)sizeof(float);
   info->n = p->n;
   info->mode = pass == 0 ? FWD : (pass == 1 ? MID : INV);
   info->lf = g.es > 1 ? 1 : 0;
   info->K = K;
   int G = 1;
   while (G < 64 && 2 * G * K <= kLineTasks && 2 * G <= g.nlines &&
-         (size_t)(2 * G) * line_lds(p, K, sizeof(float)) <= (size_t)p->lds_max)
+         (size_t)(2 * G) * line_lds(p, K, info->elt) <= (size_t)p->lds_max)
     G *= 2;
   info->Gmax = G;
   return FFTFEM_OK;
@@ -968,7 +974,16 @@ int plan_time_pass(fftfem_plan_t p, int pass, int G, int lrmax, int reps, hipStr
   if (rc) return rc;
   if (G < 1 || G > info.Gmax || (G & (G - 1)) || lrmax < 2 || lrmax > 4 || reps < 1) return FFTFEM_EINVAL;
   const Geom g = tune_geom(p, pass);
+  // data for the timing runs: the plan's own scratch (float32 workspace; the
+  // first two double-double planes for float64 plans), contents irrelevant
+  const bool f64 = info.elt == (int)sizeof(double);
   float* buf = (pass == 1 && p->tr2d) ? p->W32b : p->W32;
+  double* din = p->tmp[0];
+  double* dout = p->tmp[1];
+  auto run = [&]() {
+    return f64 ? line_pass<double>(p, g, info.mode, din, 1, dout, 0, nullptr, nullptr, s, false)
+               : line_pass<float>(p, g, info.mode, buf, 0, buf, 0, nullptr, nullptr, s, false);
+  };
   hipEvent_t a = nullptr, b = nullptr;
   if ((rc = from_hip(hipEventCreate(&a)))) return rc;
   if ((rc = from_hip(hipEventCreate(&b)))) {
@@ -979,10 +994,9 @@ int plan_time_pass(fftfem_plan_t p, int pass, int G, int lrmax, int reps, hipStr
   p->lrforce = lrmax;
   Recorder* saved = p->rec;
   p->rec = nullptr;
-  rc = line_pass<float>(p, g, info.mode, buf, 0, buf, 0, nullptr, nullptr, s, false);  // warm-up
+  rc = run();  // warm-up
   if (!rc) rc = from_hip(hipEventRecord(a, s));
-  for (int i = 0; i < reps && !rc; ++i)
-    rc = line_pass<float>(p, g, info.mode, buf, 0, buf, 0, nullptr, nullptr, s, false);
+  for (int i = 0; i < reps && !rc; ++i) rc = run();
   if (!rc) rc = from_hip(hipEventRecord(b, s));
   if (!rc) rc = from_hip(hipEventSynchronize(b));
   if (!rc) rc = from_hip(hipEventElapsedTime(ms, a, b));

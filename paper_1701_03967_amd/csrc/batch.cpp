@@ -64,22 +64,22 @@ struct Group {
   size_t lds = 0;
 };
 
-// Measures, for every float32 2D line-pass kind of the batch (n, mode,
+// Measures, for every 2D line-pass kind of the plans (precision, n, mode,
 // strided or not, element-count class), the candidate lines per tile and
-// largest FFT radixes on the problem of that kind with the most lines, and
-// keeps the fastest (process-wide).
-int tune_batch(fftfem_batch_s* b, hipStream_t s) {
+// largest FFT radixes on the plan of that kind with the most data, and keeps
+// the fastest (process-wide).
+int tune_plans(const std::vector<fftfem_plan_t>& plans, hipStream_t s) {
   struct Cand {
     fftfem_plan_t p;
     int pass;
     int64_t lines;
   };
-  std::map<std::tuple<int, int, int, int64_t>, Cand> kinds;
-  for (fftfem_plan_t p : b->plans) {
+  std::map<std::tuple<int, int, int, int, int64_t>, Cand> kinds;
+  for (fftfem_plan_t p : plans) {
     for (int pass = 0; pass < 3; ++pass) {
       PassInfo info;
       if (plan_pass_info(p, pass, &info) != FFTFEM_OK) continue;
-      const auto key = std::make_tuple(info.n, info.mode, info.lf, tune_class(info.K));
+      const auto key = std::make_tuple(info.elt, info.n, info.mode, info.lf, tune_class(info.K));
       const int64_t lines = (int64_t)fftfem_workspace_bytes(p);  // proxy for the problem size
       auto it = kinds.find(key);
       if (it == kinds.end() || it->second.lines < lines) kinds[key] = Cand{p, pass, lines};
@@ -93,7 +93,7 @@ int tune_batch(fftfem_batch_s* b, hipStream_t s) {
     float best = 0;
     TuneVal bv{0, 4};
     for (int G = 1; G <= info.Gmax; G *= 2)
-      for (int lr = 4; lr >= 3; --lr) {
+      for (int lr = 4; lr >= 2; --lr) {
         float ms = 0;
         rc = plan_time_pass(c.p, c.pass, G, lr, 3, s, &ms);
         if (rc) return rc;
@@ -102,7 +102,7 @@ int tune_batch(fftfem_batch_s* b, hipStream_t s) {
           bv = TuneVal{G, lr};
         }
       }
-    tune_set(TuneKey{(int)sizeof(float), info.n, info.mode, info.lf, tune_class(info.K)}, bv);
+    tune_set(TuneKey{info.elt, info.n, info.mode, info.lf, tune_class(info.K)}, bv);
   }
   return FFTFEM_OK;
 }
@@ -111,7 +111,7 @@ int build_graph(fftfem_batch_s* b, const double* const* f, double* const* u, hip
   release_graph(b);
   int rc;
   if (b->flags & FFTFEM_BATCH_TUNE && !b->tuned) {
-    if ((rc = tune_batch(b, s))) return rc;
+    if ((rc = tune_plans(b->plans, s))) return rc;
     b->tuned = true;
   }
   // record every problem's schedule
@@ -287,6 +287,14 @@ int fftfem_solve_batch(fftfem_batch_t b, const double* const* f, double* const* 
   b->last = s;
   for (fftfem_plan_t p : b->plans) plan_set_stream(p, s);
   return hip_rc(hipGraphLaunch(b->exec, s));
+}
+
+int fftfem_tune(fftfem_plan_t p, hipStream_t s) {
+  if (!p) return FFTFEM_EINVAL;
+  PassInfo info;
+  int rc = plan_pass_info(p, 0, &info);
+  if (rc) return rc;
+  return tune_plans(std::vector<fftfem_plan_t>{p}, s);
 }
 
 int fftfem_batch_get_stats(fftfem_batch_t b, int i, fftfem_stats* out) {

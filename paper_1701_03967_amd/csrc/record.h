@@ -74,10 +74,11 @@ void tune_set(const TuneKey& k, const TuneVal& v);
 bool tune_get(const TuneKey& k, TuneVal* v);
 
 // Candidate line-pass parameters for the tuner and a timing run of one pass
-// of plan p (on its own float32 workspace; float32 plans only).  pass: 0
+// of plan p (on its own scratch; 2D plans only).  pass: 0
 // forward along the last axis, 1 the middle pass along axis 0 (in the
 // layout the solve uses), 2 inverse along the last axis.
 struct PassInfo {
+  int elt;  // bytes per value of the pass (4 or 8)
   int n, mode, lf;
   int64_t K;
   int Gmax;  // largest admissible lines per tile

@@ -29,7 +29,7 @@ EXPORTS = [
     "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
-    "fftfem_destroy_batch",
+    "fftfem_destroy_batch", "fftfem_tune",
 ]
 BATCH_TUNE = 1
 
@@ -104,6 +104,7 @@ def lib():
         L.fftfem_batch_workspace_bytes.restype = ctypes.c_size_t
         L.fftfem_destroy_batch.argtypes = [vp]
         L.fftfem_destroy_batch.restype = None
+        L.fftfem_tune.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -289,6 +290,11 @@ class Plan:
         self._check_tensor(y, "y")
         _check(lib().fftfem_apply_A(self._h, _tptr(u), _tptr(y), _stream_ptr(stream)), "fftfem_apply_A")
         return y
+
+    def tune(self, stream=None):
+        """Measures this plan's line-pass parameters (2D plans; the choice is
+        kept process-wide for plans of the same kind)."""
+        _check(lib().fftfem_tune(self._h, _stream_ptr(stream)), "fftfem_tune")
 
     def stats(self):
         s = Stats()

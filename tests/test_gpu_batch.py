@@ -153,3 +153,21 @@ def test_c5_full_batch_sampled(fm):
             assert e < 1e-10, (i, r, e)
     del fs, us, b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_refine", 1e-10), ("fp32", 1e-5)])
+def test_plan_tune(fm, precision, tol):
+    """A single 2D plan tuned by measurement (every admissible lines per
+    tile and largest FFT radix of its three line passes, in the layout its
+    solve uses) still solves to the oracle's accuracy."""
+    K, n = (40, 64), 5
+    diff, react = (1.3, 0.7), 0.25
+    f = inputs.draw_rhs((n * K[0] - 1, n * K[1] - 1), seed=21)
+    ref = osolve.solve(f, n, K, diff, react)
+    say("tune", precision, K, n)
+    p = fm.Plan(K, n, diff, react, precision=precision,
+                max_iter=4 if precision == "fp32_refine" else 0, tol=1e-13)
+    p.tune()
+    u = p.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert rel(u.cpu().numpy(), ref) < tol
