@@ -22,9 +22,10 @@ using namespace fftfem;
 
 namespace {
 
-// Per-axis device tables: Q, twf, twm, twd, mu, and for K not a power of
-// two the Bluestein chirp, bhat and twl (null otherwise).
-constexpr int kNumTables = 8;
+// Per-axis device tables: Q, twf, twm, twd, mu, for K not a power of two
+// the Bluestein chirp, bhat and twl (null otherwise), and the condensed
+// per-frequency solve's constants.
+constexpr int kNumTables = 9;
 struct DevTables {
   double* d[kNumTables] = {};
   float* f[kNumTables] = {};
@@ -350,6 +351,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.chirp = tab<T>(p, gm.axis, 5);
   a.bhat = tab<T>(p, gm.axis, 6);
   a.twl = tab<T>(p, gm.axis, 7);
+  a.arrow = tab<T>(p, gm.axis, 8);
   a.react = (T)p->desc.react;
   a.nother = gm.nother;
   for (int e = 0; e < gm.nother; ++e) {
@@ -714,7 +716,15 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
       for (int c = 0; c < d.n; ++c)
         for (int l = 0; l < d.n; ++l)
           qs[(size_t)(c * d.n + l) * t.K + k] = t.Q[(size_t)k * d.n * d.n + c * d.n + l];
-    const std::vector<double>* src[kNumTables] = {&qs, &t.twf, &t.twm, &t.twd, &mu, &t.chirp, &t.bhat, &t.twl};
+    // condensed-solve constants with the stiffness parts scaled like mu
+    std::vector<double> arrow = t.arrow;
+    const ArrowLayout al(d.n);
+    for (int m = 0; m < al.nb; ++m) {
+      arrow[al.nu + m] *= p->coef[i];
+      arrow[al.gA + m] *= p->coef[i];
+    }
+    const std::vector<double>* src[kNumTables] = {&qs,     &t.twf,  &t.twm, &t.twd, &mu,
+                                                  &t.chirp, &t.bhat, &t.twl, &arrow};
     for (int w = 0; w < kNumTables && !rc; ++w) {
       if (src[w]->empty()) continue;
       rc = upload<double>(p, &p->dev[i].d[w], *src[w]);

@@ -37,6 +37,17 @@ struct AxisTables {
   std::vector<double> chirp;  // K complex: exp(-i pi j^2 / K)
   std::vector<double> bhat;   // L complex: DFT_L of the conjugate chirp, / L
   std::vector<double> twl;    // L complex: exp(-2 pi i q / L)
+  // condensed per-frequency solve of the fused middle pass (layout in
+  // condensed_tables): ne^2 + no^2 + 3 (n - 1) + 2 values, unscaled
+  std::vector<double> arrow;
+};
+
+// Offsets into AxisTables::arrow for order n.
+struct ArrowLayout {
+  int ne, no, nb, We, Wo, nu, gA, gC, cc, size;
+  explicit ArrowLayout(int n)
+      : ne(n / 2), no((n - 1) / 2), nb(n - 1), We(0), Wo(ne * ne), nu(Wo + no * no), gA(nu + nb),
+        gC(gA + nb), cc(gC + nb), size(cc + 2) {}
 };
 
 // Builds the tables of one axis.  Returns 0 or a negative FFTFEM_* status.

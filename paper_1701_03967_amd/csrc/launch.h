@@ -30,6 +30,8 @@ struct LineArgs {
   const T* chirp;         // K complex exp(-i pi j^2/K)
   const T* bhat;          // L complex, spectrum of the conjugate chirp / L
   const T* twl;           // L complex exp(-2 pi i q/L)
+  const T* arrow;         // condensed per-frequency solve (MID): bubble eigenbases
+                          // We, Wo, then coef nu, coef gA, gC (n - 1 each), cc0, cc1
   const T* mu_self;       // M: diff_d 4/h_d^2 lambda along this axis
   const T* mu_o[2];       // other axes
   int64_t so[2], Mo[2];   // their strides and lengths

@@ -308,57 +308,95 @@ __device__ __forceinline__ void contract_inv2(rsrc_t Q, int K, int ka, int kb, c
   }
 }
 
-// Forward contraction, division and inverse contraction of the MID pass in
-// one sweep over the modes l: with q_l column l of Q_k,
-//   out = sum_l q_l (q_l . ch) / (bd + mu_l),
-// so each column is loaded once and used twice (half the table traffic of a
-// forward and a separate inverse contraction).  Two frequencies (chains a
-// and b) interleave.  Column l + 2 is loaded once column l's rank-1 update
-// is done (empty asm statements on the lane offset consume all outputs), so
-// at most three columns per chain are live and one is always in flight.
-// ra: number of modes of chain a (n - 1 for the bubble block k = 0, whose
-// column n - 1 is zero padding).
+// The fused MID pass needs, per frequency k, x = Q_k diag(1/(bd + mu_kl))
+// Q_k^T y, i.e. the solution of the shifted n x n system
+// (coef A_k + bd C_k) x = y of the projected pencil.  Its bubble blocks do
+// not depend on k and couple to the nodal channel only through cos psi and
+// sin psi (psi = pi k / (2K)), so in the bubble eigenbasis (We, Wo: fixed
+// per axis) the system is an arrowhead one, solved by eliminating the
+// bubble modes: O(n) work and one division per frequency instead of two
+// n x n products with a table of n^2 values per frequency.  The nodal
+// Schur complement comes from the product form
+//   den = (cc0 + cc1 cos^2 psi) prod_l (mu_kl + bd) / prod_m (nu_m + bd),
+// every factor a sum of positive terms, so it keeps full relative accuracy
+// at the lowest frequencies, where the direct form
+// alpha_k - sum_m s_m^2 g_m^2 / D_m cancels.
+//
+// Per line (bd = react + the other axes' terms): r_m = 1 / (nu_m + bd) and
+// g_m = coef gA_m + bd gC_m for the n - 1 bubble modes (even, then odd).
 template <typename T, int NORD>
-__device__ __forceinline__ void mid_apply2(rsrc_t Q, int K, int ka, int kb, const T* cha, const T* chb,
-                                           T* outa, T* outb, T bd, const T* __restrict__ mua,
-                                           const T* __restrict__ mub, int ra, T dep) {
-  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
-  T qa[NORD][NORD], qb[NORD][NORD];  // [column][row]; only three columns live at a time
-  {
-    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
+__device__ __forceinline__ void cond_line(const T* __restrict__ ar, T bd, T* r, T* g) {
+  constexpr int ne = NORD / 2, no = (NORD - 1) / 2, nb = NORD - 1;
+  constexpr int onu = ne * ne + no * no, ogA = onu + nb, ogC = ogA + nb;
 #pragma unroll
-    for (int l = 0; l < 2 && l < NORD; ++l)
+  for (int m = 0; m < nb; ++m) {
+    r[m] = (T)1 / (ar[onu + m] + bd);
+    g[m] = ar[ogA + m] + bd * ar[ogC + m];
+  }
+}
+
+// Bubble channels into (BACK = false: W^T) or out of (BACK = true: W) the
+// bubble eigenbasis; v and w hold the n - 1 bubble values, even then odd.
+template <typename T, int NORD, bool BACK>
+__device__ __forceinline__ void cond_basis(const T* __restrict__ ar, const T* v, T* w) {
+  constexpr int ne = NORD / 2, no = (NORD - 1) / 2;
 #pragma unroll
-      for (int c = 0; c < NORD; ++c) {
-        qa[l][c] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
-        qb[l][c] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
-      }
+  for (int i = 0; i < ne; ++i) {
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < ne; ++j) acc += (BACK ? ar[i * ne + j] : ar[j * ne + i]) * v[j];
+    w[i] = acc;
   }
 #pragma unroll
-  for (int c = 0; c < NORD; ++c) outa[c] = outb[c] = 0;
+  for (int i = 0; i < no; ++i) {
+    T acc = 0;
 #pragma unroll
-  for (int l = 0; l < NORD; ++l) {
-    T sa = 0, sb = 0;
+    for (int j = 0; j < no; ++j)
+      acc += (BACK ? ar[ne * ne + i * no + j] : ar[ne * ne + j * no + i]) * v[ne + j];
+    w[ne + i] = acc;
+  }
+}
+
+// Frequency k >= 1: ch (nodal, even, odd channel values) -> out; cs, sn =
+// cos psi, sin psi; mu: the n values mu_kl; twoK = 2 / K (the projected
+// pencil is K/2 times the element-level one).
+template <typename T, int NORD>
+__device__ __forceinline__ void cond_solve(const T* __restrict__ ar, const T* r, const T* g, T bd, T cs,
+                                           T sn, const T* __restrict__ mu, T twoK, const T* ch, T* out) {
+  constexpr int ne = NORD / 2, no = (NORD - 1) / 2, nb = NORD - 1;
+  constexpr int occ = ne * ne + no * no + 3 * nb;
+  constexpr int NC = nb > 0 ? nb : 1;
+  T yh[NC], xh[NC];
+  if constexpr (nb > 0) cond_basis<T, NORD, false>(ar, ch + 1, yh);
+  T se = 0, so = 0;
 #pragma unroll
-    for (int c = 0; c < NORD; ++c) {
-      sa += qa[l][c] * cha[c];
-      sb += qb[l][c] * chb[c];
-    }
-    const T ta = l < ra ? sa / (bd + mua[l]) : (T)0;
-    const T tb = sb / (bd + mub[l]);
+  for (int m = 0; m < ne; ++m) se += g[m] * r[m] * yh[m];
 #pragma unroll
-    for (int c = 0; c < NORD; ++c) {
-      outa[c] += qa[l][c] * ta;
-      outb[c] += qb[l][c] * tb;
-    }
-    if (l + 2 < NORD) {
-      const uint32_t pa = after_all<T, NORD>(oa, outa), pb = after_all<T, NORD>(ob, outb);
+  for (int m = ne; m < nb; ++m) so += g[m] * r[m] * yh[m];
+  const T num = ch[0] - cs * se - sn * so;
+  T den = (ar[occ] + ar[occ + 1] * cs * cs) * (mu[0] + bd);
 #pragma unroll
-      for (int c = 0; c < NORD; ++c) {
-        qa[l + 2][c] = ldq<T>(Q, pa, qrow<T, NORD>(c, l + 2, K));
-        qb[l + 2][c] = ldq<T>(Q, pb, qrow<T, NORD>(c, l + 2, K));
-      }
-    }
+  for (int l = 1; l < NORD; ++l) den *= (mu[l] + bd) * r[l - 1];
+  const T x0 = twoK * num / den;
+#pragma unroll
+  for (int m = 0; m < nb; ++m) xh[m] = r[m] * (twoK * yh[m] - (m < ne ? cs : sn) * g[m] * x0);
+  out[0] = x0;
+  if constexpr (nb > 0) cond_basis<T, NORD, true>(ar, xh, out + 1);
+}
+
+// The bubble-only block (k = 0, projected pencil K times the element-level
+// bubble blocks): ch and out hold the n - 1 bubble values.
+template <typename T, int NORD>
+__device__ __forceinline__ void cond_solve0(const T* __restrict__ ar, const T* r, T invK, const T* ch,
+                                            T* out) {
+  constexpr int nb = NORD - 1;
+  constexpr int NC = nb > 0 ? nb : 1;
+  if constexpr (nb > 0) {
+    T yh[NC];
+    cond_basis<T, NORD, false>(ar, ch, yh);
+#pragma unroll
+    for (int m = 0; m < nb; ++m) yh[m] *= r[m] * invK;
+    cond_basis<T, NORD, true>(ar, yh, out);
   }
 }
 
@@ -671,11 +709,25 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       }
       T res[2][NORD];
       {
-        const int ra = ka == 0 ? n - 1 : n;
-        const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
-        const int offb = kbq == 0 ? 0 : n - 1 + (kbq - 1) * n;
-        mid_apply2<T, NORD>(qtab, K, ka, kbq, cha, chb, res[0], res[1], bd, a.mu_self + offa,
-                            a.mu_self + offb, ra, cha[0]);
+        T lr[NC], lgc[NC];
+        if constexpr (NORD > 1) cond_line<T, NORD>(a.arrow, bd, lr, lgc);
+        const T twoK = (T)2 / (T)K;
+        if (ka == 0) {
+          cond_solve0<T, NORD>(a.arrow, lr, (T)0.5 * twoK, cha, res[0]);
+          res[0][NORD - 1] = 0;
+        } else {
+          const C2<T> w = twm[ka];
+          cond_solve<T, NORD>(a.arrow, lr, lgc, bd, w.x, -w.y, a.mu_self + (n - 1 + (ka - 1) * n), twoK, cha,
+                              res[0]);
+        }
+        if (kbq != 0) {
+          const C2<T> w = twm[kbq];
+          cond_solve<T, NORD>(a.arrow, lr, lgc, bd, w.x, -w.y, a.mu_self + (n - 1 + (kbq - 1) * n), twoK, chb,
+                              res[1]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NORD; ++c) res[1][c] = 0;
+        }
       }
       // inverse inputs: bubble pre-twiddles (pair-local slots), nodal values
       if constexpr (NORD > 1) {

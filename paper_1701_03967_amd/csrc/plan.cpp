@@ -352,6 +352,78 @@ bool zero_block(int n, int64_t K, const std::vector<q>& A, const std::vector<q>&
   return true;
 }
 
+// Tables of the condensed per-frequency solve.  At frequency k >= 1
+// (psi = pi k / (2K)) the projected pencil is K/2 times
+//   [ a0 + a1 cos 2psi     cos psi ve^T   sin psi vo^T ]
+//   [ cos psi ve           E              0            ]
+//   [ sin psi vo           0              O            ]
+// (stiffness; the mass pencil likewise): the bubble blocks E (even
+// channels) and O (odd) do not depend on k, and the nodal couplings only
+// through cos psi and sin psi.  With We, Wo the mass-orthonormal
+// eigenvectors of (E_A, E_C) and (O_A, O_C) (eigenvalues nu), the shifted
+// system (coef A_k + bd C_k) x = y is an arrowhead system in the bubble
+// eigenbasis.  Stored: We (ne x ne, [channel][mode]), Wo (no x no), nu,
+// gA = W^T vA, gC = W^T vC (even modes then odd), and cc0, cc1 with
+// cc0 + cc1 cos^2 psi the nodal Schur complement of the mass pencil.
+bool condensed_tables(int n, const std::vector<q>& A, const std::vector<q>& C, AxisTables* t) {
+  const int ne = num_even(n), no = num_odd(n), nb = n - 1;
+  auto terms = channel_terms(n, true);
+  auto blk = [&](const std::vector<q>& X, int a, int b) {
+    q s = 0;
+    for (const Term& ta : terms[a])
+      for (const Term& tb : terms[b]) s += (q)(ta.w * tb.w) * X[ta.i * (n + 1) + tb.i];
+    return s;
+  };
+  // nodal coupling of bubble channel a: even channels see the sum of the two
+  // end rows (cos psi), odd channels their difference (sin psi)
+  auto cpl = [&](const std::vector<q>& X, int a) {
+    q s = 0;
+    const bool odd = a >= ne;
+    for (const Term& tb : terms[a])
+      s += (q)tb.w * (odd ? X[n * (n + 1) + tb.i] - X[tb.i] : X[tb.i] + X[n * (n + 1) + tb.i]);
+    return s;
+  };
+  std::vector<q> W(nb * nb, 0), nu(nb, 0), gA(nb, 0), gC(nb, 0);
+  for (int part = 0; part < 2; ++part) {
+    const int r = part == 0 ? ne : no, o = part == 0 ? 0 : ne;
+    if (r == 0) continue;
+    std::vector<q> Ma(r * r), Mc(r * r);
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        Ma[a * r + b] = blk(A, o + a, o + b);
+        Mc[a * r + b] = blk(C, o + a, o + b);
+      }
+    std::vector<q> lam, V;
+    if (!pencil_eigen(r, Ma, Mc, &lam, &V)) return false;
+    for (int m = 0; m < r; ++m) {
+      nu[o + m] = lam[m];
+      q sa = 0, sc = 0;
+      for (int c = 0; c < r; ++c) {
+        W[(o + c) * nb + o + m] = V[c * r + m];
+        sa += V[c * r + m] * cpl(A, o + c);
+        sc += V[c * r + m] * cpl(C, o + c);
+      }
+      gA[o + m] = sa;
+      gC[o + m] = sc;
+    }
+  }
+  q Ge = 0, Go = 0;
+  for (int m = 0; m < nb; ++m) (m < ne ? Ge : Go) += gC[m] * gC[m];
+  const q c0 = C[0] + C[n * (n + 1) + n], c1 = C[n] + C[n * (n + 1)];
+  t->arrow.clear();
+  for (int c = 0; c < ne; ++c)
+    for (int m = 0; m < ne; ++m) t->arrow.push_back((double)W[c * nb + m]);
+  for (int c = 0; c < no; ++c)
+    for (int m = 0; m < no; ++m) t->arrow.push_back((double)W[(ne + c) * nb + ne + m]);
+  for (int m = 0; m < nb; ++m) t->arrow.push_back((double)nu[m]);
+  for (int m = 0; m < nb; ++m) t->arrow.push_back((double)gA[m]);
+  for (int m = 0; m < nb; ++m) t->arrow.push_back((double)gC[m]);
+  // cos 2psi = 2 cos^2 psi - 1, sin^2 psi = 1 - cos^2 psi
+  t->arrow.push_back((double)(c0 - c1 - Go));
+  t->arrow.push_back((double)(2 * c1 - Ge + Go));
+  return true;
+}
+
 }  // namespace
 
 void element_matrices(int n, std::vector<double>* A, std::vector<double>* C) {
@@ -392,6 +464,7 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
   t->lam.assign(t->M, 0.0);
   t->Q.assign((size_t)K * n * n, 0.0);
   if (!zero_block(n, K, A, C, t)) return kESPECTRUM;
+  if (!condensed_tables(n, A, C, t)) return kESPECTRUM;
   unsigned hw = std::thread::hardware_concurrency();
   int nthreads = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
   if (K < 64) nthreads = 1;
