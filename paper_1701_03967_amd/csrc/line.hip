@@ -39,17 +39,19 @@ namespace fftfem {
 extern __shared__ double2 fftfem_lds[];
 
 #ifndef FFTFEM_MINW64
-#define FFTFEM_MINW64 2
+#define FFTFEM_MINW64 4
 #endif
 #ifndef FFTFEM_MINW32
 #define FFTFEM_MINW32 4
 #endif
 
-// Threads per line-kernel workgroup: 512 for float32; 256 for float64, whose
-// register footprint allows no more than eight waves per CU anyway.  Every
-// tile has G * K <= 1024 element tasks and G * K / 2 contraction tasks.
+// Threads per line-kernel workgroup: 512 for both precisions.  A float64
+// line of K = 1024 elements fills half the LDS of a CU, so two tiles share
+// a CU; at <= 128 VGPRs their 16 waves (four per SIMD) hide more latency
+// than eight 256-thread waves with room for 256 VGPRs.  Every tile has
+// G * K <= 1024 element tasks and G * K / 2 contraction tasks.
 #ifndef FFTFEM_NT64
-#define FFTFEM_NT64 256
+#define FFTFEM_NT64 512
 #endif
 
 template <typename T>
@@ -57,8 +59,8 @@ struct LineCfg {
   static constexpr int NT = sizeof(T) == 8 ? FFTFEM_NT64 : 512;
   static constexpr int TPT = 1024 / NT;  // element tasks per thread
   static constexpr int CPT = 512 / NT;   // contraction tasks per thread
-  // minimum waves per SIMD the register allocation must allow: two 256-thread
-  // float64 tiles per CU (<= 256 VGPRs), two 512-thread float32 tiles (<= 128)
+  // minimum waves per SIMD the register allocation must allow: two 512-thread
+  // tiles per CU (<= 128 VGPRs)
   static constexpr int MINW = sizeof(T) == 8 ? FFTFEM_MINW64 : FFTFEM_MINW32;
 };
 
