@@ -119,7 +119,7 @@ def copy_calibration(torch, nbytes: int):
 def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=False):
     plan = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=precision,
                    max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12)
-    if tune and prob.N == 2:
+    if tune and prob.N >= 2:
         plan.tune()  # measured line-pass parameters, before the untimed warm-up
     u = torch.empty_like(f)
     for _ in range(warmup):
@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
     ap.add_argument("--batch-iters", type=int, default=3, help="c5_batch: refinement steps")
     ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
-    ap.add_argument("--tune", action="store_true", help="2D workloads: measure line-pass parameters first")
+    ap.add_argument("--tune", action="store_true", help="measure line-pass parameters first (N >= 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
     args = ap.parse_args()

@@ -69,7 +69,7 @@ enum {
 /* Full plan description.  Fields left zero take the documented defaults. */
 typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
-  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, K[d] >= 2 */
+  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above) */
   int n;                          /* element order, 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */
@@ -174,7 +174,7 @@ int fftfem_get_timing(fftfem_plan_t p, int max, char* names, double* avg_ms, int
  * axes are computed once per axis length within a plan; every plan owns its
  * device tables and workspace).  flags: FFTFEM_BATCH_TUNE measures, on the
  * first solve, the lines per tile and the largest FFT radix of every
- * two-dimensional line pass kind in the batch (kept process-wide for
+ * line pass kind in the batch (kept process-wide for
  * later plans of the same kind).  EINVAL for count < 1 or a null pointer;
  * otherwise the status of the first descriptor that fails fftfem_plan_ex.
  *
@@ -200,13 +200,14 @@ void fftfem_destroy_batch(fftfem_batch_t b);
 
 /*
  * fftfem_tune: the measurement FFTFEM_BATCH_TUNE makes, for the line passes
- * of one two-dimensional plan (float32, float32 with refinement or float64):
- * each pass (forward along the last axis, the middle pass, inverse) is timed
- * on the plan's own scratch, in the layout its solve uses, for every
- * admissible lines per tile and largest FFT radix (16, 8, 4); the fastest
- * is kept process-wide and used by every later solve of plans of that kind.
- * Synchronizes s.  ENOTIMPL for plans that are not two-dimensional, EINVAL
- * for a null plan, EHIP on a runtime error.
+ * of one plan with N >= 2 (float32, float32 with refinement or float64): each
+ * of the 2N - 1 passes of the solve (forward along axes N-1 .. 1, the middle
+ * pass, inverse along 1 .. N-1) is timed on the plan's own scratch, in the
+ * layout its solve uses, for every admissible lines per tile and largest
+ * FFT radix (16, 8, 4); the fastest per pass kind (precision, n, mode,
+ * strided or not, element count) is kept process-wide and used by every
+ * later solve of plans of that kind.  Synchronizes s.  ENOTIMPL for N = 1,
+ * EINVAL for a null plan, EHIP on a runtime error.
  */
 int fftfem_tune(fftfem_plan_t p, hipStream_t s);
 

@@ -576,10 +576,22 @@ int transform_chain(fftfem_plan_t p, const void* in, int in_f64, T* work, T* wor
   return line_pass<T>(p, natural_geom(p, N - 1, true), INV, work, 0, out, 1, upd, flag, s, partials);
 }
 
-// Geometry of the tuner's passes (2D plans), as the solve runs them: 0
-// forward along axis 1, 1 the middle pass along axis 0 (on the transposed
-// copy when the solve uses one), 2 inverse along axis 1.
+// Mode of pass `pass` of the chain (0 .. 2N - 2): forward passes along axes
+// N - 1 down to 1, the middle pass along axis 0, inverse passes along axes 1
+// up to N - 1.
+int chain_mode(const fftfem_plan_s* p, int pass) {
+  return pass < p->N - 1 ? FWD : (pass == p->N - 1 ? MID : INV);
+}
+
+// Geometry of the tuner's passes, as the solve runs them.  2D: 0 forward
+// along axis 1, 1 the middle pass along axis 0 (on the transposed copy when
+// the solve uses one), 2 inverse along axis 1.
 Geom tune_geom(fftfem_plan_t p, int pass) {
+  if (p->N != 2) {
+    const int N = p->N;
+    const int axis = pass < N - 1 ? N - 1 - pass : (pass == N - 1 ? 0 : pass - N + 1);
+    return natural_geom(p, axis, true);
+  }
   if (pass != 1) {
     Geom g = natural_geom(p, p->N - 1, true);
     if (pass == 0 && p->trfused) g.oes = p->M[0];
@@ -647,8 +659,9 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   for (int i = 0; i < d.N; ++i)
     if (d.X[i] == 0) d.X[i] = 1.0;
   if (d.n > kMaxLineOrder) return FFTFEM_ENOTIMPL;
+  // a line-kernel tile holds at most kLineTasks element tasks
   for (int i = 0; i < d.N; ++i)
-    if (d.K[i] > (is_pow2(d.K[i]) ? 2048 : kLineTasks)) return FFTFEM_ENOTIMPL;
+    if (d.K[i] > kLineTasks) return FFTFEM_ENOTIMPL;
   fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
   if (!p) return FFTFEM_ENOMEM;
   p->desc = d;
@@ -960,14 +973,16 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
 
 namespace fftfem {
 
+int plan_num_passes(fftfem_plan_t p) { return p ? 2 * p->N - 1 : 0; }
+
 int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info) {
-  if (!p || !info || pass < 0 || pass > 2) return FFTFEM_EINVAL;
-  if (p->N != 2) return FFTFEM_ENOTIMPL;
+  if (!p || !info || pass < 0 || pass >= 2 * p->N - 1) return FFTFEM_EINVAL;
+  if (p->N < 2) return FFTFEM_ENOTIMPL;
   const Geom g = tune_geom(p, pass);
   const int64_t K = p->K[g.axis];
   info->elt = p->desc.precision == FFTFEM_FP64 ? (int)sizeof(double) : (int)sizeof(float);
   info->n = p->n;
-  info->mode = pass == 0 ? FWD : (pass == 1 ? MID : INV);
+  info->mode = chain_mode(p, pass);
   info->lf = g.es > 1 ? 1 : 0;
   info->K = K;
   int G = 1;
@@ -987,7 +1002,7 @@ int plan_time_pass(fftfem_plan_t p, int pass, int G, int lrmax, int reps, hipStr
   // data for the timing runs: the plan's own scratch (float32 workspace; the
   // first two double-double planes for float64 plans), contents irrelevant
   const bool f64 = info.elt == (int)sizeof(double);
-  float* buf = (pass == 1 && p->tr2d) ? p->W32b : p->W32;
+  float* buf = (p->N == 2 && pass == 1 && p->tr2d) ? p->W32b : p->W32;
   double* din = p->tmp[0];
   double* dout = p->tmp[1];
   auto run = [&]() {

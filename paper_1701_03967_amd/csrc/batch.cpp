@@ -64,7 +64,7 @@ struct Group {
   size_t lds = 0;
 };
 
-// Measures, for every 2D line-pass kind of the plans (precision, n, mode,
+// Measures, for every line-pass kind of the plans (precision, n, mode,
 // strided or not, element-count class), the candidate lines per tile and
 // largest FFT radixes on the plan of that kind with the most data, and keeps
 // the fastest (process-wide).
@@ -76,7 +76,7 @@ int tune_plans(const std::vector<fftfem_plan_t>& plans, hipStream_t s) {
   };
   std::map<std::tuple<int, int, int, int, int64_t>, Cand> kinds;
   for (fftfem_plan_t p : plans) {
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < plan_num_passes(p); ++pass) {
       PassInfo info;
       if (plan_pass_info(p, pass, &info) != FFTFEM_OK) continue;
       const auto key = std::make_tuple(info.elt, info.n, info.mode, info.lf, tune_class(info.K));

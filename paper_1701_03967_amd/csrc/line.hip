@@ -444,7 +444,10 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
   const int K = a.K, lk = a.log2K, lg = a.log2G, G = 1 << lg;
   const int M = n * K - 1;
   const int ls = (a.L ? a.L : K) + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
-  const int LS = NB * ls * 2;  // T slots per line
+  // raw line data (loaded input, spectral output, scattered result) is
+  // packed at M slots per line: it never coexists with the FFT buffers
+  // (NB ls complex slots per line), which it aliases across barriers
+  const int RS = M;
   const int64_t l0 = (int64_t)xcd_remap(bid, nblk) << lg;
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)(K * n * n));
   const C2<T>* twf = reinterpret_cast<const C2<T>*>(a.twf);
@@ -458,7 +461,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       const int64_t line = l0 + g;
       const bool ok = line < a.nlines;
       const int64_t base = ok ? line_base(a, line) : 0;
-      T* dst = raw + g * LS;
+      T* dst = raw + g * RS;
       const int step = kNT >> lg;
       for (int i0 = tid >> lg; i0 < M; i0 += 16 * step) {
         T v[16];
@@ -479,7 +482,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         for (int g = 0; g < G; ++g) {
           const int64_t line = l0 + g;
           if (line >= a.nlines) break;
-          T* dst = raw + g * LS;
+          T* dst = raw + g * RS;
           for (int i0 = tid; i0 < M; i0 += 4 * kNT) {
             T v[4];
 #pragma unroll
@@ -496,23 +499,24 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         }
         return;
       }
-      for (int g = 0; g < G; ++g) {
-        const int64_t line = l0 + g;
-        if (line >= a.nlines) break;
-        const int64_t base = line * (int64_t)M;
-        T* dst = raw + g * LS;
-        for (int i0 = tid; i0 < M; i0 += 16 * kNT) {
-          T v[16];
+      // the lines of a contiguous tile are adjacent: one flat segment of
+      // nl M values, loaded in one sweep into the packed raw layout (a loop
+      // over the lines would wait for each line's loads before issuing the
+      // next line's)
+      const int nl = (int)(a.nlines - l0 < (int64_t)G ? a.nlines - l0 : (int64_t)G);
+      const int nflat = nl * M;
+      const int64_t base = l0 * (int64_t)M;
+      for (int i0 = tid; i0 < nflat; i0 += 16 * kNT) {
+        T v[16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            int i = i0 + u * kNT;
-            v[u] = i < M ? load_in<T>(src, f64, base + i) : (T)0;
-          }
+        for (int u = 0; u < 16; ++u) {
+          int i = i0 + u * kNT;
+          v[u] = i < nflat ? load_in<T>(src, f64, base + i) : (T)0;
+        }
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            int i = i0 + u * kNT;
-            if (i < M) dst[i] = v[u];
-          }
+        for (int u = 0; u < 16; ++u) {
+          int i = i0 + u * kNT;
+          if (i < nflat) raw[i] = v[u];
         }
       }
     }
@@ -534,7 +538,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       const int64_t line = l0 + g;
       if (line < a.nlines) {
         const int64_t base = line_base(a, line);
-        const T* srcl = raw + g * LS;
+        const T* srcl = raw + g * RS;
         const int step = kNT >> lg;
         for (int i = tid >> lg; i < M; i += step) put(base + (int64_t)i * a.es, srcl[i]);
       }
@@ -544,18 +548,15 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         for (int g = 0; g < G; ++g) {
           const int64_t line = l0 + g;
           if (line >= a.nlines) break;
-          const T* srcl = raw + g * LS;
+          const T* srcl = raw + g * RS;
           for (int i = tid; i < M; i += kNT) put(line + (int64_t)i * a.oes, srcl[i]);
         }
         return;
       }
-      for (int g = 0; g < G; ++g) {
-        const int64_t line = l0 + g;
-        if (line >= a.nlines) break;
-        const int64_t base = line * (int64_t)M;
-        const T* srcl = raw + g * LS;
-        for (int i = tid; i < M; i += kNT) put(base + i, srcl[i]);
-      }
+      const int nl = (int)(a.nlines - l0 < (int64_t)G ? a.nlines - l0 : (int64_t)G);
+      const int nflat = nl * M;
+      const int64_t base = l0 * (int64_t)M;
+      for (int i = tid; i < nflat; i += kNT) put(base + i, raw[i]);
     }
   };
 
@@ -598,7 +599,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       if (t < ntask) {
         int g, jp;
         esplit(t, g, jp);
-        const T* r = raw + g * LS + jp * n;
+        const T* r = raw + g * RS + jp * n;
         T y[NORD];
 #pragma unroll
         for (int m = 0; m < n - 1; ++m) y[m] = r[m];
@@ -828,7 +829,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       for (int l = 0; l < NORD; ++l)
         if (l >= ra) hw[s][0][l] = 0;
     } else {
-      const T* rs = raw + g * LS;
+      const T* rs = raw + g * RS;
       T wa[NORD], wb[NORD];
 #pragma unroll
       for (int l = 0; l < NORD; ++l) {
@@ -848,7 +849,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       if (t >= nctask) continue;
       int g, kap;
         csplit(t, g, kap);
-      T* rs = raw + g * LS;
+      T* rs = raw + g * RS;
 #pragma unroll
       for (int fi = 0; fi < 2; ++fi) {
         int k = fi == 0 ? kap : (kap == 0 ? (K >> 1) : K - kap);
@@ -966,7 +967,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       if (t < ntask) {
         int g, jp;
         esplit(t, g, jp);
-        T* r = raw + g * LS + jp * n;
+        T* r = raw + g * RS + jp * n;
 #pragma unroll
         for (int m = 0; m < n - 1; ++m) r[m] = hv[s][m];
         if (jp < K - 1) r[n - 1] = hv[s][n - 1];

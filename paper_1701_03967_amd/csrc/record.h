@@ -74,15 +74,16 @@ void tune_set(const TuneKey& k, const TuneVal& v);
 bool tune_get(const TuneKey& k, TuneVal* v);
 
 // Candidate line-pass parameters for the tuner and a timing run of one pass
-// of plan p (on its own scratch; 2D plans only).  pass: 0
-// forward along the last axis, 1 the middle pass along axis 0 (in the
-// layout the solve uses), 2 inverse along the last axis.
+// of plan p (on its own scratch; plans with N >= 2).  pass 0 .. 2N - 2 in
+// the order of the solve's chain: forward along axes N - 1 .. 1, the middle
+// pass along axis 0 (in the layout the solve uses), inverse along 1 .. N - 1.
 struct PassInfo {
   int elt;  // bytes per value of the pass (4 or 8)
   int n, mode, lf;
   int64_t K;
   int Gmax;  // largest admissible lines per tile
 };
+int plan_num_passes(fftfem_plan_t p);
 int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info);
 int plan_time_pass(fftfem_plan_t p, int pass, int G, int lrmax, int reps, hipStream_t s, float* ms);
 

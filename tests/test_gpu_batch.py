@@ -171,3 +171,20 @@ def test_plan_tune(fm, precision, tol):
     u = p.solve(torch.from_numpy(f).cuda())
     torch.cuda.synchronize()
     assert rel(u.cpu().numpy(), ref) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_plan_tune_3d(fm, precision, tol):
+    """Tuning the five passes of a 3D plan (forward along axes 2 and 1, the
+    middle pass along axis 0, inverse along 1 and 2) keeps the oracle's
+    accuracy."""
+    K, n = (8, 16, 12), 3
+    diff, react = (1.0, 2.0, 0.5), 0.0
+    f = inputs.draw_rhs(tuple(n * k - 1 for k in K), seed=22)
+    ref = osolve.solve(f, n, K, diff, react)
+    say("tune 3d", precision, K, n)
+    p = fm.Plan(K, n, diff, react, precision=precision)
+    p.tune()
+    u = p.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert rel(u.cpu().numpy(), ref) < tol
