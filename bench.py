@@ -193,13 +193,16 @@ def cpu_baseline(prob, budget_s: float = 20.0):
 def run_batch(args, torch, fm):
     """The batched heat-step workload: 512 independent 2D problems (n in 2..8,
     K per axis in 32..512, diff in [0.5, 2], react = 1/tau = 1000, 1..8
-    right-hand sides), float32 transforms with float64 refinement, solved
-    in one graph launch; line-pass parameters tuned on the first solve.
+    right-hand sides), float32 transforms with float64 refinement (or, with
+    --batch-precision fp64, float64 transforms), solved in one graph launch;
+    line-pass parameters tuned on the first solve.
     Right-hand sides: N(0,1), drawn on the device per problem from a seeded
     generator (the problem parameters come from the seeded workload draw)."""
     draw = inputs.draw_batch(count=args.batch_count)
-    probs = [dict(K=p.K, n=p.n, diff=p.diff, react=p.react, precision="fp32_refine",
-                  max_iter=args.batch_iters, tol=1e-12, nrhs=p.nrhs) for p in draw.problems]
+    prec = args.batch_precision
+    probs = [dict(K=p.K, n=p.n, diff=p.diff, react=p.react, precision=prec,
+                  max_iter=args.batch_iters if prec == "fp32_refine" else 0, tol=1e-12, nrhs=p.nrhs)
+             for p in draw.problems]
     total = sum(p.nrhs * p.size for p in draw.problems)
     t0 = time.perf_counter()
     b = fm.Batch(probs, tune=not args.no_tune)
@@ -242,11 +245,11 @@ def run_batch(args, torch, fm):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if prec == "fp32_refine" else ("f64" if prec == "fp64" else "f32"),
         "data": "synthetic",
         "config": {"workload": f"c5_batch_{len(probs)}_2d_heat_step", "problems": len(probs),
-                   "unknowns": total, "react": draw.problems[0].react, "precision": "fp32_refine",
-                   "max_iter": args.batch_iters, "tuned": not args.no_tune},
+                   "unknowns": total, "react": draw.problems[0].react, "precision": prec,
+                   "max_iter": args.batch_iters if prec == "fp32_refine" else 0, "tuned": not args.no_tune},
         "plan_s": t_plan, "first_solve_s": t_first,
         "refinement": {"iterations_min": min(its), "iterations_max": max(its), "converged": conv},
         "workspace_bytes": b.workspace_bytes(),
@@ -266,6 +269,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
     ap.add_argument("--batch-iters", type=int, default=3, help="c5_batch: refinement steps")
     ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
+    ap.add_argument("--batch-precision", default="fp32_refine", choices=("fp32_refine", "fp64", "fp32"),
+                    help="c5_batch: precision mode of every problem")
     ap.add_argument("--tune", action="store_true", help="measure line-pass parameters first (N >= 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")

@@ -46,10 +46,11 @@ struct fftfem_plan_s {
   float* W32 = nullptr;      // float32 workspace (float32 modes)
   float* W32b = nullptr;     // second float32 workspace (transposed 2D schedule)
   double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
-  double* W64r = nullptr;    // float64 residual (float32 + refinement, 1D)
+  double* W64r = nullptr;    // float64 residual (float32 + refinement)
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
   double* tmp[8] = {};       // operator-apply partial products (double-double planes)
+  double* cor = nullptr;     // while set: the update pass also stores its correction here
   int ntmp = 0;
   double* partials = nullptr;
   int npartials = 0;
@@ -317,6 +318,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.in = in;
   a.out = out;
   a.upd = upd;
+  a.cor = upd ? p->cor : nullptr;
   a.in_f64 = in_f64;
   a.out_kind = out_kind;
   a.K = (int)t.K;
@@ -399,8 +401,9 @@ struct DDp {
 // 0 float, 1 double, 2 double-double (o1h, o1l).
 int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, void* o1h, double* o1l,
                int o1_kind, double* o2h, double* o2l, const double c1[4], const double c2[4],
-               const int* flag, hipStream_t s) {
+               const int* flag, hipStream_t s, bool dd = true) {
   ApplyArgs a{};
+  a.dd = dd ? 1 : 0;
   a.in1[0] = in1.h;
   a.in1[1] = in1.l;
   a.in2[0] = in2.h;
@@ -436,10 +439,10 @@ int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, voi
   size_t lds = (size_t)planes * a.G * W * sizeof(double);
   int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
   if (p->rec) {
-    record(p, REC_APPLY, {p->n, in1.l ? 1 : 0}, a, nblocks, lds);
+    record(p, REC_APPLY, {p->n, in1.l ? 1 : 0, dd ? 1 : 0}, a, nblocks, lds);
     return FFTFEM_OK;
   }
-  Timed tm(p, s, std::string("apply_ax") + std::to_string(axis));
+  Timed tm(p, s, std::string(dd ? "apply_ax" : "apply64_ax") + std::to_string(axis));
   return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
 }
 
@@ -480,6 +483,37 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   double c1[4] = {c[0], 0, 0, 1};
   return apply_pass(p, 0, {T[4], T[5]}, {T[6], T[7]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
                     nullptr, flag, s);
+}
+
+// r <- r - A c in plain float64 (N >= 2): the residual of u + c from the
+// residual r of u, for a correction c that is small next to u (rounding of
+// A c is then far below the refinement's target).  c is read from tmp[1];
+// the passes write hi planes only (tmp[0], tmp[2]; in 3D also tmp[4], tmp[6]).
+int operator_apply_incr(fftfem_plan_t p, double* r, const int* flag, hipStream_t s, int ph) {
+  const double* c = p->coef;
+  const double react = p->desc.react;
+  double** T = p->tmp;
+  const DDp none{nullptr, nullptr};
+  const double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
+  int rc;
+  p->phase = ph;
+  rc = apply_pass(p, p->N - 1, {T[1], nullptr}, none, nullptr, T[0], nullptr, 1, T[2], nullptr, cC, cA, flag, s,
+                  false);
+  if (rc) return rc;
+  p->phase = ph + 1;
+  if (p->N == 2) {
+    double c1[4] = {c[0], react, 0, c[1]};
+    return apply_pass(p, 0, {T[0], nullptr}, {T[2], nullptr}, r, r, nullptr, 1, nullptr, nullptr, c1, nullptr,
+                      flag, s, false);
+  }
+  double c4[4] = {c[1], react, 0, c[2]};
+  rc = apply_pass(p, 1, {T[0], nullptr}, {T[2], nullptr}, nullptr, T[4], nullptr, 1, T[6], nullptr, cC, c4, flag,
+                  s, false);
+  if (rc) return rc;
+  p->phase = ph + 2;
+  double c1[4] = {c[0], 0, 0, 1};
+  return apply_pass(p, 0, {T[4], nullptr}, {T[6], nullptr}, r, r, nullptr, 1, nullptr, nullptr, c1, nullptr, flag,
+                    s, false);
 }
 
 // Forward on axes N-1..1, MID on axis 0, inverse on axes 1..N-1.
@@ -764,7 +798,7 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     rc = dev_alloc(p, (void**)&p->W32, (size_t)p->size * sizeof(float));
   if (!rc && p->tr2d && d.precision != FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W32b, (size_t)p->size * sizeof(float));
-  if (!rc && d.precision == FFTFEM_FP32_REFINE && d.N == 1)
+  if (!rc && d.precision == FFTFEM_FP32_REFINE)
     rc = dev_alloc(p, (void**)&p->W64r, (size_t)p->size * sizeof(double));
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
@@ -848,12 +882,22 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
     if (rc || p->desc.precision == FFTFEM_FP32) continue;
     for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
       const int pit = base + 1 + SC + (it - 1) * per_it;
-      // residual in float64 for the 1D float64 pass, float32 otherwise
       const bool one = N == 1;
-      void* r = one ? (void*)p->W64r : (void*)p->W32;
-      rc = operator_apply(p, ur, fr, r, one ? 1 : 0, flag, s, pit);
-      if (!rc)
-        rc = transform_chain<float>(p, r, one ? 1 : 0, p->W32, p->W32b, ur, ur, flag, s, true, one, pit + N);
+      if (one) {
+        // 1D: double-double residual every step, float64 chain
+        rc = operator_apply(p, ur, fr, p->W64r, 1, flag, s, pit);
+        if (!rc)
+          rc = transform_chain<float>(p, p->W64r, 1, p->W32, p->W32b, ur, ur, flag, s, true, true, pit + N);
+      } else {
+        // first step: the double-double residual f - A u (float64); later
+        // steps: r - A c in float64 with the stored correction c
+        rc = it == 1 ? operator_apply(p, ur, fr, p->W64r, 1, flag, s, pit)
+                     : operator_apply_incr(p, p->W64r, flag, s, pit);
+        p->cor = p->tmp[1];
+        if (!rc)
+          rc = transform_chain<float>(p, p->W64r, 1, p->W32, p->W32b, ur, ur, flag, s, true, false, pit + N);
+        p->cor = nullptr;
+      }
       if (rc) break;
       p->phase = pit + N + SC;
       if (p->rec) {

@@ -201,7 +201,7 @@ int build_graph(fftfem_batch_s* b, const double* const* f, double* const* u, hip
         break;
       }
       case REC_APPLY:
-        e = launch_apply_grouped(g.key[0], g.key[1] != 0, GroupedOps{jobs, jobof, start, g.nblocks, g.lds},
+        e = launch_apply_grouped(g.key[0], g.key[1] != 0, g.key[2] != 0, GroupedOps{jobs, jobof, start, g.nblocks, g.lds},
                                  b->cap);
         break;
       case REC_TR32:

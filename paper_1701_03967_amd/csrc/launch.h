@@ -14,6 +14,7 @@ struct LineArgs {
   const void* in;
   void* out;
   const double* upd;      // INV with update: out = upd + result (float64)
+  double* cor;            // INV with update, optional: the result (the correction) as float64
   int in_f64;
   int out_kind;           // 0: T, 1: double, 2: float
   int K, log2K;
@@ -56,6 +57,7 @@ struct ApplyArgs {
   const double* Ael[2];   // element matrices, hi and lo parts
   const double* Cel[2];
   const int* flag;
+  int dd;                 // 1: double-double arithmetic; 0: plain float64 (no lo planes)
 };
 
 
@@ -85,7 +87,7 @@ struct GroupedOps {
   int nblocks;
   size_t lds;
 };
-hipError_t launch_apply_grouped(int n, bool lo, const GroupedOps& g, hipStream_t s);
+hipError_t launch_apply_grouped(int n, bool lo, bool dd, const GroupedOps& g, hipStream_t s);
 template <typename T>
 hipError_t launch_transpose_grouped(const GroupedOps& g, hipStream_t s);
 hipError_t launch_reset_grouped(const ResetJob* jobs, int njobs, hipStream_t s);

@@ -526,6 +526,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
     if constexpr (UPD) {
       double u = a.upd[idx] + (double)v;
       ((double*)a.out)[idx] = u;
+      if (a.cor) a.cor[idx] = (double)v;
       acc_c += (double)v * (double)v;
       acc_u += u * u;
     } else {

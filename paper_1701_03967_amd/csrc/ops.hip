@@ -62,6 +62,25 @@ __device__ __forceinline__ dd dd_norm(dd s) {
   return {h, s.l - (h - s.h)};
 }
 
+// The same row in plain float64 arithmetic (hi parts of the element
+// matrices only; the operator of the incremental residual r - A c, where c
+// is a small correction and its float64 rounding is far below the accuracy
+// the refinement needs).
+template <int NORD>
+__device__ __forceinline__ double row_apply_f64(const double* v, int g, const double* X) {
+  constexpr int n = NORD;
+  const bool node = (g + 1) % n == 0;
+  const int l = node ? n : g % n + 1;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t <= n; ++t) s = __builtin_fma(X[l * (n + 1) + t], v[g - l + t], s);
+  if (node) {
+#pragma unroll
+    for (int t = 0; t <= n; ++t) s = __builtin_fma(X[t], v[g + t], s);
+  }
+  return s;
+}
+
 // One row of a 1D element-assembled matrix at position g of a line
 // (Sect. 2: element-by-element assembly of A and C).  With v = 0 outside
 // the line (Dirichlet):
@@ -98,10 +117,12 @@ __device__ __forceinline__ dd row_apply(const double* vh, const double* vl, int 
 //   o2 = c2[0] a(in1) + c2[1] c(in1) + c2[2] a(in2) + c2[3] c(in2)
 // Chained along the axes these give the sum-factorized tensor operator.
 // Tiles: G lines x TL positions with an n-dof halo on each side, staged in
-// LDS as separate hi and lo planes.
-template <int NORD, bool LO>
+// LDS as separate hi and lo planes.  DD: double-double arithmetic (error-free
+// products and sums); otherwise plain float64 (LO false, hi outputs only).
+template <int NORD, bool LO, bool DD>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, int bid, int nblk) {
 #pragma clang fp contract(off)
+  static_assert(DD || !LO, "double-double inputs need double-double arithmetic");
   if (a.flag && *a.flag) return;
   constexpr int n = NORD;
   constexpr int XX = (NORD + 1) * (NORD + 1);
@@ -175,6 +196,32 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int bid, int nblk
     if (line >= a.nlines || pos >= a.M) continue;
     // window pointers shifted so that index = position along the line
     const int sh = g * W + n - (int)s0;
+    if constexpr (!DD) {
+      double A1 = 0, C1 = 0, A2 = 0, C2v = 0;
+      if (needA1) A1 = row_apply_f64<NORD>(v1h + sh, (int)pos, Xa);
+      if (needC1) C1 = row_apply_f64<NORD>(v1h + sh, (int)pos, Xc);
+      if (needA2) A2 = row_apply_f64<NORD>(v2h + sh, (int)pos, Xa);
+      if (needC2) C2v = row_apply_f64<NORD>(v2h + sh, (int)pos, Xc);
+      int64_t outer = line / a.es, inner = line - outer * a.es;
+      int64_t idx = outer * a.M * a.es + inner + pos * a.es;
+      double r = a.c1[0] * A1;
+      r = __builtin_fma(a.c1[1], C1, r);
+      r = __builtin_fma(a.c1[2], A2, r);
+      r = __builtin_fma(a.c1[3], C2v, r);
+      if (a.f) r = a.f[idx] - r;
+      if (a.o1_kind == 0)
+        ((float*)a.o1[0])[idx] = (float)r;
+      else
+        ((double*)a.o1[0])[idx] = r;
+      if (a.o2[0]) {
+        double q = a.c2[0] * A1;
+        q = __builtin_fma(a.c2[1], C1, q);
+        q = __builtin_fma(a.c2[2], A2, q);
+        q = __builtin_fma(a.c2[3], C2v, q);
+        a.o2[0][idx] = q;
+      }
+      continue;
+    }
     dd A1{0, 0}, C1{0, 0}, A2{0, 0}, C2v{0, 0};
     if (needA1) A1 = row_apply<NORD, LO>(v1h + sh, v1l + sh, (int)pos, Xa);
     if (needC1) C1 = row_apply<NORD, LO>(v1h + sh, v1l + sh, (int)pos, Xc);
@@ -212,19 +259,19 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int bid, int nblk
   }
 }
 
-template <int NORD, bool LO>
+template <int NORD, bool LO, bool DD>
 __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
-  apply_body<NORD, LO>(a, blockIdx.x, gridDim.x);
+  apply_body<NORD, LO, DD>(a, blockIdx.x, gridDim.x);
 }
 
 // Grouped launch: block b runs tile b - start[j] of job j = job_of[b].
-template <int NORD, bool LO>
+template <int NORD, bool LO, bool DD>
 __global__ __launch_bounds__(kThreads) void apply_kernel_grouped(const ApplyArgs* __restrict__ jobs,
                                                                  const int* __restrict__ job_of,
                                                                  const int* __restrict__ start) {
   const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
   const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
-  apply_body<NORD, LO>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
+  apply_body<NORD, LO, DD>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,17 +387,20 @@ hipError_t launch_transpose_grouped(const GroupedOps& g, hipStream_t s) {
 template hipError_t launch_transpose_grouped<float>(const GroupedOps&, hipStream_t);
 template hipError_t launch_transpose_grouped<double>(const GroupedOps&, hipStream_t);
 
-hipError_t launch_apply_grouped(int n, bool lo, const GroupedOps& g, hipStream_t s) {
+hipError_t launch_apply_grouped(int n, bool lo, bool dd, const GroupedOps& g, hipStream_t s) {
   const ApplyArgs* jobs = (const ApplyArgs*)g.jobs;
   switch (n) {
-#define FFTFEM_CASE(N)                                                                                 \
-  case N:                                                                                              \
-    if (lo)                                                                                            \
-      hipLaunchKernelGGL((apply_kernel_grouped<N, true>), dim3(g.nblocks), dim3(kThreads), g.lds, s, jobs, \
-                         g.job_of, g.start);                                                           \
-    else                                                                                               \
-      hipLaunchKernelGGL((apply_kernel_grouped<N, false>), dim3(g.nblocks), dim3(kThreads), g.lds, s,     \
-                         jobs, g.job_of, g.start);                                                     \
+#define FFTFEM_CASE(N)                                                                                       \
+  case N:                                                                                                    \
+    if (!dd)                                                                                                 \
+      hipLaunchKernelGGL((apply_kernel_grouped<N, false, false>), dim3(g.nblocks), dim3(kThreads), g.lds, s, \
+                         jobs, g.job_of, g.start);                                                           \
+    else if (lo)                                                                                             \
+      hipLaunchKernelGGL((apply_kernel_grouped<N, true, true>), dim3(g.nblocks), dim3(kThreads), g.lds, s,   \
+                         jobs, g.job_of, g.start);                                                           \
+    else                                                                                                     \
+      hipLaunchKernelGGL((apply_kernel_grouped<N, false, true>), dim3(g.nblocks), dim3(kThreads), g.lds, s,  \
+                         jobs, g.job_of, g.start);                                                           \
     return hipGetLastError();
     FFTFEM_CASE(1)
     FFTFEM_CASE(2)
@@ -389,13 +439,16 @@ template hipError_t launch_transpose<double>(const double*, double*, int64_t, in
 
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s) {
   const bool lo = a.in1[1] != nullptr;
+  if (!a.dd && lo) return hipErrorInvalidValue;
   switch (n) {
-#define FFTFEM_CASE(N)                                                                         \
-  case N:                                                                                      \
-    if (lo)                                                                                    \
-      hipLaunchKernelGGL((apply_kernel<N, true>), dim3(nblocks), dim3(kThreads), lds, s, a);   \
-    else                                                                                       \
-      hipLaunchKernelGGL((apply_kernel<N, false>), dim3(nblocks), dim3(kThreads), lds, s, a);  \
+#define FFTFEM_CASE(N)                                                                                \
+  case N:                                                                                             \
+    if (!a.dd)                                                                                        \
+      hipLaunchKernelGGL((apply_kernel<N, false, false>), dim3(nblocks), dim3(kThreads), lds, s, a);  \
+    else if (lo)                                                                                      \
+      hipLaunchKernelGGL((apply_kernel<N, true, true>), dim3(nblocks), dim3(kThreads), lds, s, a);    \
+    else                                                                                              \
+      hipLaunchKernelGGL((apply_kernel<N, false, true>), dim3(nblocks), dim3(kThreads), lds, s, a);   \
     return hipGetLastError();
     FFTFEM_CASE(1)
     FFTFEM_CASE(2)

@@ -20,7 +20,7 @@ enum RecKind { REC_LINE32 = 0, REC_LINE64, REC_APPLY, REC_TR32, REC_TR64, REC_RE
 struct Rec {
   int phase;                        // position in the plan's schedule (see fftfem_solve)
   int kind;                         // RecKind
-  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo
+  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo, dd
   std::vector<unsigned char> args;  // LineArgs<T>, ApplyArgs, TransposeJob, ResetJob or ReduceJob
   int nblocks;
   size_t lds;
