@@ -199,6 +199,28 @@ size_t fftfem_batch_workspace_bytes(const fftfem_batch_t b);
 void fftfem_destroy_batch(fftfem_batch_t b);
 
 /*
+ * Implicit Euler time stepping of the semi-discrete heat equation of the
+ * plan's operator (Sect. 4 remarks that implicit time discretizations of
+ * heat-type equations lead at every time level to the system solved here):
+ *
+ *   C (u^{m+1} - u^m) / tau + A_diff u^{m+1} = F,   tau = 1 / react,
+ *
+ * A_diff = sum_d diff[d] 4 h_d^-2 C_1 x .. x A_d x .. x C_N and
+ * C = C_1 x ... x C_N, i.e. (A_diff + react C) u^{m+1} = F + react C u^m.
+ * Each of the nsteps steps is one mass apply (F + react C u^m into work, in
+ * double-double arithmetic) and one fftfem_solve (the plan's precision mode);
+ * the plan (tables, workspace) is reused by every step.
+ * u: in/out, u^0 on entry, u^nsteps on return, layout and right-hand-side
+ * sets as in fftfem_solve; F: the scaled load (nrhs sets), constant in time,
+ * or NULL for zero; work: caller-owned device array of the size of u.  u,
+ * work and F must not overlap.  Asynchronous on s.  EINVAL: null plan, u or
+ * work, nsteps < 0, react <= 0, overlapping arrays, or a plan that belongs
+ * to a batch being recorded; otherwise the status of the first failing step.
+ */
+int fftfem_implicit_euler(fftfem_plan_t p, const double* F, double* u, double* work, int nsteps,
+                          hipStream_t s);
+
+/*
  * fftfem_tune: the measurement FFTFEM_BATCH_TUNE makes, for the line passes
  * of one plan with N >= 2 (float32, float32 with refinement or float64): each
  * of the 2N - 1 passes of the solve (forward along axes N-1 .. 1, the middle

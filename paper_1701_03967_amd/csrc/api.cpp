@@ -485,6 +485,29 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
                     nullptr, flag, s);
 }
 
+// out = F + scale C u with C = C_1 x ... x C_N (F may be null), in
+// double-double arithmetic (one right-hand side).
+int mass_apply(fftfem_plan_t p, const double* u, const double* F, double* out, double scale, hipStream_t s) {
+  double** T = p->tmp;
+  const DDp none{nullptr, nullptr};
+  const double cC[4] = {0, 1, 0, 0};
+  // F - (-scale) C u, or scale C u without F
+  const double last[4] = {0, F ? -scale : scale, 0, 0};
+  int rc;
+  p->phase = 0;
+  if (p->N == 1)
+    return apply_pass(p, 0, {u, nullptr}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
+  rc = apply_pass(p, p->N - 1, {u, nullptr}, none, nullptr, T[0], T[1], 2, nullptr, nullptr, cC, nullptr, nullptr,
+                  s);
+  if (rc) return rc;
+  if (p->N == 3) {
+    rc = apply_pass(p, 1, {T[0], T[1]}, none, nullptr, T[4], T[5], 2, nullptr, nullptr, cC, nullptr, nullptr, s);
+    if (rc) return rc;
+    return apply_pass(p, 0, {T[4], T[5]}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
+  }
+  return apply_pass(p, 0, {T[0], T[1]}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
+}
+
 // r <- r - A c in plain float64 (N >= 2): the residual of u + c from the
 // residual r of u, for a correction c that is small next to u (rounding of
 // A c is then far below the refinement's target).  c is read from tmp[1];
@@ -907,6 +930,23 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
         rc = from_hip(launch_reduce(p->partials, p->nparts_last, it, p->desc.tol, flag, st, s));
       }
     }
+  }
+  return rc;
+}
+
+int fftfem_implicit_euler(fftfem_plan_t p, const double* F, double* u, double* work, int nsteps, hipStream_t s) {
+  if (!p || !u || !work || nsteps < 0) return FFTFEM_EINVAL;
+  if (!(p->desc.react > 0) || p->rec) return FFTFEM_EINVAL;
+  const size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
+  if (overlap(u, work, bytes) || (F && (overlap(F, work, bytes) || overlap(F, u, bytes)))) return FFTFEM_EINVAL;
+  const double react = p->desc.react;
+  int rc = FFTFEM_OK;
+  for (int m = 0; m < nsteps && !rc; ++m) {
+    for (int r = 0; r < p->nrhs && !rc; ++r) {
+      const size_t o = (size_t)r * p->size;
+      rc = mass_apply(p, u + o, F ? F + o : nullptr, work + o, react, s);
+    }
+    if (!rc) rc = fftfem_solve(p, work, u, s);
   }
   return rc;
 }

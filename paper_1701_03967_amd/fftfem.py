@@ -29,7 +29,7 @@ EXPORTS = [
     "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
-    "fftfem_destroy_batch", "fftfem_tune",
+    "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler",
 ]
 BATCH_TUNE = 1
 
@@ -105,6 +105,7 @@ def lib():
         L.fftfem_destroy_batch.argtypes = [vp]
         L.fftfem_destroy_batch.restype = None
         L.fftfem_tune.argtypes = [vp, vp]
+        L.fftfem_implicit_euler.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
         _lib = L
     return _lib
 
@@ -290,6 +291,21 @@ class Plan:
         self._check_tensor(y, "y")
         _check(lib().fftfem_apply_A(self._h, _tptr(u), _tptr(y), _stream_ptr(stream)), "fftfem_apply_A")
         return y
+
+    def implicit_euler(self, u, nsteps: int, F=None, work=None, stream=None):
+        """nsteps implicit Euler steps of C du/dt + A_diff u = F with
+        tau = 1/react, in place on u (float64 device tensor); F: constant load
+        or None; work: scratch of u's shape (allocated when None)."""
+        import torch
+        self._check_tensor(u, "u")
+        if F is not None:
+            self._check_tensor(F, "F")
+        if work is None:
+            work = torch.empty_like(u)
+        self._check_tensor(work, "work")
+        _check(lib().fftfem_implicit_euler(self._h, _tptr(F) if F is not None else None, _tptr(u), _tptr(work),
+                                           int(nsteps), _stream_ptr(stream)), "fftfem_implicit_euler")
+        return u
 
     def tune(self, stream=None):
         """Measures this plan's line-pass parameters (2D plans; the choice is
