@@ -257,6 +257,52 @@ def run_batch(args, torch, fm):
     print(json.dumps(line))
 
 
+def run_heat(args, torch, fm):
+    """Implicit Euler time stepping on the C3 mesh (2D, n = 9, K = 1024,
+    diff (1, 1)) with tau = 1e-3 (react = 1000, the batched workload's heat
+    step): u^0 and the load drawn N(0,1) on the device from seeded
+    generators; each step is one double-double mass apply and one solve with
+    the reused plan (float64).  Value: unknowns advanced per second."""
+    prob = inputs.WORKLOADS["c3_2d_n9_k1024"].problem
+    react = 1000.0
+    plan = fm.Plan(prob.K, prob.n, prob.diff, react, precision=args.heat_precision,
+                   max_iter=3 if args.heat_precision == "fp32_refine" else 0, tol=1e-12)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    u = torch.randn(prob.shape, generator=g, dtype=torch.float64, device="cuda")
+    F = torch.randn(prob.shape, generator=g, dtype=torch.float64, device="cuda")
+    work = torch.empty_like(u)
+    nsteps = args.heat_steps
+    plan.implicit_euler(u, args.warmup, F=F, work=work)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.implicit_euler(u, nsteps, F=F, work=work)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    line = {
+        "metric": "implicit Euler heat steps: unknowns advanced per second",
+        "value": prob.size * nsteps / (ms * 1e-3),
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.heat_precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "heat_c3_2d_n9_k1024_tau1e-3", "unknowns": prob.size, "react": react,
+                   "time_steps_per_step": nsteps, "precision": args.heat_precision},
+        "ms_per_time_step": ms / nsteps,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +317,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
     ap.add_argument("--batch-precision", default="fp32_refine", choices=("fp32_refine", "fp64", "fp32"),
                     help="c5_batch: precision mode of every problem")
+    ap.add_argument("--heat-steps", type=int, default=10, help="heat: implicit Euler steps per timed step")
+    ap.add_argument("--heat-precision", default="fp64", choices=("fp64", "fp32_refine", "fp32"))
     ap.add_argument("--tune", action="store_true", help="measure line-pass parameters first (N >= 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
@@ -283,6 +331,9 @@ def main():
     fm.lib()
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration)
+    if args.workload == "heat":
+        run_heat(args, torch, fm)
+        return
     if args.workload == "c5_batch":
         run_batch(args, torch, fm)
         return

@@ -208,7 +208,7 @@ void fftfem_destroy_batch(fftfem_batch_t b);
  * A_diff = sum_d diff[d] 4 h_d^-2 C_1 x .. x A_d x .. x C_N and
  * C = C_1 x ... x C_N, i.e. (A_diff + react C) u^{m+1} = F + react C u^m.
  * Each of the nsteps steps is one mass apply (F + react C u^m into work, in
- * double-double arithmetic) and one fftfem_solve (the plan's precision mode);
+ * float64) and one fftfem_solve (the plan's precision mode);
  * the plan (tables, workspace) is reused by every step.
  * u: in/out, u^0 on entry, u^nsteps on return, layout and right-hand-side
  * sets as in fftfem_solve; F: the scaled load (nrhs sets), constant in time,

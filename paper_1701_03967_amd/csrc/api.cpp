@@ -485,8 +485,10 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
                     nullptr, flag, s);
 }
 
-// out = F + scale C u with C = C_1 x ... x C_N (F may be null), in
-// double-double arithmetic (one right-hand side).
+// out = F + scale C u with C = C_1 x ... x C_N (F may be null), in plain
+// float64 (one right-hand side; no cancellation: the mass is positive
+// definite and well conditioned, so float64 rounding of C u is at the level
+// of the representation of F).
 int mass_apply(fftfem_plan_t p, const double* u, const double* F, double* out, double scale, hipStream_t s) {
   double** T = p->tmp;
   const DDp none{nullptr, nullptr};
@@ -496,16 +498,20 @@ int mass_apply(fftfem_plan_t p, const double* u, const double* F, double* out, d
   int rc;
   p->phase = 0;
   if (p->N == 1)
-    return apply_pass(p, 0, {u, nullptr}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
-  rc = apply_pass(p, p->N - 1, {u, nullptr}, none, nullptr, T[0], T[1], 2, nullptr, nullptr, cC, nullptr, nullptr,
-                  s);
+    return apply_pass(p, 0, {u, nullptr}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s,
+                      false);
+  rc = apply_pass(p, p->N - 1, {u, nullptr}, none, nullptr, T[0], nullptr, 1, nullptr, nullptr, cC, nullptr,
+                  nullptr, s, false);
   if (rc) return rc;
   if (p->N == 3) {
-    rc = apply_pass(p, 1, {T[0], T[1]}, none, nullptr, T[4], T[5], 2, nullptr, nullptr, cC, nullptr, nullptr, s);
+    rc = apply_pass(p, 1, {T[0], nullptr}, none, nullptr, T[4], nullptr, 1, nullptr, nullptr, cC, nullptr, nullptr,
+                    s, false);
     if (rc) return rc;
-    return apply_pass(p, 0, {T[4], T[5]}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
+    return apply_pass(p, 0, {T[4], nullptr}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s,
+                      false);
   }
-  return apply_pass(p, 0, {T[0], T[1]}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s);
+  return apply_pass(p, 0, {T[0], nullptr}, none, F, out, nullptr, 1, nullptr, nullptr, last, nullptr, nullptr, s,
+                    false);
 }
 
 // r <- r - A c in plain float64 (N >= 2): the residual of u + c from the
