@@ -32,6 +32,18 @@ from .element import element_matrices, element_matrices_ld
 from .fem1d import apply_elementwise, assemble, dense_eigen
 
 
+def orders(n, N: int):
+    """Per-axis element orders n = (n_1, ..., n_N) (Sect. 4 builds the space
+    as a tensor product of 1D spaces of orders n_i); an int means the same
+    order on every axis."""
+    if isinstance(n, (int, np.integer)):
+        return [int(n)] * N
+    ns = [int(x) for x in n]
+    if len(ns) != N:
+        raise ValueError("one element order per axis")
+    return ns
+
+
 def _h(K, X):
     X = [1.0] * len(K) if X is None else list(X)
     return [x / k for x, k in zip(X, K)]
@@ -47,7 +59,7 @@ def mode_product(B: np.ndarray, u: np.ndarray, axis: int) -> np.ndarray:
     return np.moveaxis(np.tensordot(B, u, axes=([1], [axis])), 0, axis)
 
 
-def apply_A(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+def apply_A(u: np.ndarray, n, K: Sequence[int], diff: Sequence[float], react: float,
             X=None, extended: bool = False) -> np.ndarray:
     """y = A u, by element-wise 1D operators along each axis.
 
@@ -55,28 +67,28 @@ def apply_A(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], reac
     arithmetic are x87 extended precision (np.longdouble) and the result is
     returned in that precision.
     """
+    N = len(K)
     if extended:
-        A, C = element_matrices_ld(n)
+        mats = [element_matrices_ld(m) for m in orders(n, N)]
         u = u.astype(np.longdouble)
     else:
-        A, C = element_matrices(n)
-    N = len(K)
+        mats = [element_matrices(m) for m in orders(n, N)]
     coef = coefficients(K, diff, X)
     y = np.zeros_like(u)
     for d in range(N):
         t = u
         for e in range(N):
-            t = apply_elementwise(A if e == d else C, t, e)
+            t = apply_elementwise(mats[e][0] if e == d else mats[e][1], t, e)
         y += coef[d] * t
     if react != 0.0:
         t = u
         for e in range(N):
-            t = apply_elementwise(C, t, e)
+            t = apply_elementwise(mats[e][1], t, e)
         y += react * t
     return y
 
 
-def apply_A_exact(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+def apply_A_exact(u: np.ndarray, n, K: Sequence[int], diff: Sequence[float], react: float,
                   X=None) -> np.ndarray:
     """y = A u in exact rational arithmetic, returned correctly rounded to float64.
 
@@ -88,10 +100,11 @@ def apply_A_exact(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float]
     """
     from fractions import Fraction
     from .element import element_matrices_exact
-    Ae, Ce = element_matrices_exact(n)
-    A = np.array(Ae, dtype=object)
-    C = np.array(Ce, dtype=object)
     N = len(K)
+    mats = []
+    for m in orders(n, N):
+        Ae, Ce = element_matrices_exact(m)
+        mats.append((np.array(Ae, dtype=object), np.array(Ce, dtype=object)))
     Xs = [1.0] * N if X is None else list(X)
     coef = [Fraction(diff[d]) * 4 * (Fraction(K[d]) / Fraction(Xs[d])) ** 2 for d in range(N)]
     uq = np.vectorize(Fraction, otypes=[object])(np.asarray(u, dtype=np.float64))
@@ -99,12 +112,12 @@ def apply_A_exact(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float]
     for d in range(N):
         t = uq
         for e in range(N):
-            t = apply_elementwise(A if e == d else C, t, e)
+            t = apply_elementwise(mats[e][0] if e == d else mats[e][1], t, e)
         y = y + coef[d] * t
     if react != 0.0:
         t = uq
         for e in range(N):
-            t = apply_elementwise(C, t, e)
+            t = apply_elementwise(mats[e][1], t, e)
         y = y + Fraction(react) * t
     return np.vectorize(float, otypes=[np.float64])(y)
 
@@ -112,14 +125,14 @@ def apply_A_exact(u: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float]
 class EigenSolver:
     """u = A^{-1} f by per-axis dense eigendecomposition, plus refinement."""
 
-    def __init__(self, n: int, K: Sequence[int], diff: Sequence[float], react: float, X=None):
+    def __init__(self, n, K: Sequence[int], diff: Sequence[float], react: float, X=None):
         self.n, self.K, self.diff, self.react, self.X = n, tuple(K), tuple(diff), react, X
         cache = {}
         self.lam, self.S = [], []
-        for k in self.K:
-            if k not in cache:
-                cache[k] = dense_eigen(n, k)
-            lam, S = cache[k]
+        for m, k in zip(orders(n, len(self.K)), self.K):
+            if (m, k) not in cache:
+                cache[(m, k)] = dense_eigen(m, k)
+            lam, S = cache[(m, k)]
             self.lam.append(lam)
             self.S.append(S)
         coef = coefficients(self.K, self.diff, X)
@@ -169,7 +182,7 @@ class EigenSolver:
         return u
 
 
-def solve(f: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+def solve(f: np.ndarray, n, K: Sequence[int], diff: Sequence[float], react: float,
           X=None, max_refine: int = 6) -> np.ndarray:
     """u = A^{-1} f (float64, with refinement).  f may carry a leading RHS axis."""
     s = EigenSolver(n, K, diff, react, X)
@@ -178,12 +191,13 @@ def solve(f: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react:
     return s.solve(f, max_refine)
 
 
-def assemble_full(n: int, K: Sequence[int], diff: Sequence[float], react: float, X=None):
+def assemble_full(n, K: Sequence[int], diff: Sequence[float], react: float, X=None):
     """The full N-D matrix via Kronecker products (tiny meshes only)."""
-    ops = [assemble(n, k) for k in K]
-    coef = coefficients(K, diff, X)
     N = len(K)
-    size = int(np.prod([n * k - 1 for k in K]))
+    ns = orders(n, N)
+    ops = [assemble(m, k) for m, k in zip(ns, K)]
+    coef = coefficients(K, diff, X)
+    size = int(np.prod([m * k - 1 for m, k in zip(ns, K)]))
     Afull = np.zeros((size, size))
     for d in range(N):
         T = np.ones((1, 1))
@@ -198,7 +212,7 @@ def assemble_full(n: int, K: Sequence[int], diff: Sequence[float], react: float,
     return Afull
 
 
-def solve_cholesky(f: np.ndarray, n: int, K: Sequence[int], diff: Sequence[float], react: float,
+def solve_cholesky(f: np.ndarray, n, K: Sequence[int], diff: Sequence[float], react: float,
                    X=None) -> np.ndarray:
     """u = A^{-1} f by dense Cholesky of the assembled N-D matrix."""
     Afull = assemble_full(n, K, diff, react, X)

@@ -369,3 +369,55 @@ def test_exact_apply_galerkin_quadratic(n, K):
     W = [w[0] + w[n] if (g + 1) % n == 0 else w[g % n + 1] for g in range(M)]
     expect = np.array([float(2 * v) for v in W])
     assert np.array_equal(y, expect)
+
+
+# --- per-axis element orders (Sect. 4: the space of orders n = (n_1, ..., n_N))
+
+MIXED = [((2, 4), (4, 3)), ((1, 3), (5, 2)), ((3, 1, 2), (2, 3, 2)), ((9, 2), (2, 3))]
+
+
+@pytest.mark.parametrize("ns,K", MIXED)
+def test_mixed_orders_eigen_solve_matches_cholesky(ns, K):
+    """Per-axis orders: the per-axis eigen solve equals dense Cholesky of the
+    Kronecker-assembled matrix (each axis assembled with its own order)."""
+    N = len(K)
+    diff = (1.0, 0.25, 2.0)[:N]
+    shape = [m * k - 1 for m, k in zip(ns, K)]
+    f = np.random.default_rng(12).standard_normal(shape)
+    u1 = solve.solve(f, ns, K, diff, 0.5)
+    u2 = solve.solve_cholesky(f, ns, K, diff, 0.5)
+    assert np.linalg.norm(u1 - u2) / np.linalg.norm(u2) < 1e-11
+
+
+@pytest.mark.parametrize("ns,K", MIXED)
+def test_mixed_orders_apply_matches_assembly_and_exact(ns, K):
+    """The element-wise operator with per-axis orders equals the assembled
+    Kronecker matrix and, rounded, the exact rational apply."""
+    N = len(K)
+    diff = (1.0, 2.0, 0.5)[:N]
+    shape = [m * k - 1 for m, k in zip(ns, K)]
+    v = np.random.default_rng(6).standard_normal(shape)
+    Afull = solve.assemble_full(ns, K, diff, 0.3)
+    y = solve.apply_A(v, ns, K, diff, 0.3)
+    assert np.allclose(y.reshape(-1), Afull @ v.reshape(-1), rtol=0, atol=1e-10 * np.abs(Afull).max())
+    if np.prod(shape) <= 200:
+        ye = solve.apply_A_exact(v, ns, K, diff, 0.3)
+        assert np.abs(y - ye).max() <= 1e-12 * np.abs(ye).max()
+
+
+def test_mixed_orders_separable_mode():
+    """A product of 1D eigenvectors of each axis's own order solves the
+    system with the summed denominator (dense 1D eigenpairs of the assembled
+    1D pencils, SciPy)."""
+    ns, K, diff, react = (2, 5), (6, 3), (1.0, 0.5), 0.7
+    vecs, lams = [], []
+    for m, k in zip(ns, K):
+        Ag, Cg = fem1d.assemble(m, k)
+        lam, S = scipy.linalg.eigh(Ag, Cg)
+        vecs.append(S[:, 2])
+        lams.append(lam[2])
+    u = np.outer(vecs[0], vecs[1])
+    den = react + sum(d * 4.0 * k * k * l for d, k, l in zip(diff, K, lams))
+    f = den * solve.mode_product(fem1d.assemble(ns[1], K[1])[1], solve.mode_product(fem1d.assemble(ns[0], K[0])[1], u, 0), 1)
+    got = solve.solve(f, ns, K, diff, react)
+    assert np.linalg.norm(got - u) / np.linalg.norm(u) < 1e-12
