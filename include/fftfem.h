@@ -19,11 +19,12 @@
  * (Sect. 3, Theorem 2; Sect. 4, algorithm (a)).
  *
  * Array layout (f, u, y): dense row-major float64 of shape (M_1, ..., M_N),
- * M_d = n*K_d - 1, last axis contiguous, optionally with a leading dimension
- * of nrhs.  Along axis d, 0-based index g is the dof at x = (g+1) h_d / n:
- * mesh node j = (g+1)/n when (g+1) % n == 0, else bubble l = g % n + 1 of
- * element j = g / n + 1 (the ordering of S_K^(n), Sect. 2).  Boundary dofs
- * are not stored.
+ * M_d = n_d*K_d - 1 with n_d the element order of axis d (Sect. 4 allows an
+ * order per axis; by default n_d = n), last axis contiguous, optionally with
+ * a leading dimension of nrhs.  Along axis d (order n = n_d), 0-based index g
+ * is the dof at x = (g+1) h_d / n: mesh node j = (g+1)/n when
+ * (g+1) % n == 0, else bubble l = g % n + 1 of element j = g / n + 1 (the
+ * ordering of S_K^(n), Sect. 2).  Boundary dofs are not stored.
  *
  * Pointers named "device" must point to memory allocated on the current HIP
  * device; everything else is host memory.  All functions return an int
@@ -70,7 +71,7 @@ enum {
 typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
   int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above) */
-  int n;                          /* element order, 1..FFTFEM_MAX_ORDER */
+  int n;                          /* element order (every axis without n_axis), 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */
   double X[FFTFEM_MAX_DIMS];      /* domain lengths (0 -> 1.0) */
@@ -79,6 +80,8 @@ typedef struct {
   double tol;                     /* refinement stop: ||correction||/||u|| <= tol (0 -> 1e-12) */
   int nrhs;                       /* right-hand sides per solve (0 -> 1) */
   unsigned flags;                 /* reserved, must be 0 */
+  int n_axis[FFTFEM_MAX_DIMS];    /* element order per axis (Sect. 4: n = (n_1, ..., n_N));
+                                     0 -> n; M_d = n_axis[d] K[d] - 1 */
 } fftfem_desc;
 
 /* Refinement statistics of the last fftfem_solve on a plan. */

@@ -41,8 +41,9 @@ struct fftfem_plan_s {
   double coef[3] = {0, 0, 0};
   std::vector<AxisTables> host;
   DevTables dev[3];
-  double* Ael = nullptr;
-  double* Cel = nullptr;
+  int nd[3] = {0, 0, 0};     // element order per axis
+  double* Ael[3] = {};       // per-axis element matrices, hi then lo parts
+  double* Cel[3] = {};
   float* W32 = nullptr;      // float32 workspace (float32 modes)
   float* W32b = nullptr;     // second float32 workspace (transposed 2D schedule)
   double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
@@ -166,6 +167,8 @@ int validate(const fftfem_desc* d) {
   if (!d) return FFTFEM_EINVAL;
   if (d->N < 1 || d->N > FFTFEM_MAX_DIMS) return FFTFEM_EINVAL;
   if (d->n < 1 || d->n > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
+  for (int i = 0; i < d->N; ++i)
+    if (d->n_axis[i] < 0 || d->n_axis[i] > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
   if (d->flags != 0) return FFTFEM_EINVAL;
   if (d->precision < FFTFEM_FP64 || d->precision > FFTFEM_FP32_REFINE) return FFTFEM_EINVAL;
   if (d->max_iter < 0 || d->max_iter > FFTFEM_MAX_ITERS) return FFTFEM_EINVAL;
@@ -191,16 +194,16 @@ int64_t fft_len(int64_t K) {
 int64_t tune_class_of(int64_t K) { return 2 * fft_len(K) + ((K & (K - 1)) ? 1 : 0); }
 
 
-size_t line_lds(const fftfem_plan_s* p, int64_t K, size_t elt, bool pad = true) {
-  return (size_t)(1 + p->n / 2) * (fft_len(K) + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
+size_t line_lds(int n, int64_t K, size_t elt, bool pad = true) {
+  return (size_t)(1 + n / 2) * (fft_len(K) + (pad ? 1 : 0)) * 2 * elt;  // pad slot per FFT buffer
 }
 
 // Lines per workgroup for a line pass: a power of two with G * K <= 1024
 // (per-thread task registers), G lines of LDS within the budget (64 KB, or
 // one line when a line alone is larger), at most 64 and at most nlines.
-int choose_G(const fftfem_plan_s* p, int64_t K, size_t elt, int64_t nlines) {
-  size_t per = line_lds(p, K, elt);
-  size_t budget = std::max<size_t>(line_lds(p, K, elt, false), 65536);
+int choose_G(int n, int64_t K, size_t elt, int64_t nlines) {
+  size_t per = line_lds(n, K, elt);
+  size_t budget = std::max<size_t>(line_lds(n, K, elt, false), 65536);
   int G = 1;
   while (G < 64 && (size_t)(2 * G) * per <= budget && 2 * G * K <= kLineTasks && 2 * G <= nlines)
     G *= 2;
@@ -328,7 +331,8 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.nlines = gm.nlines;
   a.ies = gm.ies;
   a.oes = gm.oes;
-  a.G = choose_G(p, t.K, sizeof(T), a.nlines);
+  const int n = p->nd[gm.axis];
+  a.G = choose_G(n, t.K, sizeof(T), a.nlines);
   a.lrmax = 4;
   {
     TuneVal tv;
@@ -336,7 +340,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
     if (p->Gforce) {
       a.G = p->Gforce;
       a.lrmax = p->lrforce;
-    } else if (tune_get(TuneKey{(int)sizeof(T), p->n, mode, lf ? 1 : 0, tune_class(t.K)}, &tv)) {
+    } else if (tune_get(TuneKey{(int)sizeof(T), n, mode, lf ? 1 : 0, tune_class(t.K)}, &tv)) {
       a.G = tv.G;
       a.lrmax = tv.lrmax;
     }
@@ -363,19 +367,19 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   }
   a.partials = want_partials ? p->partials : nullptr;
   a.flag = flag;
-  size_t lds = (size_t)a.G * line_lds(p, t.K, sizeof(T), a.G > 1);
+  size_t lds = (size_t)a.G * line_lds(n, t.K, sizeof(T), a.G > 1);
   if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
   if (want_partials && nblocks > p->npartials) return FFTFEM_ENOTIMPL;
   if (want_partials) p->nparts_last = (int)nblocks;
   if (p->rec) {
     record(p, sizeof(T) == 4 ? REC_LINE32 : REC_LINE64,
-           {p->n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, a.L == 0 ? 1 : 0}, a, nblocks, lds);
+           {n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, a.L == 0 ? 1 : 0}, a, nblocks, lds);
     return FFTFEM_OK;
   }
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +
                     "_ax" + std::to_string(gm.axis) + (gm.es == 1 && gm.axis != p->N - 1 ? "t" : ""));
-  return from_hip(launch_line<T>(p->n, mode, upd != nullptr, a, (int)nblocks, lds, s));
+  return from_hip(launch_line<T>(n, mode, upd != nullptr, a, (int)nblocks, lds, s));
 }
 
 template <typename T>
@@ -429,21 +433,22 @@ int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, voi
     a.G = 4;
     a.TL = 512;
   }
-  const int XX = (p->n + 1) * (p->n + 1);
-  a.Ael[0] = p->Ael;
-  a.Ael[1] = p->Ael + XX;
-  a.Cel[0] = p->Cel;
-  a.Cel[1] = p->Cel + XX;
+  const int n = p->nd[axis];
+  const int XX = (n + 1) * (n + 1);
+  a.Ael[0] = p->Ael[axis];
+  a.Ael[1] = p->Ael[axis] + XX;
+  a.Cel[0] = p->Cel[axis];
+  a.Cel[1] = p->Cel[axis] + XX;
   a.flag = flag;
-  int64_t W = a.TL + 2 * p->n;
+  int64_t W = a.TL + 2 * n;
   size_t lds = (size_t)planes * a.G * W * sizeof(double);
   int64_t nblocks = ((a.nlines + a.G - 1) / a.G) * ((a.M + a.TL - 1) / a.TL);
   if (p->rec) {
-    record(p, REC_APPLY, {p->n, in1.l ? 1 : 0, dd ? 1 : 0}, a, nblocks, lds);
+    record(p, REC_APPLY, {n, in1.l ? 1 : 0, dd ? 1 : 0}, a, nblocks, lds);
     return FFTFEM_OK;
   }
   Timed tm(p, s, std::string(dd ? "apply_ax" : "apply64_ax") + std::to_string(axis));
-  return from_hip(launch_apply(p->n, a, (int)nblocks, lds, s));
+  return from_hip(launch_apply(n, a, (int)nblocks, lds, s));
 }
 
 // y = A u (out_kind 1) or r = f - A u (f non-null; out_kind 0 stores it as
@@ -677,7 +682,7 @@ Geom tune_geom(fftfem_plan_t p, int pass) {
 int64_t max_blocks_last_pass(const fftfem_plan_s* p, size_t elt) {
   int axis = p->N - 1;
   int64_t nlines = p->size / p->M[axis];
-  int G = choose_G(p, p->K[axis], elt, nlines);
+  int G = choose_G(p->nd[axis], p->K[axis], elt, nlines);
   return (nlines + G - 1) / G;
 }
 
@@ -721,7 +726,10 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   if (d.nrhs == 0) d.nrhs = 1;
   for (int i = 0; i < d.N; ++i)
     if (d.X[i] == 0) d.X[i] = 1.0;
-  if (d.n > kMaxLineOrder) return FFTFEM_ENOTIMPL;
+  for (int i = 0; i < d.N; ++i)
+    if (d.n_axis[i] == 0) d.n_axis[i] = d.n;
+  for (int i = 0; i < d.N; ++i)
+    if (d.n_axis[i] > kMaxLineOrder) return FFTFEM_ENOTIMPL;
   // a line-kernel tile holds at most kLineTasks element tasks
   for (int i = 0; i < d.N; ++i)
     if (d.K[i] > kLineTasks) return FFTFEM_ENOTIMPL;
@@ -733,8 +741,9 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   p->nrhs = d.nrhs;
   p->size = 1;
   for (int i = 0; i < d.N; ++i) {
+    p->nd[i] = d.n_axis[i];
     p->K[i] = d.K[i];
-    p->M[i] = (int64_t)d.n * d.K[i] - 1;
+    p->M[i] = (int64_t)p->nd[i] * d.K[i] - 1;
     p->size *= p->M[i];
   }
   for (int i = 0; i < d.N; ++i) {
@@ -743,21 +752,22 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   }
   // tables (identical axes are computed once)
   p->host.resize(d.N);
-  std::map<int64_t, int> seen;
+  std::map<std::pair<int, int64_t>, int> seen;
   for (int i = 0; i < d.N; ++i) {
-    auto it = seen.find(d.K[i]);
+    const std::pair<int, int64_t> key{p->nd[i], d.K[i]};
+    auto it = seen.find(key);
     if (it != seen.end()) {
       p->host[i] = p->host[it->second];
-    } else if (cache && cache->get(d.n, d.K[i], &p->host[i])) {
-      seen[d.K[i]] = i;
+    } else if (cache && cache->get(p->nd[i], d.K[i], &p->host[i])) {
+      seen[key] = i;
     } else {
-      rc = build_axis_tables(d.n, d.K[i], 1.0, 1.0, &p->host[i]);
+      rc = build_axis_tables(p->nd[i], d.K[i], 1.0, 1.0, &p->host[i]);
       if (rc) {
         delete p;
         return rc;
       }
-      if (cache) cache->put(d.n, d.K[i], p->host[i]);
-      seen[d.K[i]] = i;
+      if (cache) cache->put(p->nd[i], d.K[i], p->host[i]);
+      seen[key] = i;
     }
     p->coef[i] = d.diff[i] * 4.0 * ((double)d.K[i] / d.X[i]) * ((double)d.K[i] / d.X[i]);
     p->host[i].coef = p->coef[i];
@@ -787,14 +797,15 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     std::vector<double> mu(t.lam.size());
     for (size_t c = 0; c < mu.size(); ++c) mu[c] = p->coef[i] * t.lam[c];
     // Q in structure-of-arrays order for the kernels: (c, l, k) -> (c n + l) K + k
+    const int n = p->nd[i];
     std::vector<double> qs(t.Q.size());
     for (int64_t k = 0; k < t.K; ++k)
-      for (int c = 0; c < d.n; ++c)
-        for (int l = 0; l < d.n; ++l)
-          qs[(size_t)(c * d.n + l) * t.K + k] = t.Q[(size_t)k * d.n * d.n + c * d.n + l];
+      for (int c = 0; c < n; ++c)
+        for (int l = 0; l < n; ++l)
+          qs[(size_t)(c * n + l) * t.K + k] = t.Q[(size_t)k * n * n + c * n + l];
     // condensed-solve constants with the stiffness parts scaled like mu
     std::vector<double> arrow = t.arrow;
-    const ArrowLayout al(d.n);
+    const ArrowLayout al(n);
     for (int m = 0; m < al.nb; ++m) {
       arrow[al.nu + m] *= p->coef[i];
       arrow[al.gA + m] *= p->coef[i];
@@ -807,16 +818,16 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
       if (!rc) rc = upload<float>(p, &p->dev[i].f[w], *src[w]);
     }
   }
-  if (!rc) {
+  for (int i = 0; i < d.N && !rc; ++i) {
     std::vector<double> A, C;
-    element_matrices_dd(d.n, &A, &C);
-    rc = upload<double>(p, &p->Ael, A);
-    if (!rc) rc = upload<double>(p, &p->Cel, C);
+    element_matrices_dd(p->nd[i], &A, &C);
+    rc = upload<double>(p, &p->Ael[i], A);
+    if (!rc) rc = upload<double>(p, &p->Cel[i], C);
   }
   // workspace
   size_t elt = d.precision == FFTFEM_FP64 ? sizeof(double) : sizeof(float);
   if (d.N == 2) {
-    int G0 = choose_G(p, p->K[0], elt, p->size / p->M[0]);
+    int G0 = choose_G(p->nd[0], p->K[0], elt, p->size / p->M[0]);
     p->tr2d = (size_t)G0 * elt < 64;
     // float64: the axis-1 passes store and load the transposed layout
     // themselves (measured at n = 9, K = 1024: 3.38 ms against 3.54 ms with
@@ -1071,13 +1082,13 @@ int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info) {
   const Geom g = tune_geom(p, pass);
   const int64_t K = p->K[g.axis];
   info->elt = p->desc.precision == FFTFEM_FP64 ? (int)sizeof(double) : (int)sizeof(float);
-  info->n = p->n;
+  info->n = p->nd[g.axis];
   info->mode = chain_mode(p, pass);
   info->lf = g.es > 1 ? 1 : 0;
   info->K = K;
   int G = 1;
   while (G < 64 && 2 * G * K <= kLineTasks && 2 * G <= g.nlines &&
-         (size_t)(2 * G) * line_lds(p, K, info->elt) <= (size_t)p->lds_max)
+         (size_t)(2 * G) * line_lds(info->n, K, info->elt) <= (size_t)p->lds_max)
     G *= 2;
   info->Gmax = G;
   return FFTFEM_OK;

@@ -53,6 +53,7 @@ class Desc(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("nrhs", ctypes.c_int),
         ("flags", ctypes.c_uint),
+        ("n_axis", ctypes.c_int * MAX_DIMS),
     ]
 
 
@@ -147,16 +148,29 @@ def _tptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(K: Sequence[int], n: int, diff: Sequence[float], react: float = 0.0,
+def orders(n, N: int):
+    """Element order per axis: an int (every axis) or a sequence of N ints."""
+    if isinstance(n, (int, np.integer)):
+        return (int(n),) * N
+    ns = tuple(int(x) for x in n)
+    if len(ns) != N:
+        raise ValueError("one element order per axis")
+    return ns
+
+
+def make_desc(K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
               X: Optional[Sequence[float]] = None, precision: str = "fp64", max_iter: int = 0,
               tol: float = 0.0, nrhs: int = 1) -> "Desc":
+    """n: one element order for every axis, or one per axis."""
     d = Desc()
     d.N = len(K)
+    ns = orders(n, d.N)
     for i, k in enumerate(K):
         d.K[i] = int(k)
         d.diff[i] = float(diff[i])
         d.X[i] = float(X[i]) if X is not None else 0.0
-    d.n = int(n)
+        d.n_axis[i] = ns[i]
+    d.n = ns[0]
     d.react = float(react)
     d.precision = PRECISIONS[precision]
     d.max_iter = int(max_iter)
@@ -184,7 +198,7 @@ class Batch:
         for i, pr in enumerate(problems):
             descs[i] = make_desc(**pr)
             nrhs = int(pr.get("nrhs", 1))
-            shape = tuple(int(pr["n"]) * int(k) - 1 for k in pr["K"])
+            shape = tuple(m * int(k) - 1 for m, k in zip(orders(pr["n"], len(pr["K"])), pr["K"]))
             self.shapes.append(((nrhs,) if nrhs > 1 else ()) + shape)
         h = ctypes.c_void_p()
         _check(lib().fftfem_plan_batch(ctypes.byref(h), len(problems), descs, BATCH_TUNE if tune else 0),
@@ -229,28 +243,18 @@ class Batch:
 class Plan:
     """A solver plan: fixed sizes, coefficients and precision mode."""
 
-    def __init__(self, K: Sequence[int], n: int, diff: Sequence[float], react: float = 0.0,
+    def __init__(self, K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
                  X: Optional[Sequence[float]] = None, precision: str = "fp64",
                  max_iter: int = 0, tol: float = 0.0, nrhs: int = 1):
-        d = Desc()
-        d.N = len(K)
-        for i, k in enumerate(K):
-            d.K[i] = int(k)
-            d.diff[i] = float(diff[i])
-            d.X[i] = float(X[i]) if X is not None else 0.0
-        d.n = int(n)
-        d.react = float(react)
-        d.precision = PRECISIONS[precision]
-        d.max_iter = int(max_iter)
-        d.tol = float(tol)
-        d.nrhs = int(nrhs)
+        d = make_desc(K, n, diff, react, X, precision, max_iter, tol, nrhs)
         h = ctypes.c_void_p()
         _check(lib().fftfem_plan_ex(ctypes.byref(h), ctypes.byref(d)), "fftfem_plan_ex")
         self._h = h
         self.K = tuple(int(k) for k in K)
-        self.n = int(n)
+        self.orders = orders(n, len(self.K))
+        self.n = n if isinstance(n, (int, np.integer)) else self.orders
         self.nrhs = int(nrhs)
-        self.shape = tuple(self.n * k - 1 for k in self.K)
+        self.shape = tuple(m * k - 1 for m, k in zip(self.orders, self.K))
         self.precision = precision
 
     def close(self):
@@ -322,9 +326,10 @@ class Plan:
         M = self.shape[axis]
         K = self.K[axis]
         lam = np.zeros(M)
-        Q = np.zeros(K * self.n * self.n)
+        m = self.orders[axis]
+        Q = np.zeros(K * m * m)
         _check(lib().fftfem_plan_tables(self._h, axis, _dptr(lam), _dptr(Q)), "fftfem_plan_tables")
-        return lam, Q.reshape(K, self.n, self.n)
+        return lam, Q.reshape(K, m, m)
 
     def set_timing(self, enable: bool = True):
         _check(lib().fftfem_set_timing(self._h, int(enable)), "fftfem_set_timing")

@@ -49,6 +49,8 @@ def _plan_ex(**kw):
     d.max_iter = kw.get("max_iter", 0)
     d.nrhs = kw.get("nrhs", 1)
     d.flags = kw.get("flags", 0)
+    for i, v in enumerate(kw.get("n_axis", ())):
+        d.n_axis[i] = v
     h = ctypes.c_void_p()
     rc = fftfem.lib().fftfem_plan_ex(ctypes.byref(h), ctypes.byref(d))
     return rc, h
@@ -59,6 +61,7 @@ def _plan_ex(**kw):
     ({"diff": (0.0, 1.0)}, -1), ({"diff": (1.0, -2.0)}, -1), ({"precision": 7}, -1),
     ({"flags": 1}, -1), ({"max_iter": 99}, -1), ({"react": float("nan")}, -1),
     ({"K": (1025, 8)}, -7), ({"n": 12}, -7), ({"K": (4096, 8)}, -7), ({"K": (2048, 8)}, -7),
+    ({"n_axis": (2, -1)}, -1), ({"n_axis": (17, 2)}, -1), ({"n_axis": (2, 10)}, -7), ({"n": 12, "n_axis": (3, 12)}, -7),
 ])
 def test_invalid_arguments_rejected_on_host(kw, code):
     rc, h = _plan_ex(**kw)
