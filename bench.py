@@ -303,6 +303,69 @@ def run_heat(args, torch, fm):
     print(json.dumps(line))
 
 
+TRANSFORM_K = {"pow2": (32, 64, 128, 256, 512, 1024), "prime": (31, 61, 127, 257, 509, 1021),
+               "composite": (48, 96, 200, 384, 600, 1000)}
+
+
+def run_transform1d(args, torch, fm):
+    """1D FC_n (forward) and F_n (inverse) transforms, n = 5, along the
+    contiguous axis of a 3D array of about 2^26 dofs (the lines are the other
+    two axes), for element counts that are powers of two, primes and
+    composites (the latter two through chirp-z DFTs); float64.  Per K: the
+    mean time of one transform of all lines, dofs/s and GB/s (one read and one
+    write of 8 bytes per dof)."""
+    n = 5
+    rows = []
+    for kind, Ks in TRANSFORM_K.items():
+        for K in Ks:
+            M = n * K - 1
+            lines = max(1, (1 << 26) // M)
+            k0 = max(2, min(1024, int(round(np.sqrt(lines) / n))))
+            k1 = max(2, min(1024, int(round(lines / (n * k0 - 1) / n))))
+            plan = fm.Plan((k0, k1, K), n, (1.0, 1.0, 1.0), 0.0)
+            g = torch.Generator(device="cuda")
+            g.manual_seed(K)
+            x = torch.randn(plan.shape, generator=g, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            rec = {"kind": kind, "K": K, "lines": plan.shape[0] * plan.shape[1], "dofs": x.numel()}
+            for name, d in (("fc_n", +1), ("f_n", -1)):
+                for _ in range(args.warmup):
+                    plan.debug_transform(2, d, x, y)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    plan.debug_transform(2, d, x, y)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                rec[name] = {"ms": ms, "dofs_per_s": x.numel() / (ms * 1e-3),
+                             "GB_per_s": 16 * x.numel() / (ms * 1e-3) / 1e9}
+            rows.append(rec)
+            print(f"[bench] transform1d {kind} K={K}: fc_n {rec['fc_n']['ms']:.3f} ms, "
+                  f"f_n {rec['f_n']['ms']:.3f} ms ({rec['dofs']} dofs)", file=sys.stderr, flush=True)
+            del plan, x, y
+    fwd = [r["fc_n"]["dofs_per_s"] for r in rows if r["kind"] == "pow2"]
+    line = {
+        "metric": "1D FC_n / F_n transform throughput, n=5 (dofs/s)",
+        "value": float(np.exp(np.mean(np.log(fwd)))),
+        "unit": "dofs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean([r["fc_n"]["ms"] for r in rows])),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "transform1d_n5", "n": 5, "value": "geometric mean of the forward "
+                   "transform over the power-of-two K"},
+        "per_K": rows,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +394,9 @@ def main():
     fm.lib()
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration)
+    if args.workload == "transform1d":
+        run_transform1d(args, torch, fm)
+        return
     if args.workload == "heat":
         run_heat(args, torch, fm)
         return
