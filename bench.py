@@ -116,7 +116,11 @@ def copy_calibration(torch, nbytes: int):
     del a, b
 
 
-def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=False):
+def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=False, graph=False):
+    """Mean and median of `steps` solves (direct launches, events per step,
+    no per-kernel instrumentation), then per-kernel times from a separate
+    instrumented run, and with `graph` the mean of graph replays of one
+    captured solve.  Returns (plan, u, ms, kernels, stats, extra)."""
     plan = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=precision,
                    max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12)
     if tune and prob.N >= 2:
@@ -125,21 +129,46 @@ def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=Fa
     for _ in range(warmup):
         plan.solve(f, u)
     torch.cuda.synchronize()
-    plan.get_timing()
-    plan.set_timing(timing)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         plan.solve(f, u)
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    kt = plan.get_timing() if timing else {}
-    plan.set_timing(False)
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    extra = {"median_ms": float(np.median(per)), "min_ms": float(np.min(per))}
     st = plan.stats()
-    return plan, u, ms, kt, st
+    kt = {}
+    if timing:
+        plan.get_timing()
+        plan.set_timing(True)
+        for _ in range(min(steps, 10)):
+            plan.solve(f, u)
+        torch.cuda.synchronize()
+        kt = plan.get_timing()
+        plan.set_timing(False)
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.solve(f, u)
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.solve(f, u)
+        g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        extra["graph_ms"] = e0.elapsed_time(e1) / steps
+        del g
+    return plan, u, ms, kt, st, extra
 
 
 def cpu_baseline(prob, budget_s: float = 20.0):
@@ -382,6 +411,8 @@ def main():
                     help="c5_batch: precision mode of every problem")
     ap.add_argument("--heat-steps", type=int, default=10, help="heat: implicit Euler steps per timed step")
     ap.add_argument("--heat-precision", default="fp64", choices=("fp64", "fp32_refine", "fp32"))
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of one solve captured in a hipGraph")
     ap.add_argument("--tune", action="store_true", help="measure line-pass parameters first (N >= 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
@@ -415,10 +446,11 @@ def main():
         kts = {}
         for mode in args.modes.split(","):
             steps = args.steps if full else max(5, args.steps // 3)
-            plan, u, ms, kt, st = time_mode(fm, torch, prob, f, mode, steps, args.warmup, tune=args.tune)
+            plan, u, ms, kt, st, extra = time_mode(fm, torch, prob, f, mode, steps, args.warmup, tune=args.tune,
+                                                   graph=args.graph)
             sols[mode] = u.clone()
             kts[mode] = kt
-            rec = {"ms": ms, "unknowns_per_s": prob.size / (ms * 1e-3)}
+            rec = {"ms": ms, "unknowns_per_s": prob.size / (ms * 1e-3), **extra}
             if mode == "fp32_refine":
                 rec["iterations"] = st["iterations"]
                 rec["rel_correction"] = st["rel_correction"]
@@ -452,7 +484,7 @@ def main():
             roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
                     "kernel": name, "symbol": kname, "bytes_per_launch": by, "avg_ms": avg_ms,
-                    "launches_per_step": cnt / args.steps}
+                    "launches_per_step": cnt / min(args.steps, 10)}
     line = {
         "metric": METRIC,
         "value": value,
