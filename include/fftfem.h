@@ -237,6 +237,20 @@ int fftfem_implicit_euler(fftfem_plan_t p, const double* F, double* u, double* w
 int fftfem_tune(fftfem_plan_t p, hipStream_t s);
 
 /*
+ * The process-wide table of measured line-pass parameters as a text file
+ * (one kind per line: bytes per value, n, pass mode, strided, element-count
+ * class, lines per tile, log2 of the largest FFT radix).  fftfem_tune_save
+ * writes the table to `path` and returns the number of entries;
+ * fftfem_tune_load adds the entries of `path` to the table (replacing equal
+ * kinds) and returns their number.  Tuning (fftfem_tune, FFTFEM_BATCH_TUNE)
+ * measures only kinds the table does not hold, so a loaded file replaces the
+ * measurement.  Host only.  EINVAL: null path, unreadable/unwritable file, or
+ * a malformed or out-of-range line (then nothing is loaded).
+ */
+int fftfem_tune_save(const char* path);
+int fftfem_tune_load(const char* path);
+
+/*
  * Host-only access to the plan arithmetic, for tests on machines without a
  * GPU (no device is touched).  fftfem_axis_tables_host: the lam and Q tables
  * of fftfem_plan_tables for one axis of n-th order elements on K elements.

@@ -3,6 +3,8 @@
 // a solve runs in the HIP kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -344,7 +346,10 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
       a.G = tv.G;
       a.lrmax = tv.lrmax;
     }
-    while (a.G > 1 && (a.G > a.nlines || (int64_t)a.G * t.K > kLineTasks)) a.G /= 2;
+    // tuned or loaded values still respect this plan's lines, tasks and LDS
+    while (a.G > 1 && (a.G > a.nlines || (int64_t)a.G * t.K > kLineTasks ||
+                       (size_t)a.G * line_lds(n, t.K, sizeof(T)) > (size_t)p->lds_max))
+      a.G /= 2;
   }
   a.log2G = ilog2i(a.G);
   a.Q = tab<T>(p, gm.axis, 0);
@@ -1057,6 +1062,44 @@ int fftfem_element_matrices_host(int n, double* A, double* C) {
   std::memcpy(A, a.data(), a.size() * sizeof(double));
   std::memcpy(C, c.data(), c.size() * sizeof(double));
   return FFTFEM_OK;
+}
+
+int fftfem_tune_save(const char* path) {
+  if (!path) return FFTFEM_EINVAL;
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return FFTFEM_EINVAL;
+  std::fprintf(f, "# fftfem line-pass parameters: elt n mode strided kclass G lrmax\n");
+  for (const auto& kv : g_tune)
+    std::fprintf(f, "%d %d %d %d %lld %d %d\n", kv.first.elt, kv.first.n, kv.first.mode, kv.first.lf,
+                 (long long)kv.first.K, kv.second.G, kv.second.lrmax);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? (int)g_tune.size() : FFTFEM_EINVAL;
+}
+
+int fftfem_tune_load(const char* path) {
+  if (!path) return FFTFEM_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return FFTFEM_EINVAL;
+  std::vector<std::pair<TuneKey, TuneVal>> rows;
+  char line[256];
+  bool bad = false;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int elt, n, mode, lf, G, lr;
+    long long kc;
+    if (std::sscanf(line, "%d %d %d %d %lld %d %d", &elt, &n, &mode, &lf, &kc, &G, &lr) != 7 ||
+        (elt != 4 && elt != 8) || n < 1 || n > kMaxLineOrder || (mode != FWD && mode != MID && mode != INV) ||
+        (lf != 0 && lf != 1) || kc < 1 || G < 1 || G > 64 || (G & (G - 1)) || lr < 2 || lr > 4) {
+      bad = true;
+      break;
+    }
+    rows.push_back({TuneKey{elt, n, mode, lf, (int64_t)kc}, TuneVal{G, lr}});
+  }
+  std::fclose(f);
+  if (bad) return FFTFEM_EINVAL;
+  for (const auto& r : rows) tune_set(r.first, r.second);
+  return (int)rows.size();
 }
 
 int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in, double* out,

@@ -65,9 +65,9 @@ struct Group {
 };
 
 // Measures, for every line-pass kind of the plans (precision, n, mode,
-// strided or not, element-count class), the candidate lines per tile and
-// largest FFT radixes on the plan of that kind with the most data, and keeps
-// the fastest (process-wide).
+// strided or not, element-count class) that the table does not hold yet,
+// the candidate lines per tile and largest FFT radixes on the plan of that
+// kind with the most data, and keeps the fastest (process-wide).
 int tune_plans(const std::vector<fftfem_plan_t>& plans, hipStream_t s) {
   struct Cand {
     fftfem_plan_t p;
@@ -80,6 +80,8 @@ int tune_plans(const std::vector<fftfem_plan_t>& plans, hipStream_t s) {
       PassInfo info;
       if (plan_pass_info(p, pass, &info) != FFTFEM_OK) continue;
       const auto key = std::make_tuple(info.elt, info.n, info.mode, info.lf, tune_class(info.K));
+      TuneVal known;
+      if (tune_get(TuneKey{info.elt, info.n, info.mode, info.lf, tune_class(info.K)}, &known)) continue;
       const int64_t lines = (int64_t)fftfem_workspace_bytes(p);  // proxy for the problem size
       auto it = kinds.find(key);
       if (it == kinds.end() || it->second.lines < lines) kinds[key] = Cand{p, pass, lines};

@@ -29,7 +29,7 @@ EXPORTS = [
     "fftfem_debug_transform", "fftfem_axis_tables_host", "fftfem_element_matrices_host",
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
-    "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler",
+    "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler", "fftfem_tune_save", "fftfem_tune_load",
 ]
 BATCH_TUNE = 1
 
@@ -107,6 +107,8 @@ def lib():
         L.fftfem_destroy_batch.restype = None
         L.fftfem_tune.argtypes = [vp, vp]
         L.fftfem_implicit_euler.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
+        L.fftfem_tune_save.argtypes = [ctypes.c_char_p]
+        L.fftfem_tune_load.argtypes = [ctypes.c_char_p]
         _lib = L
     return _lib
 
@@ -156,6 +158,22 @@ def orders(n, N: int):
     if len(ns) != N:
         raise ValueError("one element order per axis")
     return ns
+
+
+def tune_save(path: str) -> int:
+    """Write the process-wide line-pass parameter table; returns its size."""
+    rc = lib().fftfem_tune_save(os.fsencode(path))
+    if rc < 0:
+        _check(rc, "fftfem_tune_save")
+    return rc
+
+
+def tune_load(path: str) -> int:
+    """Add a saved line-pass parameter table; returns the entries loaded."""
+    rc = lib().fftfem_tune_load(os.fsencode(path))
+    if rc < 0:
+        _check(rc, "fftfem_tune_load")
+    return rc
 
 
 def make_desc(K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,

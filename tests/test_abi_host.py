@@ -147,3 +147,21 @@ def test_host_tables_eigenvectors():
             s = s / np.sqrt(s @ C @ s)
             assert np.allclose(v, s, atol=1e-13)
             assert abs(lam[n - 1 + (k - 1) * n + l] - float(lam_o)) < 1e-13 * float(lam_o)
+
+
+def test_tune_table_file_round_trip(tmp_path):
+    """Saved line-pass parameters load back; malformed files load nothing."""
+    good = tmp_path / "tune.txt"
+    good.write_text("# comment\n8 9 2 0 2048 1 4\n4 5 0 1 129 8 3\n")
+    assert fftfem.tune_load(str(good)) == 2
+    out = tmp_path / "saved.txt"
+    assert fftfem.tune_save(str(out)) >= 2
+    rows = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert ["8", "9", "2", "0", "2048", "1", "4"] in rows and ["4", "5", "0", "1", "129", "8", "3"] in rows
+    for bad in ("8 9 2 0 2048 3 4\n", "8 12 2 0 2048 1 4\n", "8 9 2 0\n", "8 9 7 0 2048 1 4\n"):
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        with pytest.raises(fftfem.FftfemError):
+            fftfem.tune_load(str(f))
+    with pytest.raises(fftfem.FftfemError):
+        fftfem.tune_load(str(tmp_path / "missing.txt"))
