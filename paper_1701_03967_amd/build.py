@@ -24,6 +24,8 @@ LIB = os.path.join(HERE, "libfftfem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# extra defines of the objects for element counts that are not powers of two
+ANY_DEFINES = ()
 
 
 def _run(cmd):
@@ -35,9 +37,11 @@ def _run(cmd):
     return time.time() - t
 
 
-def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=()) -> str:
+def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=(), any_defines=None) -> str:
     """Compile and link the library.  `defines` (``NAME=VALUE`` strings) are
-    passed to the kernel compiles, `lib` and `build_dir` place the outputs."""
+    passed to the kernel compiles, `any_defines` additionally to the objects
+    for element counts that are not powers of two (default ANY_DEFINES),
+    `lib` and `build_dir` place the outputs."""
     BUILD = build_dir
     LIB = lib
     dflags = [f"-D{d}" for d in defines]
@@ -58,7 +62,9 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
             print(f"[build] {src} {dt:.1f}s", flush=True)
     # kernels: line.hip four times (element counts that are powers of two or
     # not, float32 or float64), ops.hip once; compiled in parallel
-    units = [("line.hip", f"line_{kind}_{real}.o", [f"-DFFTFEM_LINE_POW2={p2}", f"-DFFTFEM_LINE_REAL={real}"])
+    extra_any = [f"-D{d}" for d in (ANY_DEFINES if any_defines is None else any_defines)]
+    units = [("line.hip", f"line_{kind}_{real}.o", [f"-DFFTFEM_LINE_POW2={p2}", f"-DFFTFEM_LINE_REAL={real}"]
+              + (extra_any if p2 == 0 else []))
              for kind, p2 in (("p2", 1), ("any", 0)) for real in ("float", "double")]
     units.append(("ops.hip", "ops.o", []))
 

@@ -183,17 +183,24 @@ int validate(const fftfem_desc* d) {
   return FFTFEM_OK;
 }
 
-// FFT buffer length of an axis: K, or the Bluestein length L.
+// FFT buffer length of an axis: K (a power of two), K rounded up to a
+// multiple of 32 (mixed radix: the LDS slot swizzle permutes within aligned
+// blocks of up to 32 slots, so every permuted slot of the first K stays in
+// the buffer), or the Bluestein length L.
 int64_t fft_len(int64_t K) {
   if ((K & (K - 1)) == 0) return K;
+  if (!mixed_radices(K).empty()) return (K + 31) & ~int64_t(31);
   int64_t L = 1;
   while (L < 2 * K - 1) L *= 2;
   return L;
 }
 
-// Tuned parameters are shared by element counts with the same FFT length
-// (K itself, or the Bluestein length) and kind of transform.
-int64_t tune_class_of(int64_t K) { return 2 * fft_len(K) + ((K & (K - 1)) ? 1 : 0); }
+// Tuned parameters are shared by element counts with the same FFT buffer
+// length and kind of transform (power of two, mixed radix, Bluestein).
+int64_t tune_class_of(int64_t K) {
+  const int kind = (K & (K - 1)) == 0 ? 0 : (mixed_radices(K).empty() ? 1 : 2);
+  return 4 * fft_len(K) + kind;
+}
 
 
 size_t line_lds(int n, int64_t K, size_t elt, bool pad = true) {
@@ -359,6 +366,15 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   a.mu_self = tab<T>(p, gm.axis, 4);
   a.L = (int)t.L;
   a.log2L = t.L ? ilog2(t.L) : 0;
+  a.fl = (int)fft_len(t.K);
+  a.nrad = (int)t.radices.size();
+  if (a.nrad > 21) return FFTFEM_ENOTIMPL;
+  a.radpack = 0;
+  for (int i = 0; i < a.nrad; ++i) {
+    const int R = t.radices[i];
+    const uint64_t code = R == 2 ? 0 : R == 3 ? 1 : R == 4 ? 2 : R == 5 ? 3 : R == 7 ? 4 : R == 8 ? 5 : 6;
+    a.radpack |= code << (3 * i);
+  }
   a.chirp = tab<T>(p, gm.axis, 5);
   a.bhat = tab<T>(p, gm.axis, 6);
   a.twl = tab<T>(p, gm.axis, 7);
@@ -379,7 +395,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   if (want_partials) p->nparts_last = (int)nblocks;
   if (p->rec) {
     record(p, sizeof(T) == 4 ? REC_LINE32 : REC_LINE64,
-           {n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, a.L == 0 ? 1 : 0}, a, nblocks, lds);
+           {n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, (t.K & (t.K - 1)) == 0 ? 1 : 0}, a, nblocks, lds);
     return FFTFEM_OK;
   }
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +

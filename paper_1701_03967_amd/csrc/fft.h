@@ -200,6 +200,161 @@ __device__ void fft_all(C2<T>* buf, int nfft, int lk, const C2<T>* tw, int ls, i
   if (rem == 1) fft_stage<T, 2, INV, NT>(buf, nfft, lk, 1 << lns, lns, tw, ls);
 }
 
+// cos(2 pi j / R) and sin(2 pi j / R), j < R, for the odd radices.
+template <typename T, int R>
+struct OddRoots;
+template <typename T>
+struct OddRoots<T, 3> {
+  static constexpr T c[3] = {(T)1, (T)-0.5, (T)-0.5};
+  static constexpr T s[3] = {(T)0, (T)0.866025403784438646763723170752936183,
+                             (T)-0.866025403784438646763723170752936183};
+};
+template <typename T>
+struct OddRoots<T, 5> {
+  static constexpr T c[5] = {(T)1, (T)0.309016994374947424102293417182819059,
+                             (T)-0.809016994374947424102293417182819059,
+                             (T)-0.809016994374947424102293417182819059,
+                             (T)0.309016994374947424102293417182819059};
+  static constexpr T s[5] = {(T)0, (T)0.951056516295153572116439333379382143,
+                             (T)0.587785252292473129168705954639072769,
+                             (T)-0.587785252292473129168705954639072769,
+                             (T)-0.951056516295153572116439333379382143};
+};
+template <typename T>
+struct OddRoots<T, 7> {
+  static constexpr T c[7] = {(T)1,
+                             (T)0.623489801858733530525004884004239811,
+                             (T)-0.222520933956314404288902564496794759,
+                             (T)-0.900968867902419126236102319507445051,
+                             (T)-0.900968867902419126236102319507445051,
+                             (T)-0.222520933956314404288902564496794759,
+                             (T)0.623489801858733530525004884004239811};
+  static constexpr T s[7] = {(T)0,
+                             (T)0.78183148246802980870844452667405775,
+                             (T)0.974927912181823607018131682993931217,
+                             (T)0.433883739117558120475768332848358755,
+                             (T)-0.433883739117558120475768332848358755,
+                             (T)-0.974927912181823607018131682993931217,
+                             (T)-0.78183148246802980870844452667405775};
+};
+
+// In-register R-point DFT for odd R, natural order in and out: with
+// p_m = v_m + v_{R-m}, d_m = v_m - v_{R-m} (m = 1 .. (R-1)/2),
+//   X_s, X_{R-s} = v_0 + sum_m p_m cos(2 pi m s / R) -/+ i sum_m d_m sin(2 pi m s / R)
+// (forward, exp(-2 pi i j s / R); the inverse swaps the signs).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_odd(C2<T>* v) {
+  constexpr int H = (R - 1) / 2;
+  using RT = OddRoots<T, R>;
+  C2<T> p[H + 1], d[H + 1];
+  C2<T> sum = v[0];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    p[m] = cadd(v[m], v[R - m]);
+    d[m] = csub(v[m], v[R - m]);
+    sum = cadd(sum, p[m]);
+  }
+  C2<T> out[R];
+  out[0] = sum;
+#pragma unroll
+  for (int s = 1; s <= H; ++s) {
+    C2<T> a = v[0], b = {(T)0, (T)0};
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const T cs = RT::c[(m * s) % R], sn = RT::s[(m * s) % R];
+      a.x += p[m].x * cs;
+      a.y += p[m].y * cs;
+      b.x += d[m].x * sn;
+      b.y += d[m].y * sn;
+    }
+    // -i b = (b.y, -b.x); +i b = (-b.y, b.x)
+    const C2<T> mib = {b.y, -b.x}, pib = {-b.y, b.x};
+    out[s] = cadd(a, INV ? pib : mib);
+    out[R - s] = cadd(a, INV ? mib : pib);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = out[r];
+}
+
+// Stockham stage of radix R (2, 3, 4, 5, 7, 8 or 16) for any K divisible
+// by Ns R, after Ns points have been combined: the index arithmetic of
+// fft_stage with divisions, and twiddles exp(-+2 pi i r (j mod Ns) / (Ns R))
+// read from the length-K table at r (j mod Ns) K / (Ns R).  The butterflies
+// of whole buffers are read into registers (chunks of at most NT max(1, 8/R)
+// butterflies: K <= 1024 and NT >= 512 keep every buffer in one chunk), the
+// workgroup synchronizes, and then all write, so the stage runs in place.
+template <typename T, int R, bool INV, int NT>
+__device__ void fft_stage_mr(C2<T>* buf, int nfft, int K, int Ns, const C2<T>* __restrict__ tw, int ls) {
+  static_assert(NT >= 512, "a buffer's butterflies must fit in one chunk");
+  constexpr int MAXB = R >= 8 ? 1 : 8 / R;  // at most 8 values in registers (16 for radix 16)
+  const int KR = K / R;
+  const int stride = K / (Ns * R);
+  const int tid = threadIdx.x;
+  int fpc = (NT * MAXB) / KR;
+  if (fpc < 1) fpc = 1;
+  for (int f0 = 0; f0 < nfft; f0 += fpc) {
+    const int nf = nfft - f0 < fpc ? nfft - f0 : fpc;
+    const int nb = nf * KR;
+    C2<T> v[MAXB][R];
+    int dst[MAXB], fb[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+      const int b = t * NT + tid;
+      dst[t] = -1;
+      if (b < nb) {
+        const int fl = b / KR, j = b - fl * KR;
+        const int f = f0 + fl;
+        const int k = j % Ns;
+        const C2<T>* x = buf + f * ls;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t][r] = slot(x, j + r * KR);
+        if (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const C2<T> w = tw[r * k * stride];
+            v[t][r] = INV ? cmulc(v[t][r], w) : cmul(v[t][r], w);
+          }
+        }
+        if constexpr (R == 3 || R == 5 || R == 7)
+          dft_odd<T, R, INV>(v[t]);
+        else
+          dft_small<T, R, INV>(v[t]);
+        fb[t] = f * ls;
+        dst[t] = (j - k) * R + k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t)
+      if (dst[t] >= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) slot(buf + fb[t], dst[t] + r * Ns) = v[t][r];
+      }
+    __syncthreads();
+  }
+}
+
+// Length-K DFTs by mixed-radix Stockham stages, for K whose prime factors
+// are at most 7: nrad stages, stage i's radix coded in bits 3i..3i+2 of
+// radpack (0..6: radix 2, 3, 4, 5, 7, 8, 16; product K).  Output in natural
+// order in slots 0..K-1.  Ends with a barrier.
+template <typename T, bool INV, int NT>
+__device__ void fft_mixed(C2<T>* buf, int nfft, int K, uint64_t radpack, int nrad, const C2<T>* tw, int ls) {
+  int Ns = 1;
+  for (int i = 0; i < nrad; ++i) {
+    const int code = (int)((radpack >> (3 * i)) & 7);
+    switch (code) {
+      case 0: fft_stage_mr<T, 2, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 2; break;
+      case 1: fft_stage_mr<T, 3, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 3; break;
+      case 2: fft_stage_mr<T, 4, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 4; break;
+      case 3: fft_stage_mr<T, 5, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 5; break;
+      case 4: fft_stage_mr<T, 7, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 7; break;
+      case 5: fft_stage_mr<T, 8, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 8; break;
+      default: fft_stage_mr<T, 16, INV, NT>(buf, nfft, K, Ns, tw, ls); Ns *= 16; break;
+    }
+  }
+}
+
 // Length-K DFT for K not a power of two (Bluestein's chirp-z): with
 // c_j = exp(-i pi j^2 / K), jk = (j^2 + k^2 - (k - j)^2) / 2 gives
 //   X_k = c_k sum_j (x_j c_j) conj(c_{k-j}),

@@ -32,7 +32,10 @@ struct AxisTables {
   std::vector<double> twf;    // K complex: exp(-2 pi i q / K)
   std::vector<double> twm;    // K complex: exp(-i pi k / (2K))
   std::vector<double> twd;    // K complex: exp(-i pi k / K)
-  // K not a power of two: Bluestein's chirp-z tables (L = 0 otherwise)
+  // K not a power of two with prime factors <= 7: the mixed-radix stages
+  // (radices 16, 8, 4, 2 for the power of two, then 3, 5, 7; empty otherwise)
+  std::vector<int> radices;
+  // other K not a power of two: Bluestein's chirp-z tables (L = 0 otherwise)
   int64_t L = 0;              // power of two >= 2K - 1
   std::vector<double> chirp;  // K complex: exp(-i pi j^2 / K)
   std::vector<double> bhat;   // L complex: DFT_L of the conjugate chirp, / L
@@ -59,6 +62,31 @@ void element_matrices(int n, std::vector<double>* A, std::vector<double>* C);
 // The same matrices as unevaluated sums hi + lo of doubles: 2 (n+1)^2 values
 // each, the (n+1)^2 hi parts followed by the (n+1)^2 lo parts.
 void element_matrices_dd(int n, std::vector<double>* A, std::vector<double>* C);
+
+// Radices of a mixed-radix Stockham FFT of length K (K not a power of two,
+// every prime factor <= 7); empty if K has a larger prime factor.
+inline std::vector<int> mixed_radices(int64_t K) {
+  std::vector<int> r;
+  int64_t m = K;
+  int twos = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++twos;
+  }
+  int threes = 0, fives = 0, sevens = 0;
+  while (m % 3 == 0) m /= 3, ++threes;
+  while (m % 5 == 0) m /= 5, ++fives;
+  while (m % 7 == 0) m /= 7, ++sevens;
+  if (m != 1 || (threes + fives + sevens) == 0) return {};
+  while (twos >= 4) r.push_back(16), twos -= 4;
+  if (twos == 3) r.push_back(8);
+  if (twos == 2) r.push_back(4);
+  if (twos == 1) r.push_back(2);
+  for (int i = 0; i < threes; ++i) r.push_back(3);
+  for (int i = 0; i < fives; ++i) r.push_back(5);
+  for (int i = 0; i < sevens; ++i) r.push_back(7);
+  return r;
+}
 
 inline int num_even(int n) { return n / 2; }
 inline int num_odd(int n) { return (n - 1) / 2; }

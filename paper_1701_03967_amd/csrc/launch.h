@@ -27,7 +27,11 @@ struct LineArgs {
   const T* twf;           // K complex exp(-2 pi i q/K)
   const T* twm;           // K complex exp(-i pi k/(2K))
   const T* twd;           // K complex exp(-i pi k/K)
-  int L, log2L;           // K not a power of two: Bluestein length (else 0)
+  int L, log2L;           // K not a power of two without a mixed-radix plan: Bluestein length (else 0)
+  int fl;                 // complex slots per FFT buffer: K, the padded K of a mixed-radix plan, or L
+  int nrad;               // mixed-radix stages (K not a power of two, prime factors <= 7; else 0)
+  uint64_t radpack;       // their radices, 3 bits per stage (stage i at bit 3 i): codes 0..6 for
+                          // radix 2, 3, 4, 5, 7, 8, 16; product K
   const T* chirp;         // K complex exp(-i pi j^2/K)
   const T* bhat;          // L complex, spectrum of the conjugate chirp / L
   const T* twl;           // L complex exp(-2 pi i q/L)
@@ -111,7 +115,7 @@ template <typename T>
 hipError_t launch_line_grouped_any(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
 
 // Line-pass launchers, one per object built from line.hip: element counts
-// that are powers of two, and all others (a.L != 0).
+// that are powers of two, and all others.
 template <typename T>
 hipError_t launch_line_p2(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
                           hipStream_t s);
@@ -121,8 +125,8 @@ hipError_t launch_line_any(int n, int mode, bool upd, const LineArgs<T>& a, int 
 template <typename T>
 inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
                               hipStream_t s) {
-  return a.L == 0 ? launch_line_p2<T>(n, mode, upd, a, nblocks, lds, s)
-                  : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
+  return (a.K & (a.K - 1)) == 0 ? launch_line_p2<T>(n, mode, upd, a, nblocks, lds, s)
+                                 : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
 }
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
 template <typename T>

@@ -417,12 +417,15 @@ __device__ __forceinline__ void cond_solve0(const T* __restrict__ ar, const T* r
 constexpr bool kLinePow2 = FFTFEM_LINE_POW2 != 0;
 
 // Length-K DFTs of the nfft buffers of a tile: Stockham for K a power of
-// two, Bluestein otherwise.
+// two, mixed-radix Stockham for other K whose prime factors are at most 7,
+// Bluestein otherwise.
 template <typename T, bool INV, int NT, bool P2>
 __device__ __forceinline__ void line_dft(const LineArgs<T>& a, C2<T>* buf, int nfft, int ls) {
   const int lrmax = a.lrmax ? a.lrmax : 4;
   if constexpr (P2) {
     fft_all<T, INV, NT>(buf, nfft, a.log2K, reinterpret_cast<const C2<T>*>(a.twf), ls, lrmax);
+  } else if (a.nrad > 0) {
+    fft_mixed<T, INV, NT>(buf, nfft, a.K, a.radpack, a.nrad, reinterpret_cast<const C2<T>*>(a.twf), ls);
   } else {
     bluestein<T, INV, NT>(buf, nfft, a.K, a.log2L, reinterpret_cast<const C2<T>*>(a.chirp),
                           reinterpret_cast<const C2<T>*>(a.bhat), reinterpret_cast<const C2<T>*>(a.twl), ls,
@@ -443,7 +446,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
   const int tid = threadIdx.x;
   const int K = a.K, lk = a.log2K, lg = a.log2G, G = 1 << lg;
   const int M = n * K - 1;
-  const int ls = (a.L ? a.L : K) + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
+  const int ls = a.fl + (G > 1 ? 1 : 0);  // complex slots per FFT buffer (pad between lines)
   // raw line data (loaded input, spectral output, scattered result) is
   // packed at M slots per line: it never coexists with the FFT buffers
   // (NB ls complex slots per line), which it aliases across barriers

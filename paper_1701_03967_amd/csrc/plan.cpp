@@ -484,7 +484,8 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
     if (!v) return kESPECTRUM;
   for (double v : t->lam)
     if (!(v > 0) || !std::isfinite(v)) return kESPECTRUM;
-  if (K & (K - 1)) {
+  t->radices = (K & (K - 1)) ? mixed_radices(K) : std::vector<int>();
+  if ((K & (K - 1)) && t->radices.empty()) {
     // Bluestein tables for a length-K DFT: chirp c_j = exp(-i pi j^2 / K)
     // (argument reduced exactly: j^2 mod 2K), and the spectrum of the
     // conjugate chirp b (b_m = conj(c_m) at m and L - m, |m| < K, zero

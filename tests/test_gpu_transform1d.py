@@ -60,3 +60,26 @@ def test_round_trip_large_K(fm, K):
     back = p.debug_transform(1, -1, c).cpu().numpy()
     _, C = element_matrices(n)
     assert rel(fem1d.apply_elementwise(C, back, 1), y) < 1e-12
+
+
+@pytest.mark.parametrize("K", [7, 14, 21, 49, 243, 343, 625, 720, 729, 875, 1008])
+def test_mixed_radix_round_trip_and_solve(fm, K):
+    """Element counts with prime factors 2, 3, 5, 7 only (the mixed-radix
+    Stockham stages, including radix-7 and long radix-3/5 chains): the 1D
+    round trip, and a 2D solve against the oracle where it is cheap."""
+    n = 3
+    say("mixed radix", n, K)
+    p = fm.Plan((2, K), n, (1.0, 1.0), 0.0)
+    y = inputs.draw_rhs(list(p.shape), 900 + K, "normal")
+    yt = torch.from_numpy(y).cuda()
+    back = p.debug_transform(1, -1, p.debug_transform(1, +1, yt)).cpu().numpy()
+    _, C = element_matrices(n)
+    assert rel(fem1d.apply_elementwise(C, back, 1), y) < 1e-12
+    if K <= 243:
+        from oracle import solve as osolve
+        f = inputs.draw_rhs([n * 5 - 1, n * K - 1], 950 + K, "normal")
+        for precision, tol in (("fp64", 1e-11), ("fp32_refine", 1e-10)):
+            kw = dict(max_iter=4, tol=1e-13) if precision == "fp32_refine" else {}
+            u = fm.Plan((5, K), n, (1.0, 0.5), 1.0, precision=precision, **kw).solve(torch.from_numpy(f).cuda())
+            torch.cuda.synchronize()
+            assert rel(u.cpu().numpy(), osolve.solve(f, n, (5, K), (1.0, 0.5), 1.0)) < tol, precision
