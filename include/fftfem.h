@@ -202,6 +202,26 @@ size_t fftfem_batch_workspace_bytes(const fftfem_batch_t b);
 void fftfem_destroy_batch(fftfem_batch_t b);
 
 /*
+ * Expansion in the tensor eigenbasis (Sect. 3, Theorem 2: the direct FC_n
+ * transform of loads, and, item 3, the direct F_n transform of grid
+ * values, which is FC_n of C w).  With S_d the C_d-orthonormal
+ * eigenvectors of axis d (Theorem 1) in the spectral order of
+ * fftfem_plan_tables (block k = 0, then k = 1 .. K_d - 1, n_d modes each):
+ *   fftfem_coefficients, kind 0 (values):  out = (x_d S_d^T C_d) in,
+ *                        kind 1 (loads):   out = (x_d S_d^T) in;
+ *   fftfem_synthesize:                      out = (x_d S_d) in,
+ * so synthesize(coefficients(w, values)) = w and the coefficients of a
+ * solution are those of its load divided by the denominators react +
+ * sum_d diff[d] 4/h_d^2 lambda_d.  float64 transforms for every plan
+ * precision; arrays in the layout of fftfem_solve (nrhs sets); out may equal
+ * in except for kind 0.  Eigenvectors of the k = 0 blocks carry a free sign
+ * (largest component positive).  Asynchronous on s.  EINVAL: null
+ * pointers, bad kind, overlapping arrays, or a plan being recorded.
+ */
+int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind, hipStream_t s);
+int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_t s);
+
+/*
  * Implicit Euler time stepping of the semi-discrete heat equation of the
  * plan's operator (Sect. 4 remarks that implicit time discretizations of
  * heat-type equations lead at every time level to the system solved here):

@@ -1080,6 +1080,46 @@ int fftfem_element_matrices_host(int n, double* A, double* C) {
   return FFTFEM_OK;
 }
 
+int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind, hipStream_t s) {
+  if (!p || !in || !out || (kind != 0 && kind != 1) || p->rec) return FFTFEM_EINVAL;
+  const size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
+  if (in != out && overlap(in, out, bytes)) return FFTFEM_EINVAL;
+  if (kind == 0 && in == out) return FFTFEM_EINVAL;
+  p->last = s;
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r) {
+    const size_t o = (size_t)r * p->size;
+    const double* src = in + o;
+    if (kind == 0) {
+      // values: the loads C w first (Theorem 2, item 3)
+      rc = mass_apply(p, in + o, nullptr, out + o, 1.0, s);
+      src = out + o;
+    }
+    for (int d = p->N - 1; d >= 0 && !rc; --d) {
+      rc = line_pass<double>(p, natural_geom(p, d, false), FWD, src, 1, out + o, 1, nullptr, nullptr, s, false);
+      src = out + o;
+    }
+  }
+  return rc;
+}
+
+int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_t s) {
+  if (!p || !in || !out || p->rec) return FFTFEM_EINVAL;
+  const size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
+  if (in != out && overlap(in, out, bytes)) return FFTFEM_EINVAL;
+  p->last = s;
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r) {
+    const size_t o = (size_t)r * p->size;
+    const double* src = in + o;
+    for (int d = 0; d < p->N && !rc; ++d) {
+      rc = line_pass<double>(p, natural_geom(p, d, false), INV, src, 1, out + o, 1, nullptr, nullptr, s, false);
+      src = out + o;
+    }
+  }
+  return rc;
+}
+
 int fftfem_tune_save(const char* path) {
   if (!path) return FFTFEM_EINVAL;
   std::lock_guard<std::mutex> l(g_tune_mu);

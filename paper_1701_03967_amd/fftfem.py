@@ -30,6 +30,7 @@ EXPORTS = [
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
     "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler", "fftfem_tune_save", "fftfem_tune_load",
+    "fftfem_coefficients", "fftfem_synthesize",
 ]
 BATCH_TUNE = 1
 
@@ -108,6 +109,8 @@ def lib():
         L.fftfem_tune.argtypes = [vp, vp]
         L.fftfem_implicit_euler.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
         L.fftfem_tune_save.argtypes = [ctypes.c_char_p]
+        L.fftfem_coefficients.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.fftfem_synthesize.argtypes = [vp, vp, vp, vp]
         L.fftfem_tune_load.argtypes = [ctypes.c_char_p]
         _lib = L
     return _lib
@@ -313,6 +316,30 @@ class Plan:
         self._check_tensor(y, "y")
         _check(lib().fftfem_apply_A(self._h, _tptr(u), _tptr(y), _stream_ptr(stream)), "fftfem_apply_A")
         return y
+
+    def coefficients(self, x, out=None, kind: str = "values", stream=None):
+        """Expansion coefficients in the tensor eigenbasis: of grid values
+        (kind "values", the direct F_n transform) or of a load ("loads",
+        the direct FC_n transform)."""
+        import torch
+        self._check_tensor(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "out")
+        k = {"values": 0, "loads": 1}[kind]
+        _check(lib().fftfem_coefficients(self._h, _tptr(x), _tptr(out), k, _stream_ptr(stream)),
+               "fftfem_coefficients")
+        return out
+
+    def synthesize(self, c, out=None, stream=None):
+        """Grid values of the expansion with coefficients c."""
+        import torch
+        self._check_tensor(c, "c")
+        if out is None:
+            out = torch.empty_like(c)
+        self._check_tensor(out, "out")
+        _check(lib().fftfem_synthesize(self._h, _tptr(c), _tptr(out), _stream_ptr(stream)), "fftfem_synthesize")
+        return out
 
     def implicit_euler(self, u, nsteps: int, F=None, work=None, stream=None):
         """nsteps implicit Euler steps of C du/dt + A_diff u = F with
