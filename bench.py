@@ -30,7 +30,7 @@ PAPER_UNKNOWNS_PER_S = {"c3_2d_n9_k1024": 9215 ** 2 / 120.0, "c4_3d_n9_k64": 575
 METRIC = "solve time & unknowns/s, n=9 2D/3D; FP32+refine vs FP64 at rel err ≤1e-10"
 
 
-def kernel_bytes(name: str, size: int, N: int) -> float:
+def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
     """Algorithmic HBM bytes of one launch of a named kernel (one read and one
     write of every array it touches)."""
     t = 4 if "32" in name.split("_")[0] else 8
@@ -38,6 +38,18 @@ def kernel_bytes(name: str, size: int, N: int) -> float:
         return size * 2 * t
     if name.startswith("apply"):
         return 0.0
+    if name.startswith("band"):
+        # algorithm (b) along axis 0 (order n0).  One-sweep kernel: the first
+        # sweep reads y and writes z and the node pivots, the second reads
+        # them and writes x.  Three-kernel form: cond reads y and writes z and
+        # the node right-hand sides, back reads them and writes x, nodes
+        # moves the node values (1/n0 of the array) through the elimination:
+        # read g, write g' and the pivot, read both, write x.
+        if name.startswith("bandcond") or name.startswith("bandback"):
+            return size * 16.0
+        if name.startswith("bandnodes"):
+            return size * 48.0 / n0
+        return size * (32 + 16.0 / n0)
     last = N - 1
     ax_s = name.rsplit("_ax", 1)[1]
     ax = int(ax_s.rstrip("t"))
@@ -56,7 +68,7 @@ def kernel_bytes(name: str, size: int, N: int) -> float:
     return 0.0
 
 
-KERNEL_SOURCES = ("line.hip", "fft.h", "device_common.h", "launch.h", "ops.hip", "api.cpp")
+KERNEL_SOURCES = ("line.hip", "fft.h", "device_common.h", "launch.h", "ops.hip", "api.cpp", "band.hip")
 
 
 def sources_sha256() -> str:
@@ -71,8 +83,12 @@ def sources_sha256() -> str:
 
 
 def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
-    """Symbol of the line kernel that a per-pass timing name refers to."""
+    """Symbol of the kernel that a per-pass timing name refers to."""
     head = name.split("_ax")[0]
+    for pre, sym in (("bandcond", "band_cond_kernel"), ("bandnodes", "band_nodes_kernel"),
+                     ("bandback", "band_back_kernel"), ("band", "band_kernel")):
+        if head.startswith(pre):
+            return f"{sym}<{n}>"
     dtype = "double" if head.endswith("64") else "float"
     mode = 0 if head.startswith("fwd") else (1 if head.startswith("inv") else 2)
     upd = "true" if "upd" in head else "false"
@@ -121,8 +137,11 @@ def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=Fa
     no per-kernel instrumentation), then per-kernel times from a separate
     instrumented run, and with `graph` the mean of graph replays of one
     captured solve.  Returns (plan, u, ms, kernels, stats, extra)."""
+    algorithm = "a"
+    if precision.endswith("_b"):
+        precision, algorithm = precision[:-2], "b"
     plan = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=precision,
-                   max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12)
+                   max_iter=3 if precision == "fp32_refine" else 0, tol=1e-12, algorithm=algorithm)
     if tune and prob.N >= 2:
         plan.tune()  # measured line-pass parameters, before the untimed warm-up
     u = torch.empty_like(f)
@@ -403,7 +422,8 @@ def main():
     ap.add_argument("--workload", default="c3_2d_n9_k1024")
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="fp64,fp32,fp32_refine")
+    ap.add_argument("--modes", default="fp64,fp32,fp32_refine,fp64_b",
+                    help="fp64, fp32, fp32_refine (algorithm (a)), fp64_b (algorithm (b))")
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
     ap.add_argument("--batch-iters", type=int, default=3, help="c5_batch: refinement steps")
     ap.add_argument("--no-tune", action="store_true", help="c5_batch: no line-pass tuning")
@@ -455,6 +475,9 @@ def main():
                 rec["iterations"] = st["iterations"]
                 rec["rel_correction"] = st["rel_correction"]
             rec["kernels_ms"] = {k: round(v[0], 5) for k, v in kt.items()}
+            if mode == "fp64_b":
+                rec["band_GBps"] = {k: round(kernel_bytes(k, prob.size, prob.N, prob.n) / (avg * 1e-3) / 1e9, 1)
+                                    for k, (avg, _) in kt.items() if k.startswith("band")}
             out[mode] = rec
             del plan
             print(f"[bench] {name} {mode}: {ms:.3f} ms/solve", file=sys.stderr, flush=True)
@@ -466,7 +489,10 @@ def main():
         return prob, out, kts, sols
 
     prob, res, kts, sols = run(args.workload, True)
-    best_mode = "fp64" if "fp64" in res else args.modes.split(",")[0]
+    # headline: the faster of the two float64 solves (algorithms (a) and (b)
+    # of Sect. 4 solve the same system to the same accuracy)
+    f64 = [m for m in ("fp64", "fp64_b") if m in res]
+    best_mode = min(f64, key=lambda m: res[m]["ms"]) if f64 else args.modes.split(",")[0]
     ms = res[best_mode]["ms"]
     value = prob.size / (ms * 1e-3)
     # dominant kernel of the headline mode
@@ -475,7 +501,7 @@ def main():
     if kt:
         dom = max(kt.items(), key=lambda kv: kv[1][0] * kv[1][1])
         name, (avg_ms, cnt) = dom
-        by = kernel_bytes(name, prob.size, prob.N)
+        by = kernel_bytes(name, prob.size, prob.N, prob.n)
         if by > 0:
             gbs = by / (avg_ms * 1e-3) / 1e9
             ax = int(name.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in name else 0
@@ -496,11 +522,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": value / PAPER_UNKNOWNS_PER_S[args.workload] if args.workload in PAPER_UNKNOWNS_PER_S else None,
-        "dtype": "f64" if best_mode == "fp64" else "f32",
+        "dtype": "f64" if best_mode.startswith("fp64") else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": prob.N, "n": prob.n, "K": list(prob.K),
                    "diff": list(prob.diff), "react": prob.react, "unknowns": prob.size,
-                   "mode": best_mode, "rhs": inputs.WORKLOADS[args.workload].rhs,
+                   "mode": best_mode, "algorithm": "b" if best_mode == "fp64_b" else "a", "rhs": inputs.WORKLOADS[args.workload].rhs,
                    "seed": inputs.WORKLOADS[args.workload].seed, "tuned": bool(args.tune)},
         "modes": {m: res[m] for m in res if m != "unknowns"},
         "roofline": roof,

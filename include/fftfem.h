@@ -63,6 +63,18 @@ enum {
   FFTFEM_FP32_REFINE = 2  /* float32 transforms + float64 residual/update refinement */
 };
 
+/*
+ * fftfem_desc.flags: solve by algorithm (b) of Sect. 4 instead of (a): the
+ * FC_n transform along axes 2..N only, then along axis 1 a direct banded
+ * solve of each line's shifted 1D system (the bubbles of every element
+ * condensed onto its end nodes, then the tridiagonal node system by
+ * elimination), then the inverse transforms along axes 2..N.  FFTFEM_FP64
+ * plans only (FFTFEM_ENOTIMPL otherwise) and not in batches.  The node
+ * elimination's rounding error grows like the condition number of that
+ * system, about (nK_1)^2 eps relative at react = 0.
+ */
+#define FFTFEM_ALGORITHM_B 1u
+
 #define FFTFEM_MAX_DIMS 3
 #define FFTFEM_MAX_ORDER 16
 #define FFTFEM_MAX_ITERS 16
@@ -79,7 +91,7 @@ typedef struct {
   int max_iter;                   /* refinement iterations after the first solve (0 -> 3) */
   double tol;                     /* refinement stop: ||correction||/||u|| <= tol (0 -> 1e-12) */
   int nrhs;                       /* right-hand sides per solve (0 -> 1) */
-  unsigned flags;                 /* reserved, must be 0 */
+  unsigned flags;                 /* 0 or FFTFEM_ALGORITHM_B; other bits must be 0 */
   int n_axis[FFTFEM_MAX_DIMS];    /* element order per axis (Sect. 4: n = (n_1, ..., n_N));
                                      0 -> n; M_d = n_axis[d] K[d] - 1 */
 } fftfem_desc;
@@ -106,7 +118,9 @@ int fftfem_plan(fftfem_plan_t* out, int N, const int64_t* K, int n, const double
 int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* desc);
 
 /*
- * Solve A u = f (algorithm (a) of Sect. 4).  f, u: device float64 arrays in
+ * Solve A u = f (algorithm (a) of Sect. 4, or (b) with FFTFEM_ALGORITHM_B:
+ * then the plan also holds a (K_1 - 1) M_2 .. M_N float64 work array for the
+ * elimination).  f, u: device float64 arrays in
  * the layout above (times nrhs).  f is read only; u must not overlap f.
  * Asynchronous on stream s (NULL = default stream); no host synchronization
  * and no allocation.  A plan may be used by one stream at a time.

@@ -67,6 +67,7 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
               + (extra_any if p2 == 0 else []))
              for kind, p2 in (("p2", 1), ("any", 0)) for real in ("float", "double")]
     units.append(("ops.hip", "ops.o", []))
+    units.append(("band.hip", "band.o", []))
 
     def compile_unit(u):
         src, o, extra = u

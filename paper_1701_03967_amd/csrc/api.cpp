@@ -25,9 +25,9 @@ using namespace fftfem;
 namespace {
 
 // Per-axis device tables: Q, twf, twm, twd, mu, for K not a power of two
-// the Bluestein chirp, bhat and twl (null otherwise), and the condensed
-// per-frequency solve's constants.
-constexpr int kNumTables = 9;
+// the Bluestein chirp, bhat and twl (null otherwise), the condensed
+// per-frequency solve's constants and the banded solve's (algorithm (b)).
+constexpr int kNumTables = 10;
 struct DevTables {
   double* d[kNumTables] = {};
   float* f[kNumTables] = {};
@@ -50,6 +50,9 @@ struct fftfem_plan_s {
   float* W32b = nullptr;     // second float32 workspace (transposed 2D schedule)
   double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
   double* W64r = nullptr;    // float64 residual (float32 + refinement)
+  bool algb = false;         // algorithm (b): banded solve along axis 0
+  bool band_split = false;   // ... in three kernels (few lines) instead of one sweep per line
+  double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or size values (split)
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
   double* tmp[8] = {};       // operator-apply partial products (double-double planes)
@@ -171,7 +174,7 @@ int validate(const fftfem_desc* d) {
   if (d->n < 1 || d->n > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
   for (int i = 0; i < d->N; ++i)
     if (d->n_axis[i] < 0 || d->n_axis[i] > FFTFEM_MAX_ORDER) return FFTFEM_EINVAL;
-  if (d->flags != 0) return FFTFEM_EINVAL;
+  if (d->flags & ~FFTFEM_ALGORITHM_B) return FFTFEM_EINVAL;
   if (d->precision < FFTFEM_FP64 || d->precision > FFTFEM_FP32_REFINE) return FFTFEM_EINVAL;
   if (d->max_iter < 0 || d->max_iter > FFTFEM_MAX_ITERS) return FFTFEM_EINVAL;
   if (d->nrhs < 0 || !(d->tol >= 0) || !std::isfinite(d->react)) return FFTFEM_EINVAL;
@@ -754,9 +757,12 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   // a line-kernel tile holds at most kLineTasks element tasks
   for (int i = 0; i < d.N; ++i)
     if (d.K[i] > kLineTasks) return FFTFEM_ENOTIMPL;
+  const bool algb = (d.flags & FFTFEM_ALGORITHM_B) != 0;
+  if (algb && (d.precision != FFTFEM_FP64 || cache)) return FFTFEM_ENOTIMPL;
   fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
   if (!p) return FFTFEM_ENOMEM;
   p->desc = d;
+  p->algb = algb;
   p->N = d.N;
   p->n = d.n;
   p->nrhs = d.nrhs;
@@ -832,7 +838,7 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
       arrow[al.gA + m] *= p->coef[i];
     }
     const std::vector<double>* src[kNumTables] = {&qs,     &t.twf,  &t.twm, &t.twd, &mu,
-                                                  &t.chirp, &t.bhat, &t.twl, &arrow};
+                                                  &t.chirp, &t.bhat, &t.twl, &arrow, &t.band};
     for (int w = 0; w < kNumTables && !rc; ++w) {
       if (src[w]->empty()) continue;
       rc = upload<double>(p, &p->dev[i].d[w], *src[w]);
@@ -861,6 +867,15 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     rc = dev_alloc(p, (void**)&p->W32b, (size_t)p->size * sizeof(float));
   if (!rc && d.precision == FFTFEM_FP32_REFINE)
     rc = dev_alloc(p, (void**)&p->W64r, (size_t)p->size * sizeof(double));
+  if (!rc && p->algb) {
+    // one thread per line fills the chip from about 64K lines (256 CUs, 4
+    // waves each); below that the element-parallel three-kernel form
+    const int64_t nl = p->size / p->M[0];
+    p->band_split = nl < 65536;
+    if (const char* e = std::getenv("FFTFEM_BAND_SPLIT")) p->band_split = std::atoi(e) != 0;
+    const size_t cnt = p->band_split ? (size_t)p->size : (size_t)std::max<int64_t>(1, p->K[0] - 1) * (size_t)nl;
+    rc = dev_alloc(p, (void**)&p->Wband, cnt * sizeof(double));
+  }
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
   p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 4 : 8);
@@ -911,6 +926,49 @@ static bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// Algorithm (b) of Sect. 4: FC_n transforms along axes N - 1 .. 1 (natural
+// layout, f into u), the banded solve along axis 0 in place, the inverse
+// transforms along axes 1 .. N - 1.
+static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
+  const int N = p->N;
+  int rc = FFTFEM_OK;
+  const double* src = f;
+  for (int d = N - 1; d >= 1 && !rc; --d) {
+    rc = line_pass<double>(p, natural_geom(p, d, false), FWD, src, 1, u, 1, nullptr, nullptr, s, false);
+    src = u;
+  }
+  if (rc) return rc;
+  const Geom g = natural_geom(p, 0, true);
+  BandArgs a{};
+  a.in = src;
+  a.out = u;
+  a.cp = p->Wband;
+  a.tab = p->dev[0].d[9];
+  a.coef = p->coef[0];
+  a.react = p->desc.react;
+  a.K = (int)p->K[0];
+  a.nlines = g.nlines;
+  a.nother = g.nother;
+  for (int e = 0; e < g.nother; ++e) {
+    a.mu_o[e] = tab<double>(p, g.oaxis[e], 4);
+    a.so[e] = g.so[e];
+    a.Mo[e] = g.Mo[e];
+  }
+  if (p->band_split) {
+    static const char* names[3] = {"bandcond64_ax0", "bandnodes64_ax0", "bandback64_ax0"};
+    for (int step = 0; step < 3 && !rc; ++step) {
+      Timed tm(p, s, names[step]);
+      rc = from_hip(launch_band_split(p->nd[0], step, a, s));
+    }
+  } else {
+    Timed tm(p, s, "band64_ax0");
+    rc = from_hip(launch_band(p->nd[0], a, s));
+  }
+  for (int d = 1; d < N && !rc; ++d)
+    rc = line_pass<double>(p, natural_geom(p, d, false), INV, u, 1, u, 1, nullptr, nullptr, s, false);
+  return rc;
+}
+
 int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
   if (!p || !f || !u) return FFTFEM_EINVAL;
   size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
@@ -935,6 +993,10 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
       rc = from_hip(launch_reset(flag, st, kStatsLen, s));
     }
     if (rc) break;
+    if (p->algb) {
+      rc = band_chain(p, fr, ur, s);
+      continue;
+    }
     if (p->desc.precision == FFTFEM_FP64) {
       rc = transform_chain<double>(p, fr, 1, ur, p->W64b, ur, nullptr, nullptr, s, false, false, base + 1);
       continue;

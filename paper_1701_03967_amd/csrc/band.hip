@@ -1,0 +1,395 @@
+// The banded solve along an axis of algorithm (b) of Sect. 4 (gfx950).
+//
+// After the FC_n transforms along every other axis, each line along axis 0
+// carries one shifted 1D system (coef A + sigma C) x = y of the assembled
+// nth-order stiffness A and mass C (Sect. 2), sigma = react + the other axes'
+// terms coef_d lambda_d.  Its matrix couples the n - 1 bubble unknowns of an
+// element only to each other and to the element's two end nodes, so the
+// bubbles are eliminated element by element (static condensation) and what
+// remains is a tridiagonal system in the K - 1 mesh nodes.  The bubble block
+// coef A_BB + sigma C_BB is the same in every element; in the
+// mass-orthonormal eigenbasis V of the pencil (A_BB, C_BB) (eigenvalues
+// lam) it is diagonal, coef lam_m + sigma, so the elimination needs n - 1
+// reciprocals per line and two n - 1 by n - 1 products per element.
+//
+// With t = V^T y_B, z_m = t_m / (coef lam_m + sigma) and h_L, h_R the mode
+// couplings to the left and right node, the condensed element matrix is
+// [[a, b], [b, a]] (the element is mirror symmetric), and element e adds
+// -h_L . z to the right-hand side of its left node and -h_R . z to its right
+// node.  The node system has diagonal 2a and off-diagonal b = -s; written as
+// s tridiag(-1, 2, -1) + d I with d = 2 (a + b), both s and d are formed
+// without cancellation (s from the 113-bit condensed stiffness a0 minus a
+// term proportional to sigma, d proportional to sigma), and the
+// elimination carries e_j = den_j - s, which obeys
+// e_j = d + s e_{j-1} / den_{j-1} (e_1 = s + d), a sum of non-negative terms.
+// The small eigenvalues of the node system, s (1 - cos(pi k / K)) + d, then
+// keep their relative accuracy; forming 2a and b directly would lose about
+// (K / pi)^2 eps of it.  A backward sweep substitutes the nodes and recovers
+// the bubbles x_B = V (z - (h_L x_L + h_R x_R) / (coef lam + sigma)).
+//
+// One thread per line: element i of line l is at i * nlines + l, so a wave's
+// 64 threads read and write 64 consecutive values per access.  The next
+// element's values are loaded before the current one is processed.
+#include "device_common.h"
+#include "launch.h"
+
+namespace fftfem {
+
+// Per-line constants: r_m = 1 / (coef lam_m + sigma), the node couplings
+// h_L, h_R of the bubble modes, and the node system's s and d.
+struct BandLine {
+  double r[kMaxLineOrder], hL[kMaxLineOrder], hR[kMaxLineOrder];
+  double s, d;
+};
+
+template <int NORD>
+__device__ __forceinline__ void band_line(const BandArgs& a, int64_t line, BandLine& L) {
+  constexpr int nb = NORD - 1;
+  constexpr int oL = nb * nb, oAL = oL + nb, oCL = oAL + nb, oAR = oCL + nb, oCR = oAR + nb, otL = oCR + nb,
+                otX = otL + nb, oN = otX + nb;
+  const double* __restrict__ tb = a.tab;
+  double sg = a.react;
+  for (int e = 0; e < a.nother; ++e) sg += a.mu_o[e][(line / a.so[e]) % a.Mo[e]];
+  const double cf = a.coef;
+  // a = cf a0 + sg PL, b = -cf a0 + sg PX
+  double PL = tb[oN + 0], PX = tb[oN + 1];
+#pragma unroll
+  for (int m = 0; m < nb; ++m) {
+    const double r = 1.0 / (cf * tb[oL + m] + sg);
+    const double cl = tb[oCL + m], cr = tb[oCR + m];
+    L.r[m] = r;
+    L.hL[m] = cf * tb[oAL + m] + sg * cl;
+    L.hR[m] = cf * tb[oAR + m] + sg * cr;
+    PL -= r * (cf * tb[otL + m] + sg * cl * cl);
+    PX -= r * (cf * tb[otX + m] + sg * cl * cr);
+  }
+  L.s = cf * tb[oN + 2] - sg * PX;
+  L.d = 2.0 * sg * (PL + PX);
+}
+
+// z = diag(r) V^T y_B of one element (bubble values at p[m S]).
+template <int NORD>
+__device__ __forceinline__ void band_z(const double* __restrict__ tb, const BandLine& L, const double* p,
+                                       int64_t S, double* z) {
+  constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  double y[NB];
+#pragma unroll
+  for (int i = 0; i < nb; ++i) y[i] = p[(int64_t)i * S];
+#pragma unroll
+  for (int m = 0; m < nb; ++m) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < nb; ++i) t += tb[i * nb + m] * y[i];
+    z[m] = L.r[m] * t;
+  }
+}
+
+template <int NORD>
+__global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
+  constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  const int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (line >= a.nlines) return;
+  const double* __restrict__ tb = a.tab;
+  BandLine L;
+  band_line<NORD>(a, line, L);
+  const double sn = L.s, dn = L.d;
+  const int64_t S = a.nlines;
+  const int K = a.K;
+  const double* in = a.in + line;
+  double* out = a.out + line;
+  double* cp = a.cp + line;
+
+  // forward: condensation and elimination of the node system
+  double cur[NORD], nxt[NORD];
+  cur[0] = 0.0;
+#pragma unroll
+  for (int m = 0; m < nb; ++m) cur[1 + m] = in[(int64_t)m * S];
+  double carry = 0.0, ex = 0.0, rho = 0.0, gprev = 0.0;
+  for (int e = 0; e < K; ++e) {
+    if (e + 1 < K) {
+      const int64_t b1 = (int64_t)(e + 1) * NORD;
+      nxt[0] = in[(b1 - 1) * S];
+#pragma unroll
+      for (int m = 0; m < nb; ++m) nxt[1 + m] = in[(b1 + m) * S];
+    }
+    const int64_t b0 = (int64_t)e * NORD;
+    double z[NB];
+    double pL = 0.0, pR = 0.0;
+#pragma unroll
+    for (int m = 0; m < nb; ++m) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < nb; ++i) t += tb[i * nb + m] * cur[1 + i];
+      z[m] = L.r[m] * t;
+      pL += L.hL[m] * z[m];
+      pR += L.hR[m] * z[m];
+    }
+#pragma unroll
+    for (int m = 0; m < nb; ++m) out[(b0 + m) * S] = z[m];
+    if (e > 0) {
+      const double g = cur[0] + carry - pL;
+      ex = e == 1 ? sn + dn : dn + rho * ex;
+      const double inv = 1.0 / (sn + ex);
+      rho = sn * inv;
+      gprev = (g + sn * gprev) * inv;
+      cp[(int64_t)(e - 1) * S] = rho;
+      out[(b0 - 1) * S] = gprev;
+    }
+    carry = -pR;
+#pragma unroll
+    for (int m = 0; m < NORD; ++m) cur[m] = nxt[m];
+  }
+
+  // backward: node substitution x_j = g'_j + rho_j x_{j+1}, bubble recovery
+  {
+    const int64_t b0 = (int64_t)(K - 1) * NORD;
+    cur[0] = K > 1 ? out[(b0 - 1) * S] : 0.0;
+    nxt[0] = K > 1 ? cp[(int64_t)(K - 2) * S] : 0.0;
+#pragma unroll
+    for (int m = 0; m < nb; ++m) cur[1 + m] = out[(b0 + m) * S];
+  }
+  double xR = 0.0, pc = nxt[0];
+  for (int e = K - 1; e >= 0; --e) {
+    double pn = 0.0;
+    if (e > 0) {
+      const int64_t b1 = (int64_t)(e - 1) * NORD;
+      nxt[0] = e > 1 ? out[(b1 - 1) * S] : 0.0;
+      pn = e > 1 ? cp[(int64_t)(e - 2) * S] : 0.0;
+#pragma unroll
+      for (int m = 0; m < nb; ++m) nxt[1 + m] = out[(b1 + m) * S];
+    }
+    const int64_t b0 = (int64_t)e * NORD;
+    double xL = 0.0;
+    if (e > 0) {
+      xL = cur[0] + pc * xR;
+      out[(b0 - 1) * S] = xL;
+    }
+    double w[NB];
+#pragma unroll
+    for (int m = 0; m < nb; ++m) w[m] = cur[1 + m] - L.r[m] * (L.hL[m] * xL + L.hR[m] * xR);
+#pragma unroll
+    for (int i = 0; i < nb; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < nb; ++m) v += tb[i * nb + m] * w[m];
+      out[(b0 + i) * S] = v;
+    }
+    xR = xL;
+    pc = pn;
+#pragma unroll
+    for (int m = 0; m < NORD; ++m) cur[m] = nxt[m];
+  }
+}
+
+// The same solve in three kernels, for grids with too few lines to fill the
+// chip with one thread per line (2D: M_2 lines).  The condensation and the
+// bubble recovery are independent per element and run one thread per
+// (line, group of kBandEPT elements); only the node elimination, K - 1
+// values per line, stays sequential.
+//   1. cond: y (in) -> w: z in the bubble slots, the condensed node
+//      right-hand sides g in the node slots (a thread recomputes the last
+//      z of the element before its group);
+//   2. nodes: the tridiagonal node system on w's node slots, forward
+//      elimination (pivots into the node slots of out, free after step 1)
+//      and back substitution: the node values x in w's node slots;
+//   3. back: x_B = V (z - (h_L x_L + h_R x_R) / (.)) and the node values into out.
+constexpr int kBandEPT = 16;
+
+template <int NORD>
+__global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
+  constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= a.nlines * ng) return;
+  const int64_t line = t % a.nlines, grp = t / a.nlines;
+  const int64_t S = a.nlines;
+  BandLine L;
+  band_line<NORD>(a, line, L);
+  const double* in = a.in + line;
+  double* w = a.cp + line;
+  const int e0 = (int)grp * kBandEPT, e1 = min(a.K, e0 + kBandEPT);
+  double carry = 0.0;  // -h_R . z of the element before
+  if (e0 > 0 && nb > 0) {
+    double z[NB];
+    band_z<NORD>(a.tab, L, in + (int64_t)(e0 - 1) * NORD * S, S, z);
+#pragma unroll
+    for (int m = 0; m < nb; ++m) carry -= L.hR[m] * z[m];
+  }
+  for (int e = e0; e < e1; ++e) {
+    const int64_t b0 = (int64_t)e * NORD;
+    double z[NB];
+    double pL = 0.0, pR = 0.0;
+    if constexpr (nb > 0) band_z<NORD>(a.tab, L, in + b0 * S, S, z);
+#pragma unroll
+    for (int m = 0; m < nb; ++m) {
+      pL += L.hL[m] * z[m];
+      pR += L.hR[m] * z[m];
+      w[(b0 + m) * S] = z[m];
+    }
+    if (e > 0) w[(b0 - 1) * S] = in[(b0 - 1) * S] + carry - pL;
+    carry = -pR;
+  }
+}
+
+// Node elimination, one thread per line, kBandNB node values loaded ahead.
+constexpr int kBandNB = 16;
+
+template <int NORD>
+__global__ __launch_bounds__(kBlock) void band_nodes_kernel(BandArgs a) {
+  const int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (line >= a.nlines) return;
+  const int64_t S = a.nlines;
+  BandLine L;
+  band_line<NORD>(a, line, L);
+  const double sn = L.s, dn = L.d;
+  double* w = a.cp + line;
+  double* pv = a.out + line;
+  const int nn = a.K - 1;  // node j (1..K-1) at slot j NORD - 1
+  const int64_t st = (int64_t)NORD * S;
+  double* wn = w + (int64_t)(NORD - 1) * S;   // node 1
+  double* pn = pv + (int64_t)(NORD - 1) * S;
+  double ex = sn, rho = 1.0, gprev = 0.0;      // e_1 = d + 1 * s
+  // forward: the next kBandNB right-hand sides are loaded while the current
+  // ones are eliminated
+  double g[kBandNB], gn[kBandNB];
+#pragma unroll
+  for (int i = 0; i < kBandNB; ++i) g[i] = i < nn ? wn[(int64_t)i * st] : 0.0;
+  for (int j0 = 0; j0 < nn; j0 += kBandNB) {
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i) gn[i] = j0 + kBandNB + i < nn ? wn[(int64_t)(j0 + kBandNB + i) * st] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i)
+      if (j0 + i < nn) {
+        ex = dn + rho * ex;
+        const double inv = 1.0 / (sn + ex);
+        rho = sn * inv;
+        gprev = (g[i] + sn * gprev) * inv;
+        pn[(int64_t)(j0 + i) * st] = rho;
+        wn[(int64_t)(j0 + i) * st] = gprev;
+      }
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i) g[i] = gn[i];
+  }
+  // backward: x_j = g'_j + rho_j x_{j+1}, likewise one block ahead
+  double x = 0.0;
+  const int last = nn - 1;
+  double c[kBandNB], cn[kBandNB];
+#pragma unroll
+  for (int i = 0; i < kBandNB; ++i) {
+    g[i] = last - i >= 0 ? wn[(int64_t)(last - i) * st] : 0.0;
+    c[i] = last - i >= 0 ? pn[(int64_t)(last - i) * st] : 0.0;
+  }
+  for (int j0 = last; j0 >= 0; j0 -= kBandNB) {
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i) {
+      const int j = j0 - kBandNB - i;
+      gn[i] = j >= 0 ? wn[(int64_t)j * st] : 0.0;
+      cn[i] = j >= 0 ? pn[(int64_t)j * st] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i)
+      if (j0 - i >= 0) {
+        x = g[i] + c[i] * x;
+        wn[(int64_t)(j0 - i) * st] = x;
+      }
+#pragma unroll
+    for (int i = 0; i < kBandNB; ++i) {
+      g[i] = gn[i];
+      c[i] = cn[i];
+    }
+  }
+}
+
+template <int NORD>
+__global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
+  constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= a.nlines * ng) return;
+  const int64_t line = t % a.nlines, grp = t / a.nlines;
+  const int64_t S = a.nlines;
+  BandLine L;
+  band_line<NORD>(a, line, L);
+  const double* __restrict__ tb = a.tab;
+  const double* w = a.cp + line;
+  double* out = a.out + line;
+  const int e0 = (int)grp * kBandEPT, e1 = min(a.K, e0 + kBandEPT);
+  double xL = e0 > 0 ? w[((int64_t)e0 * NORD - 1) * S] : 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int64_t b0 = (int64_t)e * NORD;
+    const double xR = e + 1 < a.K ? w[(b0 + NORD - 1) * S] : 0.0;
+    if (e > 0) out[(b0 - 1) * S] = xL;
+    if constexpr (nb > 0) {
+      double v[NB];
+#pragma unroll
+      for (int m = 0; m < nb; ++m) v[m] = w[(b0 + m) * S] - L.r[m] * (L.hL[m] * xL + L.hR[m] * xR);
+#pragma unroll
+      for (int i = 0; i < nb; ++i) {
+        double x = 0.0;
+#pragma unroll
+        for (int m = 0; m < nb; ++m) x += tb[i * nb + m] * v[m];
+        out[(b0 + i) * S] = x;
+      }
+    }
+    xL = xR;
+  }
+}
+
+hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) {
+  if (a.nlines < 1 || a.K < 1 || a.in == a.cp || a.out == a.cp || step < 0 || step > 2)
+    return hipErrorInvalidValue;
+  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
+  const int64_t nb_el = (a.nlines * ng + kBlock - 1) / kBlock;
+  const int64_t nb_ln = (a.nlines + kBlock - 1) / kBlock;
+  if (nb_el > 0x7fffffff) return hipErrorInvalidValue;
+  if (step == 1 && a.K < 2) return hipSuccess;  // no nodes
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                          \
+  case N:                                                                                       \
+    if (step == 0)                                                                              \
+      hipLaunchKernelGGL((band_cond_kernel<N>), dim3((unsigned)nb_el), dim3(kBlock), 0, s, a);  \
+    else if (step == 1)                                                                         \
+      hipLaunchKernelGGL((band_nodes_kernel<N>), dim3((unsigned)nb_ln), dim3(kBlock), 0, s, a); \
+    else                                                                                        \
+      hipLaunchKernelGGL((band_back_kernel<N>), dim3((unsigned)nb_el), dim3(kBlock), 0, s, a);  \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_band(int n, const BandArgs& a, hipStream_t s) {
+  if (a.nlines < 1 || a.K < 1) return hipErrorInvalidValue;
+  const int64_t nblocks = (a.nlines + kBlock - 1) / kBlock;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                      \
+  case N:                                                                                   \
+    hipLaunchKernelGGL((band_kernel<N>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, a);   \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fftfem

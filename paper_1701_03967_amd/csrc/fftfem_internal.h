@@ -43,6 +43,23 @@ struct AxisTables {
   // condensed per-frequency solve of the fused middle pass (layout in
   // condensed_tables): ne^2 + no^2 + 3 (n - 1) + 2 values, unscaled
   std::vector<double> arrow;
+  // banded solve along the axis (algorithm (b); layout in BandLayout), unscaled
+  std::vector<double> band;
+};
+
+// Offsets into AxisTables::band (algorithm (b), the banded solve along an
+// axis) for order n, nb = n - 1 bubbles: V (nb x nb, [bubble][mode],
+// row-major: the mass-orthonormal eigenvectors of the element's bubble
+// pencil in the physical bubble basis), lam (nb), then per mode V^T A_{B,0},
+// V^T C_{B,0}, V^T A_{B,n}, V^T C_{B,n} (couplings to the element's left and
+// right node), tL = 2 hAL hCL - hAL^2 / lam and tX = hAL hCR + hAR hCL -
+// hAL hAR / lam, then C_00, C_0n and a0 = A_00 - sum_m hAL_m^2 / lam_m (the
+// condensed stiffness' diagonal entry; its off-diagonal one is -a0).
+struct BandLayout {
+  int nb, V, lam, hAL, hCL, hAR, hCR, tL, tX, nn, size;
+  explicit BandLayout(int n)
+      : nb(n - 1), V(0), lam(nb * nb), hAL(lam + nb), hCL(hAL + nb), hAR(hCL + nb), hCR(hAR + nb),
+        tL(hCR + nb), tX(tL + nb), nn(tX + nb), size(nn + 3) {}
 };
 
 // Offsets into AxisTables::arrow for order n.

@@ -65,6 +65,25 @@ struct ApplyArgs {
 };
 
 
+// The banded solve along axis 0 (algorithm (b)): per line, the shifted 1D
+// system (coef A + sigma C) x = y with sigma = react + the other axes'
+// spectral terms.  Element i of line l sits at i * nlines + l (axis 0 of a
+// row-major array).
+struct BandArgs {
+  const double* in;       // y (may equal out)
+  double* out;            // x
+  double* cp;             // one sweep: (K - 1) x nlines work (the elimination's pivots);
+                          // three kernels: a work array of the size of y
+  const double* tab;      // the axis' band tables (unscaled)
+  double coef;            // diff 4 / h^2 of the axis
+  double react;
+  int K;
+  int64_t nlines;
+  const double* mu_o[2];  // other axes' spectral terms, strides and lengths
+  int64_t so[2], Mo[2];
+  int nother;
+};
+
 // Jobs of the grouped operator, transpose and bookkeeping launches.
 struct TransposeJob {
   const void* in;
@@ -129,6 +148,8 @@ inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, i
                                  : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
 }
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
+hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);
 hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s);

@@ -424,6 +424,57 @@ bool condensed_tables(int n, const std::vector<q>& A, const std::vector<q>& C, A
   return true;
 }
 
+// Tables of the banded solve along an axis (Sect. 4, algorithm (b)): the
+// element's bubble block of the shifted matrix coef A + sigma C is
+// diagonalized once in the mass-orthonormal eigenbasis V of the pencil
+// (A_BB, C_BB) (eigenvalues lam), so per line only the n - 1 reciprocals
+// 1 / (coef lam + sigma) are needed to eliminate the bubbles element by
+// element; the couplings of the modes to the element's end nodes give the
+// nodal tridiagonal system.  Its entries are formed without cancellation:
+// the condensed stiffness part (a0, -a0: rows summing to zero) comes from
+// this 113-bit table, and only terms proportional to sigma are added per
+// line (tL, tX: the sigma-independent parts of those terms).
+bool band_tables(int n, const std::vector<q>& A, const std::vector<q>& C, AxisTables* t) {
+  const int nb = n - 1, m = n + 1;
+  const BandLayout bl(n);
+  t->band.assign(bl.size, 0.0);
+  q a0 = A[0];
+  if (nb > 0) {
+    std::vector<q> Ma(nb * nb), Mc(nb * nb);
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        Ma[a * nb + b] = A[(1 + a) * m + 1 + b];
+        Mc[a * nb + b] = C[(1 + a) * m + 1 + b];
+      }
+    std::vector<q> lam, V;
+    if (!pencil_eigen(nb, Ma, Mc, &lam, &V)) return false;
+    for (int a = 0; a < nb; ++a)
+      for (int l = 0; l < nb; ++l) t->band[bl.V + a * nb + l] = (double)V[a * nb + l];
+    for (int l = 0; l < nb; ++l) {
+      if (!(lam[l] > 0)) return false;
+      q aL = 0, cL = 0, aR = 0, cR = 0;
+      for (int a = 0; a < nb; ++a) {
+        aL += V[a * nb + l] * A[(1 + a) * m + 0];
+        cL += V[a * nb + l] * C[(1 + a) * m + 0];
+        aR += V[a * nb + l] * A[(1 + a) * m + n];
+        cR += V[a * nb + l] * C[(1 + a) * m + n];
+      }
+      t->band[bl.lam + l] = (double)lam[l];
+      t->band[bl.hAL + l] = (double)aL;
+      t->band[bl.hCL + l] = (double)cL;
+      t->band[bl.hAR + l] = (double)aR;
+      t->band[bl.hCR + l] = (double)cR;
+      t->band[bl.tL + l] = (double)(2 * aL * cL - aL * aL / lam[l]);
+      t->band[bl.tX + l] = (double)(aL * cR + aR * cL - aL * aR / lam[l]);
+      a0 -= aL * aL / lam[l];
+    }
+  }
+  t->band[bl.nn + 0] = (double)C[0];
+  t->band[bl.nn + 1] = (double)C[n];
+  t->band[bl.nn + 2] = (double)a0;
+  return true;
+}
+
 }  // namespace
 
 void element_matrices(int n, std::vector<double>* A, std::vector<double>* C) {
@@ -465,6 +516,7 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
   t->Q.assign((size_t)K * n * n, 0.0);
   if (!zero_block(n, K, A, C, t)) return kESPECTRUM;
   if (!condensed_tables(n, A, C, t)) return kESPECTRUM;
+  if (!band_tables(n, A, C, t)) return kESPECTRUM;
   unsigned hw = std::thread::hardware_concurrency();
   int nthreads = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
   if (K < 64) nthreads = 1;

@@ -33,6 +33,7 @@ EXPORTS = [
     "fftfem_coefficients", "fftfem_synthesize",
 ]
 BATCH_TUNE = 1
+ALGORITHM_B = 1  # fftfem_desc.flags: algorithm (b) of Sect. 4
 
 
 class FftfemError(RuntimeError):
@@ -181,8 +182,12 @@ def tune_load(path: str) -> int:
 
 def make_desc(K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
               X: Optional[Sequence[float]] = None, precision: str = "fp64", max_iter: int = 0,
-              tol: float = 0.0, nrhs: int = 1) -> "Desc":
-    """n: one element order for every axis, or one per axis."""
+              tol: float = 0.0, nrhs: int = 1, algorithm: str = "a") -> "Desc":
+    """n: one element order for every axis, or one per axis.  algorithm: "a"
+    (FC_n transforms along every axis) or "b" (transforms along axes 2..N and
+    a banded solve along axis 1; fp64 only)."""
+    if algorithm not in ("a", "b"):
+        raise ValueError("algorithm must be 'a' or 'b'")
     d = Desc()
     d.N = len(K)
     ns = orders(n, d.N)
@@ -197,6 +202,7 @@ def make_desc(K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
     d.max_iter = int(max_iter)
     d.tol = float(tol)
     d.nrhs = int(nrhs)
+    d.flags = ALGORITHM_B if algorithm == "b" else 0
     return d
 
 
@@ -266,8 +272,8 @@ class Plan:
 
     def __init__(self, K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
                  X: Optional[Sequence[float]] = None, precision: str = "fp64",
-                 max_iter: int = 0, tol: float = 0.0, nrhs: int = 1):
-        d = make_desc(K, n, diff, react, X, precision, max_iter, tol, nrhs)
+                 max_iter: int = 0, tol: float = 0.0, nrhs: int = 1, algorithm: str = "a"):
+        d = make_desc(K, n, diff, react, X, precision, max_iter, tol, nrhs, algorithm)
         h = ctypes.c_void_p()
         _check(lib().fftfem_plan_ex(ctypes.byref(h), ctypes.byref(d)), "fftfem_plan_ex")
         self._h = h
@@ -277,6 +283,7 @@ class Plan:
         self.nrhs = int(nrhs)
         self.shape = tuple(m * k - 1 for m, k in zip(self.orders, self.K))
         self.precision = precision
+        self.algorithm = algorithm
 
     def close(self):
         if self._h:

@@ -59,8 +59,9 @@ def _plan_ex(**kw):
 @pytest.mark.parametrize("kw,code", [
     ({"N": 0}, -1), ({"N": 4}, -1), ({"K": (1, 8)}, -1), ({"n": 0}, -1), ({"n": 17}, -1),
     ({"diff": (0.0, 1.0)}, -1), ({"diff": (1.0, -2.0)}, -1), ({"precision": 7}, -1),
-    ({"flags": 1}, -1), ({"max_iter": 99}, -1), ({"react": float("nan")}, -1),
+    ({"flags": 2}, -1), ({"flags": 3}, -1), ({"max_iter": 99}, -1), ({"react": float("nan")}, -1),
     ({"K": (1025, 8)}, -7), ({"n": 12}, -7), ({"K": (4096, 8)}, -7), ({"K": (2048, 8)}, -7),
+    ({"flags": 1, "precision": 1}, -7), ({"flags": 1, "precision": 2}, -7),
     ({"n_axis": (2, -1)}, -1), ({"n_axis": (17, 2)}, -1), ({"n_axis": (2, 10)}, -7), ({"n": 12, "n_axis": (3, 12)}, -7),
 ])
 def test_invalid_arguments_rejected_on_host(kw, code):

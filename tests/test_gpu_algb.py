@@ -1,0 +1,143 @@
+"""GPU parity of algorithm (b) of Sect. 4 (FC_n transforms along axes 2..N,
+a banded solve of each line's shifted 1D system along axis 1, inverse
+transforms) against the oracle's plain solve, in 1D, 2D and 3D, with mixed
+element orders, element counts that are not powers of two, several
+right-hand sides, react = 0, react > 0 and react < 0 (still definite), and at
+the 2D n = 9, K = 1024 size against algorithm (a) and the double-double
+residual.
+
+Tolerance: the node system is formed as s tridiag(-1, 2, -1) + d I with s
+and d free of cancellation, and its elimination adds only non-negative
+terms, so the solve is as accurate as the transforms: the float64 bar of
+the algorithm (a) parity tests, 1e-11 against the oracle, and 1e-11 against
+algorithm (a) at full size."""
+import numpy as np
+import pytest
+
+from oracle import solve as osolve
+from paper_1701_03967_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+TOL_FULL = 1e-11
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1701_03967_amd import fftfem
+    fftfem.lib()
+    return fftfem
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [((64,), 5, 0.0), ((7,), 9, 2.0), ((40,), 1, 0.0),
+         ((32, 24), (2, 5), 0.75), ((256, 16), 9, 0.0), ((17, 33), (7, 3), 3.0), ((20, 12), (4, 6), 0.0),
+         ((8, 3), 1, 1.0), ((2, 9), (9, 2), 0.5), ((64, 64), 9, -10.0),
+         ((8, 12, 10), (3, 2, 4), 0.75), ((16, 16, 16), 9, 0.0), ((5, 6, 7), (2, 1, 3), 10.0)]
+
+
+@pytest.mark.parametrize("split", ["0", "1"])
+@pytest.mark.parametrize("K,n,react", CASES)
+def test_algorithm_b_solve(fm, monkeypatch, K, n, react, split):
+    """split 0: one sweep per line (one kernel); 1: the element-parallel
+    three-kernel form (the plan's default below 64K lines)."""
+    monkeypatch.setenv("FFTFEM_BAND_SPLIT", split)
+    N = len(K)
+    diff = (1.0, 0.5, 2.0)[:N]
+    ns = osolve.orders(n, N)
+    shape = tuple(m * k - 1 for m, k in zip(ns, K))
+    f = inputs.draw_rhs(shape, seed=81)
+    say("algorithm b", K, n, react, "split", split)
+    ref = osolve.solve(f, n, K, diff, react)
+    p = fm.Plan(K, n, diff, react, algorithm="b")
+    assert p.shape == shape
+    u = p.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    e = rel(u.cpu().numpy(), ref)
+    say("  rel", e, "tol", TOL)
+    assert e < TOL
+
+
+def test_algorithm_b_several_rhs_and_repeat(fm):
+    K, n, diff, react = (24, 40), (5, 3), (1.0, 3.0), 0.25
+    shape = tuple(m * k - 1 for m, k in zip(n, K))
+    f = inputs.draw_rhs(shape, seed=82, nrhs=3)
+    ref = osolve.solve(f, n, K, diff, react)
+    p = fm.Plan(K, n, diff, react, nrhs=3, algorithm="b")
+    fd = torch.from_numpy(f).cuda()
+    u1 = p.solve(fd).cpu().numpy()
+    u2 = p.solve(fd).cpu().numpy()
+    assert np.array_equal(u1, u2)
+    for r in range(3):
+        assert rel(u1[r], ref[r]) < TOL
+
+
+@pytest.mark.parametrize("K", [(1024, 1024), (64, 64, 64)])
+def test_algorithm_b_matches_a_and_residual_full_size(fm, K):
+    """2D n = 9, K = 1024 (84.9M unknowns; three-kernel form) and 3D n = 9,
+    K = 64 (190M; one sweep per line): u_b against the algorithm (a) solve
+    (itself pinned to the oracle on sampled outputs at these sizes) and the
+    relative residual ||f - A u_b|| / ||f|| by the double-double apply."""
+    n, react = 9, 0.0
+    diff = (1.0,) * len(K)
+    pa = fm.Plan(K, n, diff, react)
+    pb = fm.Plan(K, n, diff, react, algorithm="b")
+    shape = pa.shape
+    say("full size", K, n)
+    f = torch.from_numpy(inputs.draw_rhs(shape, seed=83)).cuda()
+    ua = pa.solve(f)
+    ub = pb.solve(f)
+    torch.cuda.synchronize()
+    e = float(torch.linalg.norm(ub - ua) / torch.linalg.norm(ua))
+    say("  |u_b - u_a| / |u_a|", e)
+    assert e < TOL_FULL
+    # residuals: a white-noise load leaves ||A|| ||u|| far above ||f||, so
+    # even the rounded exact solution has a residual of eps ||A|| ||u||; the
+    # algorithm (b) one must be no larger than algorithm (a)'s
+    ra = float(torch.linalg.norm(f - pa.apply_A(ua)) / torch.linalg.norm(f))
+    rb = float(torch.linalg.norm(f - pb.apply_A(ub)) / torch.linalg.norm(f))
+    say("  residual a", ra, "b", rb)
+    assert rb < 2 * ra
+    del pa, pb, f, ua, ub
+    torch.cuda.empty_cache()
+
+
+def test_algorithm_b_one_sweep_default_many_lines(fm):
+    """3D with more than 64K lines along axis 1: the plan's default one-sweep form."""
+    K, n, diff, react = (6, 40, 40), (3, 7, 7), (1.0, 1.0, 1.0), 0.5
+    shape = tuple(m * k - 1 for m, k in zip(n, K))
+    assert shape[1] * shape[2] >= 65536
+    f = inputs.draw_rhs(shape, seed=86)
+    ref = osolve.solve(f, n, K, diff, react)
+    u = fm.Plan(K, n, diff, react, algorithm="b").solve(torch.from_numpy(f).cuda())
+    assert rel(u.cpu().numpy(), ref) < TOL
+
+
+def test_algorithm_b_implicit_euler(fm):
+    """Time stepping through the algorithm (b) solve matches the algorithm
+    (a) one."""
+    K, n, diff, react = (16, 20), 4, (1.0, 1.0), 50.0
+    pa = fm.Plan(K, n, diff, react)
+    pb = fm.Plan(K, n, diff, react, algorithm="b")
+    u0 = torch.from_numpy(inputs.draw_rhs(pa.shape, seed=84)).cuda()
+    F = torch.from_numpy(inputs.draw_rhs(pa.shape, seed=85)).cuda()
+    ua = pa.implicit_euler(u0.clone(), 5, F)
+    ub = pb.implicit_euler(u0.clone(), 5, F)
+    torch.cuda.synchronize()
+    assert rel(ub.cpu().numpy(), ua.cpu().numpy()) < TOL
+
+
+def test_algorithm_b_not_in_batches(fm):
+    with pytest.raises(fm.FftfemError):
+        fm.Batch([dict(K=(8, 8), n=2, diff=(1.0, 1.0), algorithm="b")])
