@@ -52,7 +52,8 @@ struct fftfem_plan_s {
   double* W64r = nullptr;    // float64 residual (float32 + refinement)
   bool algb = false;         // algorithm (b): banded solve along axis 0
   bool band_split = false;   // ... in three kernels (few lines) instead of one sweep per line
-  double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or size values (split)
+  double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
+                             // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
   double* tmp[8] = {};       // operator-apply partial products (double-double planes)
@@ -873,7 +874,8 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     const int64_t nl = p->size / p->M[0];
     p->band_split = nl < 65536;
     if (const char* e = std::getenv("FFTFEM_BAND_SPLIT")) p->band_split = std::atoi(e) != 0;
-    const size_t cnt = p->band_split ? (size_t)p->size : (size_t)std::max<int64_t>(1, p->K[0] - 1) * (size_t)nl;
+    const size_t nodes = (size_t)std::max<int64_t>(1, p->K[0] - 1) * (size_t)nl;
+    const size_t cnt = p->band_split ? (size_t)((p->size + 1) & ~int64_t(1)) + 2 * nodes : nodes;
     rc = dev_alloc(p, (void**)&p->Wband, cnt * sizeof(double));
   }
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
@@ -943,6 +945,7 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
   a.in = src;
   a.out = u;
   a.cp = p->Wband;
+  a.pr = p->band_split ? p->Wband + ((p->size + 1) & ~int64_t(1)) : nullptr;  // 16-byte aligned pairs
   a.tab = p->dev[0].d[9];
   a.coef = p->coef[0];
   a.react = p->desc.react;

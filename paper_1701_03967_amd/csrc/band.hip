@@ -184,21 +184,22 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
 // The same solve in three kernels, for grids with too few lines to fill the
 // chip with one thread per line (2D: M_2 lines).  The condensation and the
 // bubble recovery are independent per element and run one thread per
-// (line, group of kBandEPT elements); only the node elimination, K - 1
+// (line, group of kBandEPTc or kBandEPTb elements); only the node elimination, K - 1
 // values per line, stays sequential.
 //   1. cond: y (in) -> w: z in the bubble slots, the condensed node
 //      right-hand sides g in the node slots (a thread recomputes the last
 //      z of the element before its group);
 //   2. nodes: the tridiagonal node system on w's node slots, forward
-//      elimination (pivots into the node slots of out, free after step 1)
-//      and back substitution: the node values x in w's node slots;
+//      elimination (g' and the pivots as pairs into a compact array) and
+//      back substitution: the node values x in w's node slots;
 //   3. back: x_B = V (z - (h_L x_L + h_R x_R) / (.)) and the node values into out.
-constexpr int kBandEPT = 16;
+// elements per thread of the condensation and of the bubble recovery
+constexpr int kBandEPTc = 16, kBandEPTb = 4;
 
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
-  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
+  const int64_t ng = (a.K + kBandEPTc - 1) / kBandEPTc;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= a.nlines * ng) return;
   const int64_t line = t % a.nlines, grp = t / a.nlines;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
   band_line<NORD>(a, line, L);
   const double* in = a.in + line;
   double* w = a.cp + line;
-  const int e0 = (int)grp * kBandEPT, e1 = min(a.K, e0 + kBandEPT);
+  const int e0 = (int)grp * kBandEPTc, e1 = min(a.K, e0 + kBandEPTc);
   double carry = 0.0;  // -h_R . z of the element before
   if (e0 > 0 && nb > 0) {
     double z[NB];
@@ -231,8 +232,9 @@ __global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
   }
 }
 
-// Node elimination, one thread per line, kBandNB node values loaded ahead.
-constexpr int kBandNB = 16;
+// Node elimination, one thread per line: the forward sweep loads kBandNF
+// right-hand sides ahead, the backward sweep kBandNB pairs (g', pivot).
+constexpr int kBandNF = 24, kBandNB = 24;
 
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_nodes_kernel(BandArgs a) {
@@ -242,68 +244,59 @@ __global__ __launch_bounds__(kBlock) void band_nodes_kernel(BandArgs a) {
   BandLine L;
   band_line<NORD>(a, line, L);
   const double sn = L.s, dn = L.d;
-  double* w = a.cp + line;
-  double* pv = a.out + line;
-  const int nn = a.K - 1;  // node j (1..K-1) at slot j NORD - 1
+  const int nn = a.K - 1;  // node j (1..K-1) at slot j NORD - 1 of w
   const int64_t st = (int64_t)NORD * S;
-  double* wn = w + (int64_t)(NORD - 1) * S;   // node 1
-  double* pn = pv + (int64_t)(NORD - 1) * S;
-  double ex = sn, rho = 1.0, gprev = 0.0;      // e_1 = d + 1 * s
-  // forward: the next kBandNB right-hand sides are loaded while the current
-  // ones are eliminated
-  double g[kBandNB], gn[kBandNB];
+  double* wn = a.cp + line + (int64_t)(NORD - 1) * S;  // node 1
+  // (g'_j, pivot_j) of node j at pair (j - 1) S + line: one 16-byte access per step
+  double2* pr = reinterpret_cast<double2*>(a.pr) + line;
+  double ex = sn, rho = 1.0, gprev = 0.0;  // e_1 = d + 1 * s
+  {
+    double g[kBandNF], gn[kBandNF];
 #pragma unroll
-  for (int i = 0; i < kBandNB; ++i) g[i] = i < nn ? wn[(int64_t)i * st] : 0.0;
-  for (int j0 = 0; j0 < nn; j0 += kBandNB) {
+    for (int i = 0; i < kBandNF; ++i) g[i] = i < nn ? wn[(int64_t)i * st] : 0.0;
+    for (int j0 = 0; j0 < nn; j0 += kBandNF) {
 #pragma unroll
-    for (int i = 0; i < kBandNB; ++i) gn[i] = j0 + kBandNB + i < nn ? wn[(int64_t)(j0 + kBandNB + i) * st] : 0.0;
+      for (int i = 0; i < kBandNF; ++i) gn[i] = j0 + kBandNF + i < nn ? wn[(int64_t)(j0 + kBandNF + i) * st] : 0.0;
 #pragma unroll
-    for (int i = 0; i < kBandNB; ++i)
-      if (j0 + i < nn) {
-        ex = dn + rho * ex;
-        const double inv = 1.0 / (sn + ex);
-        rho = sn * inv;
-        gprev = (g[i] + sn * gprev) * inv;
-        pn[(int64_t)(j0 + i) * st] = rho;
-        wn[(int64_t)(j0 + i) * st] = gprev;
-      }
+      for (int i = 0; i < kBandNF; ++i)
+        if (j0 + i < nn) {
+          ex = dn + rho * ex;
+          const double inv = 1.0 / (sn + ex);
+          rho = sn * inv;
+          gprev = (g[i] + sn * gprev) * inv;
+          pr[(int64_t)(j0 + i) * S] = make_double2(gprev, rho);
+        }
 #pragma unroll
-    for (int i = 0; i < kBandNB; ++i) g[i] = gn[i];
+      for (int i = 0; i < kBandNF; ++i) g[i] = gn[i];
+    }
   }
-  // backward: x_j = g'_j + rho_j x_{j+1}, likewise one block ahead
+  // backward: x_j = g'_j + rho_j x_{j+1} into w's node slots, likewise one block ahead
   double x = 0.0;
   const int last = nn - 1;
-  double c[kBandNB], cn[kBandNB];
+  double2 q[kBandNB], qn[kBandNB];
 #pragma unroll
-  for (int i = 0; i < kBandNB; ++i) {
-    g[i] = last - i >= 0 ? wn[(int64_t)(last - i) * st] : 0.0;
-    c[i] = last - i >= 0 ? pn[(int64_t)(last - i) * st] : 0.0;
-  }
+  for (int i = 0; i < kBandNB; ++i) q[i] = last - i >= 0 ? pr[(int64_t)(last - i) * S] : make_double2(0.0, 0.0);
   for (int j0 = last; j0 >= 0; j0 -= kBandNB) {
 #pragma unroll
     for (int i = 0; i < kBandNB; ++i) {
       const int j = j0 - kBandNB - i;
-      gn[i] = j >= 0 ? wn[(int64_t)j * st] : 0.0;
-      cn[i] = j >= 0 ? pn[(int64_t)j * st] : 0.0;
+      qn[i] = j >= 0 ? pr[(int64_t)j * S] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int i = 0; i < kBandNB; ++i)
       if (j0 - i >= 0) {
-        x = g[i] + c[i] * x;
+        x = q[i].x + q[i].y * x;
         wn[(int64_t)(j0 - i) * st] = x;
       }
 #pragma unroll
-    for (int i = 0; i < kBandNB; ++i) {
-      g[i] = gn[i];
-      c[i] = cn[i];
-    }
+    for (int i = 0; i < kBandNB; ++i) q[i] = qn[i];
   }
 }
 
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
-  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
+  const int64_t ng = (a.K + kBandEPTb - 1) / kBandEPTb;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= a.nlines * ng) return;
   const int64_t line = t % a.nlines, grp = t / a.nlines;
@@ -313,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
   const double* __restrict__ tb = a.tab;
   const double* w = a.cp + line;
   double* out = a.out + line;
-  const int e0 = (int)grp * kBandEPT, e1 = min(a.K, e0 + kBandEPT);
+  const int e0 = (int)grp * kBandEPTb, e1 = min(a.K, e0 + kBandEPTb);
   double xL = e0 > 0 ? w[((int64_t)e0 * NORD - 1) * S] : 0.0;
   for (int e = e0; e < e1; ++e) {
     const int64_t b0 = (int64_t)e * NORD;
@@ -336,10 +329,10 @@ __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
 }
 
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) {
-  if (a.nlines < 1 || a.K < 1 || a.in == a.cp || a.out == a.cp || step < 0 || step > 2)
+  if (a.nlines < 1 || a.K < 1 || a.in == a.cp || a.out == a.cp || !a.pr || step < 0 || step > 2)
     return hipErrorInvalidValue;
-  const int64_t ng = (a.K + kBandEPT - 1) / kBandEPT;
-  const int64_t nb_el = (a.nlines * ng + kBlock - 1) / kBlock;
+  const int64_t ept = step == 0 ? kBandEPTc : kBandEPTb;
+  const int64_t nb_el = (a.nlines * ((a.K + ept - 1) / ept) + kBlock - 1) / kBlock;
   const int64_t nb_ln = (a.nlines + kBlock - 1) / kBlock;
   if (nb_el > 0x7fffffff) return hipErrorInvalidValue;
   if (step == 1 && a.K < 2) return hipSuccess;  // no nodes

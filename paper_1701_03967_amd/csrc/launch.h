@@ -74,6 +74,7 @@ struct BandArgs {
   double* out;            // x
   double* cp;             // one sweep: (K - 1) x nlines work (the elimination's pivots);
                           // three kernels: a work array of the size of y
+  double* pr;             // three kernels: 2 (K - 1) x nlines work (node pairs), 16-byte aligned
   const double* tab;      // the axis' band tables (unscaled)
   double coef;            // diff 4 / h^2 of the axis
   double react;
