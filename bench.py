@@ -44,8 +44,9 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
         # them and writes x.  Three-kernel form: cond reads y and writes z and
         # the node right-hand sides, back reads them and writes x, nodes
         # moves the node values (1/n0 of the array) through the elimination:
-        # read g, write g' and the pivot, read both, write x.
-        if name.startswith("bandcond") or name.startswith("bandback"):
+        # read g, write g' and the pivot, read both, write x.  Tiled kernel
+        # (short lines): y read once, x written once.
+        if name.startswith("bandcond") or name.startswith("bandback") or name.startswith("bandtile"):
             return size * 16.0
         if name.startswith("bandnodes"):
             return size * 48.0 / n0
@@ -86,7 +87,7 @@ def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     """Symbol of the kernel that a per-pass timing name refers to."""
     head = name.split("_ax")[0]
     for pre, sym in (("bandcond", "band_cond_kernel"), ("bandnodes", "band_nodes_kernel"),
-                     ("bandback", "band_back_kernel"), ("band", "band_kernel")):
+                     ("bandback", "band_back_kernel"), ("bandtile", "band_tile_kernel"), ("band", "band_kernel")):
         if head.startswith(pre):
             return f"{sym}<{n}>"
     dtype = "double" if head.endswith("64") else "float"

@@ -51,7 +51,8 @@ struct fftfem_plan_s {
   double* W64b = nullptr;    // float64 workspace (transposed 2D schedule, float64 mode)
   double* W64r = nullptr;    // float64 residual (float32 + refinement)
   bool algb = false;         // algorithm (b): banded solve along axis 0
-  bool band_split = false;   // ... in three kernels (few lines) instead of one sweep per line
+  int band_form = 0;         // ... 0: one sweep per line, 1: three kernels (few lines),
+                             // 2: one LDS-tiled kernel (short lines)
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
                              // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
@@ -869,14 +870,22 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   if (!rc && d.precision == FFTFEM_FP32_REFINE)
     rc = dev_alloc(p, (void**)&p->W64r, (size_t)p->size * sizeof(double));
   if (!rc && p->algb) {
-    // one thread per line fills the chip from about 64K lines (256 CUs, 4
-    // waves each); below that the element-parallel three-kernel form
+    // short lines: the LDS-tiled kernel (y read once, x written once);
+    // otherwise one thread per line, which fills the chip from about 64K
+    // lines (256 CUs, 4 waves each), below that the element-parallel
+    // three-kernel form.  FFTFEM_BAND_FORM (0, 1, 2) overrides the choice
+    // where the form applies.
     const int64_t nl = p->size / p->M[0];
-    p->band_split = nl < 65536;
-    if (const char* e = std::getenv("FFTFEM_BAND_SPLIT")) p->band_split = std::atoi(e) != 0;
+    const bool tile_ok = band_tile_lines((int)p->K[0]) > 0;
+    p->band_form = tile_ok ? 2 : (nl < 65536 ? 1 : 0);
+    if (const char* e = std::getenv("FFTFEM_BAND_FORM")) {
+      const int f = std::atoi(e);
+      if (f == 0 || f == 1 || (f == 2 && tile_ok)) p->band_form = f;
+    }
     const size_t nodes = (size_t)std::max<int64_t>(1, p->K[0] - 1) * (size_t)nl;
-    const size_t cnt = p->band_split ? (size_t)((p->size + 1) & ~int64_t(1)) + 2 * nodes : nodes;
-    rc = dev_alloc(p, (void**)&p->Wband, cnt * sizeof(double));
+    if (p->band_form == 0) rc = dev_alloc(p, (void**)&p->Wband, nodes * sizeof(double));
+    if (p->band_form == 1)
+      rc = dev_alloc(p, (void**)&p->Wband, ((size_t)((p->size + 1) & ~int64_t(1)) + 2 * nodes) * sizeof(double));
   }
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
@@ -945,7 +954,7 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
   a.in = src;
   a.out = u;
   a.cp = p->Wband;
-  a.pr = p->band_split ? p->Wband + ((p->size + 1) & ~int64_t(1)) : nullptr;  // 16-byte aligned pairs
+  a.pr = p->band_form == 1 ? p->Wband + ((p->size + 1) & ~int64_t(1)) : nullptr;  // 16-byte aligned pairs
   a.tab = p->dev[0].d[9];
   a.coef = p->coef[0];
   a.react = p->desc.react;
@@ -957,12 +966,15 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
     a.so[e] = g.so[e];
     a.Mo[e] = g.Mo[e];
   }
-  if (p->band_split) {
+  if (p->band_form == 1) {
     static const char* names[3] = {"bandcond64_ax0", "bandnodes64_ax0", "bandback64_ax0"};
     for (int step = 0; step < 3 && !rc; ++step) {
       Timed tm(p, s, names[step]);
       rc = from_hip(launch_band_split(p->nd[0], step, a, s));
     }
+  } else if (p->band_form == 2) {
+    Timed tm(p, s, "bandtile64_ax0");
+    rc = from_hip(launch_band_tile(p->nd[0], a, s));
   } else {
     Timed tm(p, s, "band64_ax0");
     rc = from_hip(launch_band(p->nd[0], a, s));

@@ -328,6 +328,138 @@ __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
   }
 }
 
+// The same solve in one kernel for short lines (K G <= 1024): a workgroup
+// takes G adjacent lines; thread t works on line t mod G and on elements
+// t / G + (256 / G) i.  The condensation keeps z in registers and leaves the
+// node couplings h_L . z, h_R . z and the node loads in LDS; G threads then
+// eliminate the node systems from LDS, and every thread recovers its
+// elements' bubbles and nodes and stores them.  y is read once and x written
+// once, with no work array.
+constexpr int kBandTileEPT = 4;  // elements per thread: K G <= 256 kBandTileEPT
+
+// 1 / x on the node elimination's dependency chain (x > 0 normal).
+__device__ __forceinline__ double band_inv(double x) { return 1.0 / x; }
+
+template <int NORD, int G>
+__global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
+  constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  constexpr int STEP = kBlock / G;
+  extern __shared__ double band_lds[];
+  const int K = a.K;
+  double* pl = band_lds;                    // [K][G]: h_L . z of element e
+  double* pq = pl + (size_t)K * G;          // [K][G]: h_R . z
+  double* yn = pq + (size_t)K * G;          // [K][G]: load of the left node of e; then g'; then x
+  double* pv = yn + (size_t)K * G;          // [K][G]: pivots
+  const int tid = threadIdx.x, l = tid % G, es = tid / G;
+  const int64_t line = (int64_t)blockIdx.x * G + l;
+  const bool live = line < a.nlines;
+  const int64_t S = a.nlines;
+  const double* __restrict__ tb = a.tab;
+  BandLine L;
+  band_line<NORD>(a, live ? line : 0, L);
+  const double* in = a.in + (live ? line : 0);
+  double* out = a.out + (live ? line : 0);
+  double zr[kBandTileEPT][NB];
+#pragma unroll
+  for (int i = 0; i < kBandTileEPT; ++i) {
+    const int e = es + STEP * i;
+    if (e < K && live) {
+      const int64_t b0 = (int64_t)e * NORD;
+      double pL = 0.0, pR = 0.0;
+      if constexpr (nb > 0) {
+        band_z<NORD>(tb, L, in + b0 * S, S, zr[i]);
+#pragma unroll
+        for (int m = 0; m < nb; ++m) {
+          pL += L.hL[m] * zr[i][m];
+          pR += L.hR[m] * zr[i][m];
+        }
+      }
+      pl[e * G + l] = pL;
+      pq[e * G + l] = pR;
+      yn[e * G + l] = e > 0 ? in[(b0 - 1) * S] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid < G && live) {
+    const double sn = L.s, dn = L.d;
+    double ex = sn, rho = 1.0, gprev = 0.0;
+    for (int j = 1; j < K; ++j) {
+      const double g = yn[j * G + l] - pq[(j - 1) * G + l] - pl[j * G + l];
+      ex = dn + rho * ex;
+      const double inv = band_inv(sn + ex);
+      rho = sn * inv;
+      gprev = (g + sn * gprev) * inv;
+      pv[j * G + l] = rho;
+      yn[j * G + l] = gprev;
+    }
+    double x = 0.0;
+    for (int j = K - 1; j >= 1; --j) {
+      x = yn[j * G + l] + pv[j * G + l] * x;
+      yn[j * G + l] = x;
+    }
+    yn[l] = 0.0;  // element 0 has no left node
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kBandTileEPT; ++i) {
+    const int e = es + STEP * i;
+    if (e < K && live) {
+      const int64_t b0 = (int64_t)e * NORD;
+      const double xL = yn[e * G + l];
+      const double xR = e + 1 < K ? yn[(e + 1) * G + l] : 0.0;
+      if (e > 0) out[(b0 - 1) * S] = xL;
+      if constexpr (nb > 0) {
+        double w[NB];
+#pragma unroll
+        for (int m = 0; m < nb; ++m) w[m] = zr[i][m] - L.r[m] * (L.hL[m] * xL + L.hR[m] * xR);
+#pragma unroll
+        for (int r = 0; r < nb; ++r) {
+          double x = 0.0;
+#pragma unroll
+          for (int m = 0; m < nb; ++m) x += tb[r * nb + m] * w[m];
+          out[(b0 + r) * S] = x;
+        }
+      }
+    }
+  }
+}
+
+// Lines per workgroup of the tiled form for K elements (0: not applicable).
+int band_tile_lines(int K) {
+  if (16 * K <= kBlock * kBandTileEPT) return 16;
+  if (8 * K <= kBlock * kBandTileEPT) return 8;
+  return 0;
+}
+
+hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s) {
+  const int G = band_tile_lines(a.K);
+  if (a.nlines < 1 || a.K < 1 || G == 0) return hipErrorInvalidValue;
+  const int64_t nblk = (a.nlines + G - 1) / G;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = (size_t)4 * a.K * G * sizeof(double);
+  switch (n * 100 + G) {
+#define FFTFEM_CASE(N)                                                                                    \
+  case N * 100 + 16:                                                                                      \
+    hipLaunchKernelGGL((band_tile_kernel<N, 16>), dim3((unsigned)nblk), dim3(kBlock), lds, s, a);         \
+    return hipGetLastError();                                                                             \
+  case N * 100 + 8:                                                                                       \
+    hipLaunchKernelGGL((band_tile_kernel<N, 8>), dim3((unsigned)nblk), dim3(kBlock), lds, s, a);          \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) {
   if (a.nlines < 1 || a.K < 1 || a.in == a.cp || a.out == a.cp || !a.pr || step < 0 || step > 2)
     return hipErrorInvalidValue;

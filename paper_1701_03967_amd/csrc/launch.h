@@ -151,6 +151,8 @@ inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, i
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
 hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
+hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s);
+int band_tile_lines(int K);  // lines per workgroup of launch_band_tile for K elements, 0: K too large
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);
 hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s);

@@ -47,18 +47,19 @@ CASES = [((64,), 5, 0.0), ((7,), 9, 2.0), ((40,), 1, 0.0),
          ((8, 12, 10), (3, 2, 4), 0.75), ((16, 16, 16), 9, 0.0), ((5, 6, 7), (2, 1, 3), 10.0)]
 
 
-@pytest.mark.parametrize("split", ["0", "1"])
+@pytest.mark.parametrize("form", ["0", "1", "2"])
 @pytest.mark.parametrize("K,n,react", CASES)
-def test_algorithm_b_solve(fm, monkeypatch, K, n, react, split):
-    """split 0: one sweep per line (one kernel); 1: the element-parallel
-    three-kernel form (the plan's default below 64K lines)."""
-    monkeypatch.setenv("FFTFEM_BAND_SPLIT", split)
+def test_algorithm_b_solve(fm, monkeypatch, K, n, react, form):
+    """form 0: one sweep per line (one kernel); 1: the element-parallel
+    three-kernel form; 2: the LDS-tiled kernel (K_1 <= 128; other K_1 take
+    the plan's default)."""
+    monkeypatch.setenv("FFTFEM_BAND_FORM", form)
     N = len(K)
     diff = (1.0, 0.5, 2.0)[:N]
     ns = osolve.orders(n, N)
     shape = tuple(m * k - 1 for m, k in zip(ns, K))
     f = inputs.draw_rhs(shape, seed=81)
-    say("algorithm b", K, n, react, "split", split)
+    say("algorithm b", K, n, react, "form", form)
     ref = osolve.solve(f, n, K, diff, react)
     p = fm.Plan(K, n, diff, react, algorithm="b")
     assert p.shape == shape
@@ -83,12 +84,13 @@ def test_algorithm_b_several_rhs_and_repeat(fm):
         assert rel(u1[r], ref[r]) < TOL
 
 
-@pytest.mark.parametrize("K", [(1024, 1024), (64, 64, 64)])
-def test_algorithm_b_matches_a_and_residual_full_size(fm, K):
+@pytest.mark.parametrize("K,form", [((1024, 1024), "1"), ((64, 64, 64), "2"), ((64, 64, 64), "0")])
+def test_algorithm_b_matches_a_and_residual_full_size(fm, monkeypatch, K, form):
     """2D n = 9, K = 1024 (84.9M unknowns; three-kernel form) and 3D n = 9,
-    K = 64 (190M; one sweep per line): u_b against the algorithm (a) solve
+    K = 64 (190M; tiled and one-sweep forms): u_b against the algorithm (a) solve
     (itself pinned to the oracle on sampled outputs at these sizes) and the
     relative residual ||f - A u_b|| / ||f|| by the double-double apply."""
+    monkeypatch.setenv("FFTFEM_BAND_FORM", form)
     n, react = 9, 0.0
     diff = (1.0,) * len(K)
     pa = fm.Plan(K, n, diff, react)
@@ -114,14 +116,20 @@ def test_algorithm_b_matches_a_and_residual_full_size(fm, K):
 
 
 def test_algorithm_b_one_sweep_default_many_lines(fm):
-    """3D with more than 64K lines along axis 1: the plan's default one-sweep form."""
-    K, n, diff, react = (6, 40, 40), (3, 7, 7), (1.0, 1.0, 1.0), 0.5
-    shape = tuple(m * k - 1 for m, k in zip(n, K))
-    assert shape[1] * shape[2] >= 65536
-    f = inputs.draw_rhs(shape, seed=86)
-    ref = osolve.solve(f, n, K, diff, react)
-    u = fm.Plan(K, n, diff, react, algorithm="b").solve(torch.from_numpy(f).cuda())
-    assert rel(u.cpu().numpy(), ref) < TOL
+    """3D with K_1 > 128 and more than 64K lines along axis 1: the plan's
+    default one-sweep form, against algorithm (a) (8.7M unknowns; the
+    oracle's refined solve would take minutes)."""
+    K, n, diff, react = (130, 29, 29), (1, 9, 9), (1.0, 1.0, 1.0), 0.5
+    pa = fm.Plan(K, n, diff, react)
+    pb = fm.Plan(K, n, diff, react, algorithm="b")
+    assert pb.shape[1] * pb.shape[2] >= 65536
+    f = torch.from_numpy(inputs.draw_rhs(pb.shape, seed=86)).cuda()
+    ua = pa.solve(f)
+    ub = pb.solve(f)
+    torch.cuda.synchronize()
+    e = float(torch.linalg.norm(ub - ua) / torch.linalg.norm(ua))
+    say("many lines |u_b - u_a| / |u_a|", e)
+    assert e < TOL
 
 
 def test_algorithm_b_implicit_euler(fm):
