@@ -340,6 +340,18 @@ constexpr int kBandTileEPT = 4;  // elements per thread: K G <= 256 kBandTileEPT
 // 1 / x on the node elimination's dependency chain (x > 0 normal).
 __device__ __forceinline__ double band_inv(double x) { return 1.0 / x; }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup i to XCD i mod
+// 8), and each XCD has its own L2.  A tile's rows are 128-byte segments that
+// start anywhere in a cache line (the line count is usually odd), so
+// neighbouring tiles share cache lines; mapping consecutive workgroups of one
+// XCD to consecutive tiles keeps those shared lines in one L2.  A bijection
+// of [0, nblk): XCD x takes tiles [x q + min(x, r), ...) with q = nblk / 8,
+// r = nblk mod 8.
+__device__ __forceinline__ unsigned band_tile_of(unsigned b, unsigned nblk) {
+  const unsigned q = nblk / 8, r = nblk % 8, x = b % 8, slot = b / 8;
+  return x * q + min(x, r) + slot;
+}
+
 template <int NORD, int G>
 __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
   double* yn = pq + (size_t)K * G;          // [K][G]: load of the left node of e; then g'; then x
   double* pv = yn + (size_t)K * G;          // [K][G]: pivots
   const int tid = threadIdx.x, l = tid % G, es = tid / G;
-  const int64_t line = (int64_t)blockIdx.x * G + l;
+  const int64_t line = (int64_t)band_tile_of(blockIdx.x, gridDim.x) * G + l;
   const bool live = line < a.nlines;
   const int64_t S = a.nlines;
   const double* __restrict__ tb = a.tab;
