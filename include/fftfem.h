@@ -236,6 +236,28 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
 int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_t s);
 
 /*
+ * Non-homogeneous Dirichlet data u = b on the boundary (Sect. 4 remarks that
+ * it reduces to eq. `bvp glob 2` with a modified f^h).  On the dofs of the
+ * closed box -- every axis extended by its two boundary points, E_d = M_d + 2
+ * points at x = g h_d / n_d, g = 0 .. E_d - 1, row-major, last axis
+ * contiguous -- the interior equations read A_II u_I = f - A_IB b_B:
+ *
+ *   out = f - (interior rows of the extended operator) (b with its interior zeroed),
+ *
+ * the extended operator being the plan's tensor sum with every 1D stiffness
+ * and mass assembled over all n_d K_d + 1 points.  fftfem_solve(p, out, u)
+ * then gives the interior values of the solution; its boundary values are
+ * b's.  b: device float64, E_1 x .. x E_N per right-hand side (only entries
+ * with some index 0 or E_d - 1 are read); f, out: device float64 in the
+ * interior layout (out may equal f); work: device float64 scratch of
+ * 2 E_1 .. E_N values, overlapping none of the others.  float64 arithmetic,
+ * asynchronous on s, no allocation.  FFTFEM_EINVAL for null pointers or
+ * overlaps, or inside a batch.
+ */
+int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
+                          hipStream_t s);
+
+/*
  * Implicit Euler time stepping of the semi-discrete heat equation of the
  * plan's operator (Sect. 4 remarks that implicit time discretizations of
  * heat-type equations lead at every time level to the system solved here):

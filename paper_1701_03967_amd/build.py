@@ -68,6 +68,7 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
              for kind, p2 in (("p2", 1), ("any", 0)) for real in ("float", "double")]
     units.append(("ops.hip", "ops.o", []))
     units.append(("band.hip", "band.o", []))
+    units.append(("lift.hip", "lift.o", []))
 
     def compile_unit(u):
         src, o, extra = u

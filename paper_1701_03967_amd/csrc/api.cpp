@@ -937,6 +937,13 @@ static bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + na) and [b, b + nb) intersect
+static bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
 // Algorithm (b) of Sect. 4: FC_n transforms along axes N - 1 .. 1 (natural
 // layout, f into u), the banded solve along axis 0 in place, the inverse
 // transforms along axes 1 .. N - 1.
@@ -1175,6 +1182,62 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
     for (int d = p->N - 1; d >= 0 && !rc; --d) {
       rc = line_pass<double>(p, natural_geom(p, d, false), FWD, src, 1, out + o, 1, nullptr, nullptr, s, false);
       src = out + o;
+    }
+  }
+  return rc;
+}
+
+int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
+                          hipStream_t s) {
+  if (!p || !b || !f || !out || !work || p->rec) return FFTFEM_EINVAL;
+  const int N = p->N;
+  int64_t E[3] = {1, 1, 1}, esize = 1;
+  for (int d = 0; d < N; ++d) {
+    E[d] = p->M[d] + 2;
+    esize *= E[d];
+  }
+  const size_t ib = (size_t)p->size * p->nrhs * sizeof(double), eb = (size_t)esize * p->nrhs * sizeof(double);
+  const size_t wb = 2 * (size_t)esize * sizeof(double);
+  if (f != out && overlap(f, out, ib)) return FFTFEM_EINVAL;
+  if (overlap2(b, eb, out, ib) || overlap2(work, wb, out, ib) || overlap2(work, wb, b, eb) ||
+      overlap2(work, wb, f, ib))
+    return FFTFEM_EINVAL;
+  p->last = s;
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r) {
+    const double* br = b + (size_t)r * esize;
+    const double* fr = f + (size_t)r * p->size;
+    double* orr = out + (size_t)r * p->size;
+    double* w[2] = {work, work + esize};
+    // terms: coef_t C x .. x A_t x .. x C for t < N, react C x .. x C
+    for (int t = 0; t <= N && !rc; ++t) {
+      const double scale = t < N ? p->coef[t] : p->desc.react;
+      if (t == N && scale == 0.0) break;
+      int64_t L[3] = {E[0], E[1], E[2]};
+      const double* src = br;
+      for (int d = 0; d < N && !rc; ++d) {
+        LiftArgs a{};
+        a.in = src;
+        a.n = p->nd[d];
+        a.K = (int)p->K[d];
+        a.X = d == t ? p->Ael[d] : p->Cel[d];  // float64 (hi) part
+        a.outer = 1;
+        for (int e = 0; e < d; ++e) a.outer *= L[e];
+        a.inner = 1;
+        for (int e = d + 1; e < N; ++e) a.inner *= L[e];
+        a.mask = d == 0;
+        a.N = N;
+        for (int e = 0; e < 3; ++e) a.ext[e] = E[e];
+        const bool last = d == N - 1;
+        a.out = last ? orr : w[d % 2];
+        a.combine = last;
+        a.scale = scale;
+        a.f = last && t == 0 ? fr : nullptr;
+        Timed tm(p, s, "lift64_ax" + std::to_string(d));
+        rc = from_hip(launch_lift(a, s));
+        src = a.out;
+        L[d] = p->M[d];
+      }
     }
   }
   return rc;

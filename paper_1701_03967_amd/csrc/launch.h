@@ -85,6 +85,22 @@ struct BandArgs {
   int nother;
 };
 
+// One axis pass of the Dirichlet lifting (extended axis of E = nK + 1 points
+// -> its M = nK - 1 interior rows): out[o, i, ii] = sum_q X_ext[i + 1, q] in[o, q, ii].
+struct LiftArgs {
+  const double* in;       // shape outer x E x inner
+  double* out;            // shape outer x M x inner
+  const double* f;        // combine: out = (f ? f : out) - scale * result
+  const double* X;        // (n + 1) x (n + 1) element matrix
+  int n, K;
+  int64_t outer, inner;
+  int mask;               // the input is the extended b: its interior reads as zero
+  int N;
+  int64_t ext[3];         // extended shape of b (mask only)
+  int combine;
+  double scale;
+};
+
 // Jobs of the grouped operator, transpose and bookkeeping launches.
 struct TransposeJob {
   const void* in;
@@ -152,6 +168,7 @@ hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipS
 hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
 hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s);
+hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
 int band_tile_lines(int K);  // lines per workgroup of launch_band_tile for K elements, 0: K too large
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);

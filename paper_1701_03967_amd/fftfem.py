@@ -30,7 +30,7 @@ EXPORTS = [
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
     "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler", "fftfem_tune_save", "fftfem_tune_load",
-    "fftfem_coefficients", "fftfem_synthesize",
+    "fftfem_coefficients", "fftfem_synthesize", "fftfem_dirichlet_load",
 ]
 BATCH_TUNE = 1
 ALGORITHM_B = 1  # fftfem_desc.flags: algorithm (b) of Sect. 4
@@ -112,6 +112,7 @@ def lib():
         L.fftfem_tune_save.argtypes = [ctypes.c_char_p]
         L.fftfem_coefficients.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.fftfem_synthesize.argtypes = [vp, vp, vp, vp]
+        L.fftfem_dirichlet_load.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fftfem_tune_load.argtypes = [ctypes.c_char_p]
         _lib = L
     return _lib
@@ -346,6 +347,36 @@ class Plan:
             out = torch.empty_like(c)
         self._check_tensor(out, "out")
         _check(lib().fftfem_synthesize(self._h, _tptr(c), _tptr(out), _stream_ptr(stream)), "fftfem_synthesize")
+        return out
+
+    @property
+    def extended_shape(self):
+        """Shape of boundary data: every axis with its two boundary points."""
+        sh = tuple(m + 2 for m in self.shape)
+        return (self.nrhs,) + sh if self.nrhs > 1 else sh
+
+    def dirichlet_load(self, b, f, out=None, work=None, stream=None):
+        """f - A_IB b: the load of the homogeneous system whose solution is
+        the interior of the solution with boundary values b (extended-grid
+        float64 device tensor; only its boundary entries are read)."""
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()
+                and tuple(b.shape) == self.extended_shape):
+            raise ValueError(f"b must be a contiguous float64 device tensor of shape {self.extended_shape}")
+        self._check_tensor(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        self._check_tensor(out, "out")
+        ne = 1
+        for m in self.shape:
+            ne *= m + 2
+        if work is None:
+            work = torch.empty(2 * ne, dtype=torch.float64, device=f.device)
+        if not (isinstance(work, torch.Tensor) and work.is_cuda and work.dtype == torch.float64
+                and work.is_contiguous() and work.numel() >= 2 * ne):
+            raise ValueError(f"work must be a contiguous float64 device tensor of at least {2 * ne} values")
+        _check(lib().fftfem_dirichlet_load(self._h, _tptr(b), _tptr(f), _tptr(out), _tptr(work),
+                                           _stream_ptr(stream)), "fftfem_dirichlet_load")
         return out
 
     def implicit_euler(self, u, nsteps: int, F=None, work=None, stream=None):

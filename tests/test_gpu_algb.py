@@ -171,7 +171,7 @@ def test_algorithm_b_paper_error_tables(fm, N, table):
     for n, K, want in _golden_rows(table):
         n, K, want = int(n), int(K), float(want)
         Ks = (K,) * N
-        f = loads.load_vector(fe, n, Ks)
+        f = np.ascontiguousarray(loads.load_vector(fe, n, Ks))
         p = fm.Plan(Ks, n, (1.0,) * N, 1.0, algorithm="b")
         u = p.solve(torch.from_numpy(f).cuda()).cpu().numpy()
         got = loads.max_error(u, ue, n, Ks)
