@@ -84,7 +84,17 @@ def test_null_arguments():
     assert L.fftfem_plan(None, 2, None, 2, None, 0.0) == -1
     assert L.fftfem_solve(None, None, None, None) == -1
     assert L.fftfem_apply_A(None, None, None, None) == -1
+    assert L.fftfem_dirichlet_load(None, None, None, None, None, None) == -1
     L.fftfem_destroy(None)
+
+
+def test_algorithm_option_in_descriptor():
+    """algorithm "b" sets the descriptor flag; anything else is refused
+    before the library is called."""
+    assert fftfem.make_desc((8, 8), 2, (1.0, 1.0), algorithm="b").flags == fftfem.ALGORITHM_B
+    assert fftfem.make_desc((8, 8), 2, (1.0, 1.0)).flags == 0
+    with pytest.raises(ValueError):
+        fftfem.make_desc((8, 8), 2, (1.0, 1.0), algorithm="c")
 
 
 def test_host_element_matrices_match_oracle():
