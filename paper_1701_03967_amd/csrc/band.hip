@@ -234,11 +234,14 @@ __global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
 
 // Node elimination, one thread per line: the forward sweep loads kBandNF
 // right-hand sides ahead, the backward sweep kBandNB pairs (g', pivot).
-constexpr int kBandNF = 24, kBandNB = 24;
+// One-wave workgroups spread the few waves (2D: M_2 / 64) over as many CUs
+// as possible: each wave's sweeps are bound by its own memory latency, and
+// four waves sharing a CU's load path took 0.26 ms against 0.18 ms at C3.
+constexpr int kBandNF = 24, kBandNB = 24, kBandNodesBlock = 64;
 
 template <int NORD>
-__global__ __launch_bounds__(kBlock) void band_nodes_kernel(BandArgs a) {
-  const int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBandNodesBlock) void band_nodes_kernel(BandArgs a) {
+  const int64_t line = (int64_t)blockIdx.x * kBandNodesBlock + threadIdx.x;
   if (line >= a.nlines) return;
   const int64_t S = a.nlines;
   BandLine L;
@@ -477,8 +480,8 @@ hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) 
     return hipErrorInvalidValue;
   const int64_t ept = step == 0 ? kBandEPTc : kBandEPTb;
   const int64_t nb_el = (a.nlines * ((a.K + ept - 1) / ept) + kBlock - 1) / kBlock;
-  const int64_t nb_ln = (a.nlines + kBlock - 1) / kBlock;
-  if (nb_el > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t nb_ln = (a.nlines + kBandNodesBlock - 1) / kBandNodesBlock;
+  if (nb_el > 0x7fffffff || nb_ln > 0x7fffffff) return hipErrorInvalidValue;
   if (step == 1 && a.K < 2) return hipSuccess;  // no nodes
   switch (n) {
 #define FFTFEM_CASE(N)                                                                          \
@@ -486,7 +489,7 @@ hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) 
     if (step == 0)                                                                              \
       hipLaunchKernelGGL((band_cond_kernel<N>), dim3((unsigned)nb_el), dim3(kBlock), 0, s, a);  \
     else if (step == 1)                                                                         \
-      hipLaunchKernelGGL((band_nodes_kernel<N>), dim3((unsigned)nb_ln), dim3(kBlock), 0, s, a); \
+      hipLaunchKernelGGL((band_nodes_kernel<N>), dim3((unsigned)nb_ln), dim3(kBandNodesBlock), 0, s, a); \
     else                                                                                        \
       hipLaunchKernelGGL((band_back_kernel<N>), dim3((unsigned)nb_el), dim3(kBlock), 0, s, a);  \
     return hipGetLastError();
