@@ -118,9 +118,12 @@ int fftfem_plan(fftfem_plan_t* out, int N, const int64_t* K, int n, const double
 int fftfem_plan_ex(fftfem_plan_t* out, const fftfem_desc* desc);
 
 /*
- * Solve A u = f (algorithm (a) of Sect. 4, or (b) with FFTFEM_ALGORITHM_B:
- * then the plan also holds a (K_1 - 1) M_2 .. M_N float64 work array for the
- * elimination).  f, u: device float64 arrays in
+ * Solve A u = f (algorithm (a) of Sect. 4, or (b) with FFTFEM_ALGORITHM_B).
+ * For (b) the plan holds the banded solve's float64 work, chosen with its
+ * form at plan time: none for K_1 <= 128 (one LDS-tiled kernel),
+ * (K_1 - 1) M_2 .. M_N values with at least 64K lines (one sweep per line),
+ * else M_1 .. M_N + 2 (K_1 - 1) M_2 .. M_N values (three kernels); see
+ * fftfem_workspace_bytes.  f, u: device float64 arrays in
  * the layout above (times nrhs).  f is read only; u must not overlap f.
  * Asynchronous on stream s (NULL = default stream); no host synchronization
  * and no allocation.  A plan may be used by one stream at a time.
