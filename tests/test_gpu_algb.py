@@ -178,3 +178,16 @@ def test_algorithm_b_paper_error_tables(fm, N, table):
         say(table, n, K, "error", got, "paper", want)
         tol = 0.05 if want > 1e-10 else 0.10
         assert abs(got / want - 1) < tol, (n, K, got, want)
+
+
+def test_algorithm_b_tuned_plan(fm):
+    """Measuring line-pass parameters on an algorithm (b) plan leaves its
+    solve within the bar (the transforms along axis 2 take the tuned tiles)."""
+    K, n, diff, react = (64, 96), (5, 3), (1.0, 1.0), 0.5
+    shape = tuple(m * k - 1 for m, k in zip(n, K))
+    f = inputs.draw_rhs(shape, seed=87)
+    ref = osolve.solve(f, n, K, diff, react)
+    p = fm.Plan(K, n, diff, react, algorithm="b")
+    p.tune()
+    u = p.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert rel(u, ref) < TOL
