@@ -22,14 +22,15 @@
 // term proportional to sigma, d proportional to sigma), and the
 // elimination carries e_j = den_j - s, which obeys
 // e_j = d + s e_{j-1} / den_{j-1} (e_1 = s + d), a sum of non-negative terms.
-// The small eigenvalues of the node system, s (1 - cos(pi k / K)) + d, then
-// keep their relative accuracy; forming 2a and b directly would lose about
-// (K / pi)^2 eps of it.  A backward sweep substitutes the nodes and recovers
-// the bubbles x_B = V (z - (h_L x_L + h_R x_R) / (coef lam + sigma)).
+// The small eigenvalues of the node system, 2 s (1 - cos(pi k / K)) + d,
+// then keep their relative accuracy; forming 2a and b directly would lose
+// about (K / pi)^2 eps of it.  A backward sweep substitutes the nodes and
+// recovers the bubbles x_B = V (z - (h_L x_L + h_R x_R) / (coef lam + sigma)).
 //
-// One thread per line: element i of line l is at i * nlines + l, so a wave's
-// 64 threads read and write 64 consecutive values per access.  The next
-// element's values are loaded before the current one is processed.
+// Element i of line l is at i * nlines + l, so threads taking consecutive
+// lines read and write consecutive values.  Three forms follow: one sweep
+// per line (band_kernel), three element-parallel kernels for few long lines,
+// and one LDS-tiled kernel for short lines.
 #include "device_common.h"
 #include "launch.h"
 
@@ -84,6 +85,8 @@ __device__ __forceinline__ void band_z(const double* __restrict__ tb, const Band
   }
 }
 
+// One thread per line; the next element's values are loaded before the
+// current one is processed.
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
