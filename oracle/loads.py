@@ -128,14 +128,17 @@ def paper_3d():
     return s.lambdify((x1, x2, x3), u, "numpy"), s.lambdify((x1, x2, x3), f, "numpy")
 
 
-def sin_product(freqs: Sequence[int], diff: Sequence[float], react: float = 0.0):
-    """u = prod_d sin(m_d pi x_d) and f = (sum_d diff[d] (m_d pi)^2 + react) u."""
-    lam = sum(dd * (m * np.pi) ** 2 for dd, m in zip(diff, freqs)) + react
+def sin_product(freqs: Sequence[int], diff: Sequence[float], react: float = 0.0, X=None):
+    """u = prod_d sin(m_d pi x_d / X_d), which vanishes on the boundary of the
+    box (0, X_1) x ... x (0, X_N) (Sect. 4), and
+    f = -sum_d diff[d] d^2u/dx_d^2 + react u = (sum_d diff[d] (m_d pi / X_d)^2 + react) u."""
+    X = [1.0] * len(freqs) if X is None else list(X)
+    lam = sum(dd * (m * np.pi / x) ** 2 for dd, m, x in zip(diff, freqs, X)) + react
 
     def u(*xs):
         out = 1.0
-        for m, x in zip(freqs, xs):
-            out = out * np.sin(m * np.pi * x)
+        for m, x, xl in zip(freqs, xs, X):
+            out = out * np.sin(m * np.pi * x / xl)
         return out
 
     def f(*xs):

@@ -421,3 +421,61 @@ def test_mixed_orders_separable_mode():
     f = den * solve.mode_product(fem1d.assemble(ns[1], K[1])[1], solve.mode_product(fem1d.assemble(ns[0], K[0])[1], u, 0), 1)
     got = solve.solve(f, ns, K, diff, react)
     assert np.linalg.norm(got - u) / np.linalg.norm(u) < 1e-12
+
+
+# --- non-unit domain lengths X_d (Sect. 4: the box (0,X_1) x .. x (0,X_N)) --
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_nonunit_box_l2_convergence(n):
+    """u* = sin(pi x/X_1) sin(2 pi y/X_2) on the box (0, 0.5) x (0, 2) with
+    diff (1, 0.25), react 3: the load f^h of Gauss quadrature over that box and
+    the oracle's solve with h_d = X_d / K_d give an L2 error of order n+1 per
+    halving of h, at a size that matches h (a wrong h, e.g. K/X, or a load
+    scaled for the unit box, fails both)."""
+    X, diff, react = (0.5, 2.0), (1.0, 0.25), 3.0
+    ue, fe = loads.sin_product((1, 2), diff, react, X=X)
+    errs = []
+    Ks = (4, 8) if n >= 4 else (8, 16)
+    for K in Ks:
+        f = loads.load_vector(fe, n, (K, K), X=X)
+        u = solve.solve(f, n, (K, K), diff, react, X=X)
+        errs.append(loads.l2_error(u, ue, n, (K, K), X=X))
+    rate = math.log2(errs[0] / errs[1])
+    assert abs(rate - (n + 1)) < 0.3, (errs, rate)
+    # the L2 norm of u* over the box is sqrt(X_1 X_2) / 2 = 0.5
+    assert errs[1] < 1e-3 * 0.5
+
+
+def test_nonunit_box_operator_against_continuum():
+    """A u for u = the interpolant of sin(pi x/X_1) sin(pi y/X_2) on the box
+    (0, 2) x (0, 0.25) equals, to O(h^n), the load of
+    (diff_1 (pi/X_1)^2 + diff_2 (pi/X_2)^2) u: the coefficients enter as
+    diff_d 4 / h_d^2 with h_d = X_d / K_d."""
+    n, K, X, diff = 4, (8, 8), (2.0, 0.25), (1.0, 3.0)
+    ue, fe = loads.sin_product((1, 1), diff, X=X)
+    u = loads.interpolate(ue, n, K, X=X)
+    Au = solve.apply_A(u, n, K, diff, 0.0, X=X)
+    fh = loads.load_vector(fe, n, K, X=X)
+    assert np.abs(Au - fh).max() < 1e-3 * np.abs(fh).max()
+
+
+def test_nonunit_box_change_of_variables():
+    """x_d -> x_d / X_d maps the box onto the unit box and diff_d onto
+    diff_d / X_d^2, with the same scaled load: the solutions coincide."""
+    n, K, X, diff, react = 3, (5, 4, 3), (0.5, 2.0, 1.5), (1.0, 0.5, 2.0), 0.75
+    f = np.random.default_rng(17).standard_normal([n * k - 1 for k in K])
+    u1 = solve.solve(f, n, K, diff, react, X=X)
+    u2 = solve.solve(f, n, K, [d / (x * x) for d, x in zip(diff, X)], react)
+    assert np.linalg.norm(u1 - u2) / np.linalg.norm(u2) < 1e-13
+
+
+@pytest.mark.parametrize("N,n,K", [(2, 2, (4, 3)), (2, 4, (3, 2)), (3, 2, (2, 3, 2))])
+def test_nonunit_box_eigen_solve_matches_cholesky(N, n, K):
+    """Tiny meshes on the box with X = (0.5, 2, 1.25): per-axis eigen solve ==
+    dense Cholesky of the assembled N-D matrix."""
+    X = (0.5, 2.0, 1.25)[:N]
+    diff = (1.0, 0.25, 2.0)[:N]
+    f = np.random.default_rng(12).standard_normal([n * k - 1 for k in K])
+    u1 = solve.solve(f, n, K, diff, 0.5, X=X)
+    u2 = solve.solve_cholesky(f, n, K, diff, 0.5, X=X)
+    assert np.linalg.norm(u1 - u2) / np.linalg.norm(u2) < 1e-11
