@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,7 +38,25 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
     if name.startswith("transpose"):
         return size * 2 * t
     if name.startswith("apply"):
-        return 0.0
+        # operator passes, first (last axis) .. last (axis 0): the first reads
+        # u and writes two products, the middle ones (3D) read two and write
+        # two, the last reads two and f (or r) and writes r; double-double
+        # passes carry hi and lo planes (16 bytes per value), plain float64
+        # passes one (incremental residual r -= A c: the last pass reads r)
+        dd = not name.startswith("apply64")
+        ax = int(name.rsplit("_ax", 1)[1].rstrip("t"))
+        v = 16 if dd else 8
+        if N == 1:
+            return size * 24.0
+        if ax == N - 1:
+            return size * (8.0 + 2 * v)
+        if ax > 0:
+            return size * 4.0 * v
+        return size * (2 * v + 8.0 + 8.0)
+    if name.startswith("resid2"):
+        # fused 2D residual: reads u (or the correction) and f (or r),
+        # writes r
+        return size * 24.0
     if name.startswith("band"):
         # algorithm (b) along axis 0 (order n0).  One-sweep kernel: the first
         # sweep reads y and writes z and the node pivots, the second reads
@@ -54,18 +73,19 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
     last = N - 1
     ax_s = name.rsplit("_ax", 1)[1]
     ax = int(ax_s.rstrip("t"))
+    # the update passes of the refinement read u and write u (float64); with
+    # N >= 2 they also store the correction (float64)
+    upd = (16.0 if N >= 2 else 8.0) if "upd" in name else 0.0
     if name.startswith("fwd"):
         rd = 8 if ax == last else t
         return size * (rd + t)
     if name.startswith("mid"):
         rd = 8 if N == 1 else t
         wr = 8 if N == 1 else t
-        extra = 16 if "upd" in name else 0
-        return size * (rd + wr + extra)
+        return size * (rd + wr + upd)
     if name.startswith("inv"):
         wr = 8 if ax == last else t
-        extra = 8 if "upd" in name else 0
-        return size * (t + wr + extra)
+        return size * (t + wr + upd)
     return 0.0
 
 
@@ -89,7 +109,16 @@ def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     for pre, sym in (("bandcond", "band_cond_kernel"), ("bandnodes", "band_nodes_kernel"),
                      ("bandback", "band_back_kernel"), ("bandtile", "band_tile_kernel"), ("band", "band_kernel")):
         if head.startswith(pre):
-            return f"{sym}<{n}>"
+            # the tiled kernel also carries its lines per workgroup: match
+            # the symbol's prefix
+            return f"{sym}<{n}, " if pre == "bandtile" else f"{sym}<{n}>"
+    if head.startswith("resid2"):
+        return f"resid2_kernel<{n}, {'true' if head == 'resid2dd' else 'false'}>"
+    if head.startswith("apply"):
+        dd = not head.startswith("apply64")
+        ax = int(name.rsplit("_ax", 1)[1].rstrip("t"))
+        lo = dd and ax != N - 1
+        return f"apply_kernel<{n}, {'true' if lo else 'false'}, {'true' if dd else 'false'}>"
     dtype = "double" if head.endswith("64") else "float"
     mode = 0 if head.startswith("fwd") else (1 if head.startswith("inv") else 2)
     upd = "true" if "upd" in head else "false"
@@ -179,64 +208,150 @@ def time_mode(fm, torch, prob, f, precision, steps, warmup, timing=True, tune=Fa
             plan.solve(f, u)
         g.replay()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        gev[0].record()
+        for i in range(steps):
             g.replay()
-        e1.record()
+            gev[i + 1].record()
         torch.cuda.synchronize()
-        extra["graph_ms"] = e0.elapsed_time(e1) / steps
+        gper = [gev[i].elapsed_time(gev[i + 1]) for i in range(steps)]
+        extra["graph_ms"] = gev[0].elapsed_time(gev[steps]) / steps
+        extra["graph_median_ms"] = float(np.median(gper))
         del g
     return plan, u, ms, kt, st, extra
 
 
-def cpu_baseline(prob, budget_s: float = 20.0):
-    """The oracle's solve phase, timed on samples of the same workload.
+def golden_path(workload: str) -> str:
+    return os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}.txt")
 
-    The oracle solves by dense per-axis eigenvectors (mode products = dense
-    GEMMs) plus refinement with an extended-precision residual.  Timed here:
-    one mode product on a block of columns and one extended residual on a
-    block of rows, scaled to the full problem; the per-axis dense
-    eigendecomposition (plan work, excluded from the paper's timings as well)
-    is not included.  Assumes two refinement steps.
+
+def load_golden(workload: str):
+    """The oracle's stored solution of a full-size workload (written by
+    tests/golden/make_fullsize.py from the CPU oracle): global norms and
+    projections, sampled indices and values, and the refinement corrections
+    the oracle's solve computed.  None if there is no fixture."""
+    path = golden_path(workload)
+    if not os.path.exists(path):
+        return None
+    glob, idx, val, corr = {}, [], [], None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#"):
+                if "relative corrections" in line:
+                    corr = len(re.findall(r"\d\.\d+e[-+]\d+", line.split("relative corrections", 1)[1]))
+                continue
+            if not line:
+                continue
+            a, b = line.split()
+            if a in ("l2", "max", "sum") or a.startswith("proj"):
+                glob[a] = float(b)
+            else:
+                idx.append(int(a))
+                val.append(float(b))
+    return {"glob": glob, "idx": np.array(idx, dtype=np.int64), "val": np.array(val), "corrections": corr}
+
+
+class OracleCheck:
+    """Relative errors of a device solution against the oracle's stored one:
+    over the stored samples (l2), and the largest difference of the inner
+    products with the seeded sign vectors relative to ||u|| (any error of the
+    solution moves them by about its l2 norm, wherever it sits)."""
+
+    def __init__(self, torch, workload: str, shape):
+        self.g = load_golden(workload)
+        self.torch = torch
+        self.probes = []
+        if self.g is not None:
+            self.idx = torch.from_numpy(self.g["idx"]).cuda()
+            for i in range(inputs.NPROBE):
+                if f"proj{i}" in self.g["glob"]:
+                    self.probes.append((self.g["glob"][f"proj{i}"],
+                                        torch.from_numpy(inputs.probe_vector(shape, i)).cuda().view(-1)))
+
+    def __call__(self, u):
+        if self.g is None:
+            return None
+        flat = u.view(-1)
+        got = flat[self.idx].cpu().numpy()
+        ref = self.g["val"]
+        out = {"samples": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        l2 = self.g["glob"]["l2"]
+        if self.probes:
+            out["proj"] = float(max(abs(float(self.torch.dot(w, flat)) - v) for v, w in self.probes) / l2)
+        out["max"] = max(out.values())
+        return out
+
+
+def cpu_baseline(prob, workload: str):
+    """The CPU oracle's solve, timed on the host cores (a bounded sample).
+
+    The oracle solves by dense per-axis eigenvectors: u = S (S^T f / den)
+    with the Kronecker factors applied as mode products (dense GEMMs), then
+    refinement with the residual of the exact operator in extended precision.
+    Timed here with the oracle's own functions: one whole apply_inverse at
+    the full size (its GEMM cost does not depend on the values, so random
+    factors stand in for the eigenvectors), and the extended-precision
+    residual on a block of lines at full line length, scaled to the array.
+    The solve is one apply_inverse plus, per refinement correction the
+    oracle computed for this workload (its stored history), one residual and
+    one apply_inverse.  The eigendecomposition (plan work, which the paper
+    also leaves out of its timings) is reported separately: timed at the
+    full size when the axis has at most 2000 dofs, else on the same order
+    with K/4 elements and scaled by the cube of the size ratio.
     """
-    from oracle import solve as osolve
+    from oracle import fem1d, solve as osolve
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        blas = os.cpu_count() or 1
     shape = prob.shape
-    N = prob.N
     size = prob.size
-    g = np.random.default_rng(0)
-    t_inverse = 0.0
-    for d in range(N):
-        M = shape[d]
-        b = max(1, min(size // M, 1024 if N == 2 else 4096))
-        S = g.standard_normal((M, M))
-        blk = g.standard_normal((M, b))
-        t0 = time.perf_counter()
-        osolve.mode_product(S, blk, 0)
-        dt = time.perf_counter() - t0
-        t_inverse += 2 * dt * (size / M) / b  # forward and inverse along axis d
+    g = inputs.generator(0)
+    f = g.standard_normal(shape)
+    # one apply_inverse at full size
+    s = osolve.EigenSolver.__new__(osolve.EigenSolver)
+    s.S = [g.standard_normal((m, m)) for m in shape]
+    s.den = np.ones(shape)
+    t0 = time.perf_counter()
+    s.apply_inverse(f)
+    t_inv = time.perf_counter() - t0
+    del s
     # extended-precision residual on a block of lines along axis 0
-    rows = max(1, min(shape[0], int(200000 // max(1, size // shape[0]))))
-    blk = g.standard_normal((rows,) + tuple(shape[1:]))
-    Kb = ((rows + 1) // prob.n,) + tuple(prob.K[1:])
-    blk = blk[: prob.n * Kb[0] - 1]
+    rows = max(1, min(shape[0], int(4000000 // max(1, size // shape[0]))))
+    Kb = (max(1, (rows + 1) // prob.n),) + tuple(prob.K[1:])
+    blk = np.ascontiguousarray(f[: prob.n * Kb[0] - 1])
     t0 = time.perf_counter()
     osolve.apply_A(blk, prob.n, Kb, prob.diff, prob.react, extended=True)
     t_res = (time.perf_counter() - t0) * size / blk.size
-    refine = 2
-    total = (1 + refine) * t_inverse + refine * t_res
-    return {"value": size / total, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"dense-eigen oracle, solve phase projected from timed samples: one mode "
-                       f"product per axis on a column block ({t_inverse:.2f}s/solve scaled) and one "
-                       f"extended-precision residual on {blk.shape[0]} lines ({t_res:.2f}s scaled); "
-                       f"{refine} refinement steps; eigendecomposition excluded"),
-            "seconds_per_solve": total}
+    del f, blk
+    gold = load_golden(workload)
+    ncorr = gold["corrections"] if gold and gold["corrections"] else 3
+    total = (1 + ncorr) * t_inv + ncorr * t_res
+    # eigendecomposition of one axis
+    M = shape[0]
+    Ke = prob.K[0] if M <= 2000 else max(2, prob.K[0] // 4)
+    t0 = time.perf_counter()
+    fem1d.dense_eigen(prob.n, Ke)
+    t_eig = (time.perf_counter() - t0) * ((prob.n * prob.K[0] - 1) / (prob.n * Ke - 1)) ** 3
+    axes = len(set(prob.K))
+    return {"value": size / total, "unit": "unknowns/s", "cores": int(blas), "kind": "oracle",
+            "host_cpus": os.cpu_count(),
+            "sample": (f"dense-eigen oracle solve: one apply_inverse timed at full size ({t_inv:.2f} s), the "
+                       f"extended-precision residual timed on {blk_rows(prob, Kb)} of {shape[0]} lines along "
+                       f"axis 0 and scaled ({t_res:.2f} s per residual); {ncorr} refinement corrections "
+                       f"(the oracle's history for this workload); eigendecomposition excluded"),
+            "seconds_per_solve": total, "apply_inverse_s": t_inv, "residual_s": t_res,
+            "refinement_corrections": ncorr,
+            "eigendecomposition_s": t_eig * axes,
+            "eigendecomposition": (f"{axes} distinct axis pencil(s) of size {M}: "
+                                   + ("timed" if Ke == prob.K[0] else
+                                      f"timed at K={Ke} (size {prob.n * Ke - 1}) and scaled by the size ratio cubed"))}
+
+
+def blk_rows(prob, Kb):
+    return prob.n * Kb[0] - 1
 
 
 def run_batch(args, torch, fm):
@@ -432,8 +547,8 @@ def main():
                     help="c5_batch: precision mode of every problem")
     ap.add_argument("--heat-steps", type=int, default=10, help="heat: implicit Euler steps per timed step")
     ap.add_argument("--heat-precision", default="fp64", choices=("fp64", "fp32_refine", "fp32"))
-    ap.add_argument("--graph", action="store_true",
-                    help="also time replays of one solve captured in a hipGraph")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the timing of replays of one solve captured in a hipGraph")
     ap.add_argument("--tune", action="store_true", help="measure line-pass parameters first (N >= 2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES (profiler counter scale)")
@@ -456,62 +571,75 @@ def main():
         run_batch(args, torch, fm)
         return
 
+    def roofline_of(kt, prob, workload, steps_timed):
+        """Roofline of the dominant kernel of one mode (the most total time
+        per step), from its mean HIP-event duration on the plan's stream."""
+        if not kt:
+            return None
+        name, (avg_ms, cnt) = max(kt.items(), key=lambda kv: kv[1][0] * kv[1][1])
+        by = kernel_bytes(name, prob.size, prob.N, prob.n)
+        if by <= 0:
+            return None
+        gbs = by / (avg_ms * 1e-3) / 1e9
+        ax = int(name.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in name else 0
+        kname = profiler_kernel_name(name, prob.n, prob.N, prob.K[ax])
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, kname),
+                "kernel": name, "symbol": kname, "bytes_per_launch": by, "avg_ms": avg_ms,
+                "launches_per_step": cnt / steps_timed}
+
     def run(name, full):
         w = inputs.WORKLOADS[name]
         prob = w.problem
         f_host = inputs.workload_rhs(name)
         f = torch.from_numpy(f_host).cuda()
         del f_host
+        check = OracleCheck(torch, name, prob.shape)
         out = {"unknowns": prob.size}
         sols = {}
-        kts = {}
         for mode in args.modes.split(","):
             steps = args.steps if full else max(5, args.steps // 3)
             plan, u, ms, kt, st, extra = time_mode(fm, torch, prob, f, mode, steps, args.warmup, tune=args.tune,
-                                                   graph=args.graph)
+                                                   graph=not args.no_graph)
             sols[mode] = u.clone()
-            kts[mode] = kt
             rec = {"ms": ms, "unknowns_per_s": prob.size / (ms * 1e-3), **extra}
             if mode == "fp32_refine":
                 rec["iterations"] = st["iterations"]
                 rec["rel_correction"] = st["rel_correction"]
+            rec["converged"] = st["converged"]
+            rec["stop"] = st["stop"]
+            rec["err_vs_oracle"] = check(u)
+            tol = 1e-5 if mode == "fp32" else 1e-10
+            rec["err_tol"] = tol
+            if rec["err_vs_oracle"] is not None:
+                rec["err_ok"] = rec["err_vs_oracle"]["max"] <= tol
             rec["kernels_ms"] = {k: round(v[0], 5) for k, v in kt.items()}
-            if mode == "fp64_b":
-                rec["band_GBps"] = {k: round(kernel_bytes(k, prob.size, prob.N, prob.n) / (avg * 1e-3) / 1e9, 1)
-                                    for k, (avg, _) in kt.items() if k.startswith("band")}
+            rec["kernels_per_step"] = {k: v[1] / min(steps, 10) for k, v in kt.items()}
+            rec["stage_GBps"] = {k: round(kernel_bytes(k, prob.size, prob.N, prob.n) / (avg * 1e-3) / 1e9, 1)
+                                 for k, (avg, _) in kt.items() if kernel_bytes(k, prob.size, prob.N, prob.n) > 0}
+            step_bytes = sum(kernel_bytes(k, prob.size, prob.N, prob.n) * c / min(steps, 10) for k, (_, c) in kt.items())
+            rec["bytes_per_step"] = step_bytes
+            rec["step_GBps"] = round(step_bytes / (ms * 1e-3) / 1e9, 1)
+            rec["roofline"] = roofline_of(kt, prob, name, min(steps, 10))
             out[mode] = rec
             del plan
-            print(f"[bench] {name} {mode}: {ms:.3f} ms/solve", file=sys.stderr, flush=True)
+            print(f"[bench] {name} {mode}: {ms:.3f} ms/solve, err vs oracle {rec['err_vs_oracle']}",
+                  file=sys.stderr, flush=True)
         if "fp64" in sols:
             ref = sols["fp64"]
             for mode, u in sols.items():
                 if mode != "fp64":
                     out[mode]["rel_l2_vs_fp64"] = float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
-        return prob, out, kts, sols
+        del check
+        return prob, out, sols
 
-    prob, res, kts, sols = run(args.workload, True)
+    prob, res, sols = run(args.workload, True)
     # headline: the faster of the two float64 solves (algorithms (a) and (b)
     # of Sect. 4 solve the same system to the same accuracy)
     f64 = [m for m in ("fp64", "fp64_b") if m in res]
     best_mode = min(f64, key=lambda m: res[m]["ms"]) if f64 else args.modes.split(",")[0]
     ms = res[best_mode]["ms"]
     value = prob.size / (ms * 1e-3)
-    # dominant kernel of the headline mode
-    kt = kts[best_mode]
-    roof = None
-    if kt:
-        dom = max(kt.items(), key=lambda kv: kv[1][0] * kv[1][1])
-        name, (avg_ms, cnt) = dom
-        by = kernel_bytes(name, prob.size, prob.N, prob.n)
-        if by > 0:
-            gbs = by / (avg_ms * 1e-3) / 1e9
-            ax = int(name.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in name else 0
-            kname = profiler_kernel_name(name, prob.n, prob.N, prob.K[ax])
-            traffic = measured_traffic(args.workload, kname)
-            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                    "kernel": name, "symbol": kname, "bytes_per_launch": by, "avg_ms": avg_ms,
-                    "launches_per_step": cnt / min(args.steps, 10)}
     line = {
         "metric": METRIC,
         "value": value,
@@ -529,19 +657,23 @@ def main():
                    "diff": list(prob.diff), "react": prob.react, "unknowns": prob.size,
                    "mode": best_mode, "algorithm": "b" if best_mode == "fp64_b" else "a", "rhs": inputs.WORKLOADS[args.workload].rhs,
                    "seed": inputs.WORKLOADS[args.workload].seed, "tuned": bool(args.tune)},
+        "err_vs_oracle": res[best_mode]["err_vs_oracle"],
         "modes": {m: res[m] for m in res if m != "unknowns"},
-        "roofline": roof,
+        "roofline": res[best_mode]["roofline"],
     }
+    if "fp64" in res and best_mode != "fp64":
+        # algorithm (a), every axis transformed, beside the headline
+        line["roofline_algorithm_a"] = res["fp64"]["roofline"]
     if args.also:
         del sols
         torch.cuda.empty_cache()
-        p2, res2, kts2, sols2 = run(args.also, False)
-        line["also"] = {args.also: {m: {k: v for k, v in res2[m].items() if k != "kernels_ms"}
+        p2, res2, sols2 = run(args.also, False)
+        line["also"] = {args.also: {m: {k: v for k, v in res2[m].items() if k != "kernels_per_step"}
                                     for m in res2 if m != "unknowns"}}
         line["also"][args.also]["unknowns"] = p2.size
         del sols2
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob)
+        line["cpu_baseline"] = cpu_baseline(prob, args.workload)
     print(json.dumps(line))
 
 

@@ -96,11 +96,25 @@ typedef struct {
                                      0 -> n; M_d = n_axis[d] K[d] - 1 */
 } fftfem_desc;
 
-/* Refinement statistics of the last fftfem_solve on a plan. */
+/* Why the refinement of a solve stopped (fftfem_stats.stop). */
+enum {
+  FFTFEM_STOP_NONE = 0,       /* no refinement (FFTFEM_FP64 / FFTFEM_FP32) and a finite solution */
+  FFTFEM_STOP_TOL = 1,        /* the relative correction reached tol */
+  FFTFEM_STOP_MAX_ITER = 2,   /* max_iter corrections applied without reaching tol */
+  FFTFEM_STOP_NONFINITE = 3,  /* a NaN or Inf in the solution or in a correction (e.g. in f) */
+  FFTFEM_STOP_STALLED = 4     /* a correction was not smaller than the one before (no contraction) */
+};
+
+/* Refinement statistics of the last fftfem_solve on a plan.  With several
+ * right-hand sides: the largest iteration count and relative corrections
+ * (NaN if any is NaN), converged only if every right-hand side converged,
+ * and the stop reason of the worst one (NONFINITE, STALLED, MAX_ITER, TOL,
+ * NONE in that order). */
 typedef struct {
   int iterations;                     /* refinement corrections applied */
-  int converged;                      /* 1 if the last relative correction <= tol */
+  int converged;                      /* 1: stop is FFTFEM_STOP_TOL or FFTFEM_STOP_NONE */
   double rel_correction[FFTFEM_MAX_ITERS + 1];  /* ||c_i|| / ||u_i|| per iteration, i = 0 is the first solve */
+  int stop;                           /* FFTFEM_STOP_* */
 } fftfem_stats;
 
 /*
@@ -137,7 +151,16 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s);
  */
 int fftfem_apply_A(fftfem_plan_t p, const double* u, double* y, hipStream_t s);
 
-/* Statistics of the last solve.  Synchronizes the plan's last stream. */
+/*
+ * Statistics of the last solve.  Synchronizes the plan's last stream.  The
+ * device checks every value of the solution a solve writes for NaN and Inf
+ * (in the output pass of the line kernels; a one-dimensional algorithm (b)
+ * solve, whose output pass is the banded solve, is not checked), and in
+ * FFTFEM_FP32_REFINE mode every correction: a non-finite value ends the
+ * refinement.  Returns FFTFEM_ENOCONV, with *out filled in, when the solve
+ * did not converge (out->converged == 0: a non-finite solution, or a
+ * refinement that stopped short of tol), FFTFEM_OK otherwise.
+ */
 int fftfem_get_stats(fftfem_plan_t p, fftfem_stats* out);
 
 /* Device bytes owned by the plan (tables + workspace). */
@@ -239,8 +262,8 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
 int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_t s);
 
 /*
- * Non-homogeneous Dirichlet data u = b on the boundary (Sect. 4 remarks that
- * it reduces to eq. `bvp glob 2` with a modified f^h).  On the dofs of the
+ * Non-homogeneous Dirichlet data u = b on the boundary (Sect. 4: only the
+ * load of the scaled global system changes).  On the dofs of the
  * closed box -- every axis extended by its two boundary points, E_d = M_d + 2
  * points at x = g h_d / n_d, g = 0 .. E_d - 1, row-major, last axis
  * contiguous -- the interior equations read A_II u_I = f - A_IB b_B:
@@ -259,6 +282,7 @@ int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_
  */
 int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
                           hipStream_t s);
+
 
 /*
  * Implicit Euler time stepping of the semi-discrete heat equation of the

@@ -11,7 +11,7 @@ equations of the interior dofs read
 so u_I solves the homogeneous system with the load f^h - A_IB b_B, where
 A_IB b_B is the interior part of the extended operator applied to b with its
 interior values set to zero.  The extended operator is the same tensor sum
-as in eq. `bvp glob 2`, built from the 1D scaled stiffness and mass
+as in the scaled global system of Sect. 4, built from the 1D scaled stiffness and mass
 assembled over all n K + 1 points (no rows or columns dropped).
 """
 from __future__ import annotations

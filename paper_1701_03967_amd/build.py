@@ -37,27 +37,60 @@ def _run(cmd):
     return time.time() - t
 
 
-def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=(), any_defines=None) -> str:
+def _fresh(obj: str, srcs) -> bool:
+    """The object exists and is newer than every source and header."""
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(x) < t for x in srcs)
+
+
+def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=(), any_defines=None,
+          incremental: bool = False) -> str:
     """Compile and link the library.  `defines` (``NAME=VALUE`` strings) are
     passed to the kernel compiles, `any_defines` additionally to the objects
     for element counts that are not powers of two (default ANY_DEFINES),
-    `lib` and `build_dir` place the outputs."""
+    `lib` and `build_dir` place the outputs.  `incremental` keeps objects
+    newer than every source and header of the library (same defines
+    assumed); by default everything is compiled."""
     BUILD = build_dir
     LIB = lib
     dflags = [f"-D{d}" for d in defines]
     os.makedirs(BUILD, exist_ok=True)
+    def deps(src):
+        """The source and the project headers it includes, transitively."""
+        seen, todo = set(), [os.path.join(CSRC, src)]
+        while todo:
+            f = todo.pop()
+            if f in seen or not os.path.exists(f):
+                continue
+            seen.add(f)
+            with open(f) as fh:
+                for line in fh:
+                    line = line.strip()
+                    if line.startswith('#include "'):
+                        h = line.split('"')[1]
+                        todo += [os.path.join(CSRC, h), os.path.join(INCLUDE, h)]
+        return sorted(seen)
+
+    def keep(obj, src):
+        return incremental and _fresh(obj, deps(src))
+
     objs = []
     plan_o = os.path.join(BUILD, "plan.o")
-    dt = _run(["g++", "-O2", "-std=gnu++17", "-fPIC", "-pthread", "-Wall", "-I", CSRC, "-I", INCLUDE,
-               "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
+    if not keep(plan_o, "plan.cpp"):
+        dt = _run(["g++", "-O2", "-std=gnu++17", "-fPIC", "-pthread", "-Wall", "-I", CSRC, "-I", INCLUDE,
+                   "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
+        if verbose:
+            print(f"[build] plan.cpp {dt:.1f}s", flush=True)
     objs.append(plan_o)
-    if verbose:
-        print(f"[build] plan.cpp {dt:.1f}s", flush=True)
     for src in ("api.cpp", "batch.cpp"):
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        objs.append(obj)
+        if keep(obj, src):
+            continue
         dt = _run([HIPCC, "-O2", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
                    "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
         if verbose:
             print(f"[build] {src} {dt:.1f}s", flush=True)
     # kernels: line.hip four times (element counts that are powers of two or
@@ -73,6 +106,8 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
     def compile_unit(u):
         src, o, extra = u
         obj = os.path.join(BUILD, o)
+        if keep(obj, src):
+            return obj, f"{src} -> {o} (kept)", 0.0
         dt = _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *DEVICE_FLAGS, *dflags,
                    *extra, "-I", CSRC, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj])
         return obj, f"{src} -> {o}", dt

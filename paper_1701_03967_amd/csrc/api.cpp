@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -59,6 +60,7 @@ struct fftfem_plan_s {
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
   double* tmp[8] = {};       // operator-apply partial products (double-double planes)
   double* cor = nullptr;     // while set: the update pass also stores its correction here
+  int* bad = nullptr;        // while set: output passes without update report non-finite values here
   int ntmp = 0;
   double* partials = nullptr;
   int npartials = 0;
@@ -258,6 +260,7 @@ bool tune_get(const TuneKey& k, TuneVal* v) {
 
 void plan_set_recorder(fftfem_plan_t p, Recorder* r) { p->rec = r; }
 void plan_set_stream(fftfem_plan_t p, hipStream_t s) { p->last = s; }
+size_t plan_array_bytes(fftfem_plan_t p) { return (size_t)p->size * (size_t)p->nrhs * sizeof(double); }
 int64_t tune_class(int64_t K) { return tune_class_of(K); }
 
 }  // namespace fftfem
@@ -393,6 +396,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   }
   a.partials = want_partials ? p->partials : nullptr;
   a.flag = flag;
+  a.bad = out_kind == 1 && upd == nullptr ? p->bad : nullptr;
   size_t lds = (size_t)a.G * line_lds(n, t.K, sizeof(T), a.G > 1);
   if (lds > (size_t)p->lds_max) return FFTFEM_ENOTIMPL;
   int64_t nblocks = (a.nlines + a.G - 1) / a.G;
@@ -485,6 +489,50 @@ int apply_pass(fftfem_plan_t p, int axis, DDp in1, DDp in2, const double* f, voi
 //   3D: pass axis 2: t = c u, s = a u;
 //       pass axis 1: t2 = c t, s2 = c1 a t + react c t + c2 c s;
 //       pass axis 0: c0 a t2 + c s2
+// The fused 2D operator pass (resid2_kernel) applies to 2D plans whose two
+// axes have the same element order (in batches too: the grouped launch
+// runs the same body per job).  FFTFEM_RESID2=0 selects the two-pass form
+// everywhere (tests compare the two).
+static bool fused2d(fftfem_plan_t p) {
+  if (p->N != 2 || p->nd[0] != p->nd[1]) return false;
+  const char* e = std::getenv("FFTFEM_RESID2");
+  return !(e && e[0] == '0');
+}
+
+// Elements per one-wave workgroup along axis 0 of the fused pass: 16 (each
+// chunk also walks one element past its end), fewer when the grid would
+// not give every CU a few dozen waves.
+static int fused2d_chunk(fftfem_plan_t p) {
+  const int64_t ncb = (p->M[1] + 63) / 64;
+  int E = 16;
+  while (E > 1 && ncb * ((p->K[0] + E - 1) / E) < 8192) E /= 2;
+  return E;
+}
+
+static int resid2(fftfem_plan_t p, const double* u, const double* f, double* out, bool dd, const int* flag,
+                  hipStream_t s) {
+  Resid2Args a{};
+  a.u = u;
+  a.f = f;
+  a.out = out;
+  a.M0 = p->M[0];
+  a.M1 = p->M[1];
+  a.K0 = (int)p->K[0];
+  a.E = fused2d_chunk(p);
+  a.c0 = p->coef[0];
+  a.c1 = p->coef[1];
+  a.react = p->desc.react;
+  a.Ael = p->Ael[0];
+  a.Cel = p->Cel[0];
+  a.flag = flag;
+  if (p->rec) {
+    record(p, REC_RESID2, {p->nd[0], dd ? 1 : 0, 0, 0, 0}, a, (int)resid2_blocks(a), 0);
+    return FFTFEM_OK;
+  }
+  Timed tm(p, s, dd ? "resid2dd" : "resid2f64");
+  return from_hip(launch_resid2(p->nd[0], dd, a, s));
+}
+
 int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_kind,
                    const int* flag, hipStream_t s, int ph = 0) {
   const double* c = p->coef;
@@ -493,6 +541,7 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   const DDp none{nullptr, nullptr};
   int rc;
   p->phase = ph;
+  if (out_kind == 1 && fused2d(p)) return resid2(p, u, f, (double*)out, true, flag, s);
   if (p->N == 1) {
     double c1[4] = {c[0], react, 0, 0};
     return apply_pass(p, 0, {u, nullptr}, none, f, out, nullptr, out_kind, nullptr, nullptr, c1, nullptr,
@@ -557,6 +606,7 @@ int operator_apply_incr(fftfem_plan_t p, double* r, const int* flag, hipStream_t
   const double cC[4] = {0, 1, 0, 0}, cA[4] = {1, 0, 0, 0};
   int rc;
   p->phase = ph;
+  if (fused2d(p)) return resid2(p, T[1], nullptr, r, false, flag, s);
   rc = apply_pass(p, p->N - 1, {T[1], nullptr}, none, nullptr, T[0], nullptr, 1, T[2], nullptr, cC, cA, flag, s,
                   false);
   if (rc) return rc;
@@ -1015,15 +1065,20 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
       rc = from_hip(launch_reset(flag, st, kStatsLen, s));
     }
     if (rc) break;
+    // the chains' output passes report NaN / Inf in u through the flag
+    p->bad = flag;
     if (p->algb) {
       rc = band_chain(p, fr, ur, s);
+      p->bad = nullptr;
       continue;
     }
     if (p->desc.precision == FFTFEM_FP64) {
       rc = transform_chain<double>(p, fr, 1, ur, p->W64b, ur, nullptr, nullptr, s, false, false, base + 1);
+      p->bad = nullptr;
       continue;
     }
     rc = transform_chain<float>(p, fr, 1, p->W32, p->W32b, ur, nullptr, nullptr, s, false, false, base + 1);
+    p->bad = nullptr;
     if (rc || p->desc.precision == FFTFEM_FP32) continue;
     for (int it = 1; it <= p->desc.max_iter && !rc; ++it) {
       const int pit = base + 1 + SC + (it - 1) * per_it;
@@ -1091,17 +1146,44 @@ int fftfem_get_stats(fftfem_plan_t p, fftfem_stats* out) {
   std::vector<double> h((size_t)p->nrhs * kStatsLen);
   rc = from_hip(hipMemcpy(h.data(), p->stats, h.size() * sizeof(double), hipMemcpyDeviceToHost));
   if (rc) return rc;
+  std::vector<int> fl((size_t)p->nrhs);
+  rc = from_hip(hipMemcpy(fl.data(), p->flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost));
+  if (rc) return rc;
   std::memset(out, 0, sizeof(*out));
-  out->converged = 1;
+  // stop reasons ranked from best to worst; the worst right-hand side counts
+  auto rank = [](int stop) {
+    switch (stop) {
+      case FFTFEM_STOP_NONE: return 0;
+      case FFTFEM_STOP_TOL: return 1;
+      case FFTFEM_STOP_MAX_ITER: return 2;
+      case FFTFEM_STOP_STALLED: return 3;
+      default: return 4;
+    }
+  };
+  const bool refine = p->desc.precision == FFTFEM_FP32_REFINE && !p->algb;
   for (int r = 0; r < p->nrhs; ++r) {
     const double* st = &h[(size_t)r * kStatsLen];
     out->iterations = std::max(out->iterations, (int)st[0]);
-    if (p->desc.precision == FFTFEM_FP32_REFINE && st[1] == 0) out->converged = 0;
-    for (int i = 0; i <= FFTFEM_MAX_ITERS; ++i)
-      out->rel_correction[i] = std::max(out->rel_correction[i], st[2 + i]);
+    int stop = FFTFEM_STOP_NONE;
+    if (fl[r] & 2)
+      stop = FFTFEM_STOP_NONFINITE;  // an output pass wrote NaN or Inf
+    else if (refine)
+      stop = st[1] == 1    ? FFTFEM_STOP_TOL
+             : st[1] == -1 ? FFTFEM_STOP_NONFINITE
+             : st[1] == -2 ? FFTFEM_STOP_STALLED
+                           : FFTFEM_STOP_MAX_ITER;
+    if (rank(stop) > rank(out->stop)) out->stop = stop;
+    for (int i = 0; i <= FFTFEM_MAX_ITERS; ++i) {
+      const double v = st[2 + i];
+      double& o = out->rel_correction[i];
+      if (std::isnan(v) || std::isnan(o))
+        o = std::numeric_limits<double>::quiet_NaN();
+      else
+        o = std::max(o, v);
+    }
   }
-  if (p->desc.precision != FFTFEM_FP32_REFINE) out->converged = 1;
-  return FFTFEM_OK;
+  out->converged = out->stop == FFTFEM_STOP_NONE || out->stop == FFTFEM_STOP_TOL;
+  return out->converged ? FFTFEM_OK : FFTFEM_ENOCONV;
 }
 
 size_t fftfem_workspace_bytes(const fftfem_plan_t p) { return p ? p->bytes : 0; }
@@ -1187,21 +1269,36 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
   return rc;
 }
 
+// Extended size (prod_d (M_d + 2)) of one right-hand side of the Dirichlet data.
+static int64_t dirichlet_extended_size(fftfem_plan_t p) {
+  int64_t esize = 1;
+  for (int d = 0; d < p->N; ++d) esize *= p->M[d] + 2;
+  return esize;
+}
+
+static int dirichlet_load_impl(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
+                               hipStream_t s);
+
 int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
                           hipStream_t s) {
   if (!p || !b || !f || !out || !work || p->rec) return FFTFEM_EINVAL;
-  const int N = p->N;
-  int64_t E[3] = {1, 1, 1}, esize = 1;
-  for (int d = 0; d < N; ++d) {
-    E[d] = p->M[d] + 2;
-    esize *= E[d];
-  }
+  const int64_t esize = dirichlet_extended_size(p);
   const size_t ib = (size_t)p->size * p->nrhs * sizeof(double), eb = (size_t)esize * p->nrhs * sizeof(double);
   const size_t wb = 2 * (size_t)esize * sizeof(double);
-  if (f != out && overlap(f, out, ib)) return FFTFEM_EINVAL;
-  if (overlap2(b, eb, out, ib) || overlap2(work, wb, out, ib) || overlap2(work, wb, b, eb) ||
-      overlap2(work, wb, f, ib))
+  if (overlap2(work, wb, out, ib) || overlap2(work, wb, b, eb) || overlap2(work, wb, f, ib))
     return FFTFEM_EINVAL;
+  return dirichlet_load_impl(p, b, f, out, work, s);
+}
+
+static int dirichlet_load_impl(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
+                               hipStream_t s) {
+  const int N = p->N;
+  int64_t E[3] = {1, 1, 1};
+  for (int d = 0; d < N; ++d) E[d] = p->M[d] + 2;
+  const int64_t esize = dirichlet_extended_size(p);
+  const size_t ib = (size_t)p->size * p->nrhs * sizeof(double), eb = (size_t)esize * p->nrhs * sizeof(double);
+  if (f != out && overlap(f, out, ib)) return FFTFEM_EINVAL;
+  if (overlap2(b, eb, out, ib)) return FFTFEM_EINVAL;
   p->last = s;
   int rc = FFTFEM_OK;
   for (int r = 0; r < p->nrhs && !rc; ++r) {

@@ -206,6 +206,9 @@ int build_graph(fftfem_batch_s* b, const double* const* f, double* const* u, hip
         e = launch_apply_grouped(g.key[0], g.key[1] != 0, g.key[2] != 0, GroupedOps{jobs, jobof, start, g.nblocks, g.lds},
                                  b->cap);
         break;
+      case REC_RESID2:
+        e = launch_resid2_grouped(g.key[0], g.key[1] != 0, GroupedOps{jobs, jobof, start, g.nblocks, 0}, b->cap);
+        break;
       case REC_TR32:
         e = launch_transpose_grouped<float>(GroupedOps{jobs, jobof, start, g.nblocks, 0}, b->cap);
         break;
@@ -280,8 +283,13 @@ int fftfem_plan_batch(fftfem_batch_t* out, int count, const fftfem_desc* descs, 
 int fftfem_solve_batch(fftfem_batch_t b, const double* const* f, double* const* u, hipStream_t s) {
   if (!b || !f || !u) return FFTFEM_EINVAL;
   const int count = (int)b->plans.size();
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (!f[i] || !u[i]) return FFTFEM_EINVAL;
+    // as in fftfem_solve: u must not overlap f (the refinement rereads f)
+    const size_t bytes = plan_array_bytes(b->plans[i]);
+    const char *x = (const char*)f[i], *y = (const char*)u[i];
+    if (x < y + bytes && y < x + bytes) return FFTFEM_EINVAL;
+  }
   bool same = b->exec && (int)b->f.size() == count;
   for (int i = 0; same && i < count; ++i) same = b->f[i] == f[i] && b->u[i] == u[i];
   int rc;

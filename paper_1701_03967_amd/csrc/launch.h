@@ -44,6 +44,8 @@ struct LineArgs {
   T react;
   double* partials;       // per-block (sum c^2, sum u^2) in update mode
   const int* flag;        // nonzero: skip (refinement converged)
+  int* bad;               // non-null (output pass without update): or 2 into it when
+                          // a written value is NaN or Inf
 };
 
 // One operator pass along an axis (see apply_kernel).  Inputs and the
@@ -64,6 +66,21 @@ struct ApplyArgs {
   int dd;                 // 1: double-double arithmetic; 0: plain float64 (no lo planes)
 };
 
+
+// The fused 2D operator pass (both axes of order n): out = f - A u (double-
+// double, u and f float64; f null: out = A u) or out -= A u (plain float64,
+// in place).  Tiles of 64 columns x E elements along axis 0.
+struct Resid2Args {
+  const double* u;
+  const double* f;
+  double* out;
+  int64_t M0, M1;
+  int K0, E;
+  double c0, c1, react;   // diff_d 4 / h_d^2 of axes 0 and 1, reaction
+  const double* Ael;      // element stiffness: (n+1)^2 hi values, then (n+1)^2 lo values
+  const double* Cel;      // element mass, the same layout
+  const int* flag;
+};
 
 // The banded solve along axis 0 (algorithm (b)): per line, the shifted 1D
 // system (coef A + sigma C) x = y with sigma = react + the other axes'
@@ -165,6 +182,9 @@ inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, i
                                  : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
 }
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_resid2(int n, bool dd, const Resid2Args& a, hipStream_t s);
+hipError_t launch_resid2_grouped(int n, bool dd, const GroupedOps& g, hipStream_t s);
+int64_t resid2_blocks(const Resid2Args& a);  // workgroups of one launch
 hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
 hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s);

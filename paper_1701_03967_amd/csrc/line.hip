@@ -525,6 +525,9 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
     }
   };
   double acc_c = 0, acc_u = 0;
+  // output pass: any NaN or Inf written (v - v is 0 exactly for finite v)
+  const bool chk = !UPD && a.bad != nullptr;
+  bool nonfinite = false;
   auto put = [&](int64_t idx, T v) {
     if constexpr (UPD) {
       double u = a.upd[idx] + (double)v;
@@ -534,6 +537,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       acc_u += u * u;
     } else {
       store_out<T>(a.out, a.out_kind, idx, v);
+      if (chk) nonfinite |= !(v - v == (T)0);
     }
   };
   auto bulk_store = [&]() {
@@ -979,6 +983,10 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
     }
     __syncthreads();
     bulk_store();
+  }
+  if (chk) {
+    // one vector atomic per wave that saw a non-finite value
+    if (__ballot(nonfinite) != 0 && (tid & 63) == 0) atomicOr(a.bad, 2);
   }
   if constexpr (UPD) {
     __shared__ double red[2][kNT];

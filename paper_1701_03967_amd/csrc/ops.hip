@@ -259,6 +259,207 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int bid, int nblk
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused 2D operator pass (both axes of order n in one kernel), for the
+// refinement residual and the operator apply:
+//   A u = c0 (A_0 x C_1) u + c1 (C_0 x A_1) u + react (C_0 x C_1) u
+//       = A_0 v + C_0 z,   v = c0 C_1 u,  z = c1 A_1 u + react C_1 u,
+// v and z taken along axis 1 (rows), then A_0 and C_0 along axis 0 (the
+// sum factorization of the two-pass apply, in one pass over the array).
+//
+// One wave owns 64 columns (lane l: column col0 + l) and a chunk of E
+// elements along axis 0, which it walks one element at a time.  For element
+// e (rows t = 0..n: global row n e + t - 1, t = 0 and t = n its end nodes)
+// the wave stages rows t = 1..n (with n columns of halo on each side) in
+// LDS, forms v_t and z_t in registers, and accumulates the element's local
+// products y_q += A_0[q][t] v_t + C_0[q][t] z_t for all q = 0..n at once
+// (n + 1 independent accumulators; row t = 0 is the previous element's
+// row n, kept in registers).  Then the bubbles q = 1..n-1 are complete; the
+// node between elements e-1 and e is the previous element's y_n plus this
+// element's y_0.  A chunk also walks the element after it (without writing
+// its bubbles) to complete its last node.  The next element's rows and this
+// element's f (or r) values are loaded into registers one element ahead.
+//
+// DD: double-double arithmetic throughout, out = f - A u (or A u when f is
+// null), u float64.  Otherwise plain float64: out -= A u in place (the
+// incremental residual r - A c).
+template <int NORD, bool DD>
+__device__ __forceinline__ void resid2_body(const Resid2Args& a, int bid, int nblk) {
+#pragma clang fp contract(off)
+  if (a.flag && *a.flag) return;
+  constexpr int n = NORD, XX = (n + 1) * (n + 1), W = 64 + 2 * n;
+  __shared__ double Xa[2 * XX], Xc[2 * XX];
+  __shared__ double stg[n * W];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < 2 * XX; i += 64) {
+    Xa[i] = a.Ael[i];
+    Xc[i] = a.Cel[i];
+  }
+  const int64_t M0 = a.M0, M1 = a.M1;
+  const int ncb = (int)((M1 + 63) / 64);
+  const int tile = xcd_remap(bid, nblk);
+  const int ch = tile / ncb, cb = tile - ch * ncb;
+  const int e0 = ch * a.E;
+  const int e1 = e0 + a.E < a.K0 ? e0 + a.E : a.K0;  // elements whose rows this chunk writes
+  const int elast = e1 < a.K0 ? e1 : e1 - 1;         // plus the next one, for the last node
+  const int64_t col0 = (int64_t)cb * 64, col = col0 + lane;
+  const bool colok = col < M1;
+  const double* src = DD ? a.f : a.out;  // subtracted from (null: out = A u)
+
+  // values of global row r at columns col0 - n + lane and col0 - n + 64 + lane
+  // (zero outside the array: the Dirichlet boundary)
+  auto load_row = [&](int64_t r, double& x0, double& x1) {
+    x0 = x1 = 0.0;
+    if (r < 0 || r >= M0) return;
+    const int64_t c0 = col0 - n + lane, c1 = c0 + 64;
+    const double* row = a.u + r * M1;
+    if (c0 >= 0 && c0 < M1) x0 = row[c0];
+    if (lane < W - 64 && c1 < M1) x1 = row[c1];
+  };
+  auto stage = [&](int sr, double x0, double x1) {
+    stg[sr * W + lane] = x0;
+    if (lane < W - 64) stg[sr * W + 64 + lane] = x1;
+  };
+  // The element matrices are read from LDS at each use through an offset
+  // the compiler cannot see (zero): otherwise it keeps all 4 (n + 1)^2 values
+  // (they do not change from element to element) in registers and spills.
+  auto opaque0 = []() {
+    int z = 0;
+    __asm__ volatile("" : "+v"(z));
+    return z;
+  };
+  // v and z of staged row sr at this lane's column
+  auto rowvz = [&](int sr, dd& v, dd& z) {
+    const double* vrow = stg + sr * W + n - col0;  // index = global column
+    const int o0 = opaque0();
+    const double* Xa_ = Xa + o0;
+    const double* Xc_ = Xc + o0;
+    if constexpr (DD) {
+      const dd C = row_apply<NORD, false>(vrow, nullptr, (int)col, Xc_);
+      const dd A = row_apply<NORD, false>(vrow, nullptr, (int)col, Xa_);
+      v = dd{0, 0};
+      z = dd{0, 0};
+      dd_axpy(v, a.c0, C);
+      dd_axpy(z, a.c1, A);
+      dd_axpy(z, a.react, C);
+      v = dd_norm(v);
+      z = dd_norm(z);
+    } else {
+      const double C = row_apply_f64<NORD>(vrow, (int)col, Xc_);
+      const double A = row_apply_f64<NORD>(vrow, (int)col, Xa_);
+      v = dd{a.c0 * C, 0};
+      z = dd{__builtin_fma(a.c1, A, a.react * C), 0};
+    }
+  };
+  // acc[q] += A_0[q][t] v + C_0[q][t] z for q = 0..n
+  auto accumulate = [&](dd* acc, int t, const dd& v, const dd& z) {
+    const int o0 = opaque0();
+#pragma unroll
+    for (int q = 0; q <= n; ++q) {
+      const int o = q * (n + 1) + t + o0;
+      if constexpr (DD) {
+        dd_fma<true>(acc[q], Xa[o], Xa[XX + o], v.h, v.l);
+        dd_fma<true>(acc[q], Xc[o], Xc[XX + o], z.h, z.l);
+      } else {
+        acc[q].h = __builtin_fma(Xa[o], v.h, acc[q].h);
+        acc[q].h = __builtin_fma(Xc[o], z.h, acc[q].h);
+      }
+    }
+  };
+  auto put = [&](int64_t g, double fv, const dd& y) {
+    if (!colok || g < 0 || g >= M0) return;
+    const int64_t idx = g * M1 + col;
+    if constexpr (DD) {
+      dd r = y;
+      if (src) {
+        double hh, er;
+        two_sum(fv, -y.h, hh, er);
+        r = {hh, er - y.l};
+      }
+      r = dd_norm(r);
+      a.out[idx] = r.h;
+    } else {
+      a.out[idx] = fv - y.h;
+    }
+  };
+  auto load_f = [&](int64_t g) -> double { return (src && colok && g >= 0 && g < M0) ? src[g * M1 + col] : 0.0; };
+
+  // prologue: row t = 0 of element e0 (its left node)
+  dd v0, z0;
+  {
+    double x0, x1;
+    load_row((int64_t)n * e0 - 1, x0, x1);
+    stage(0, x0, x1);
+    __syncthreads();
+    rowvz(0, v0, z0);
+    __syncthreads();
+  }
+  dd carry{0, 0};  // the previous element's contribution to its right node
+  for (int e = e0; e <= elast; ++e) {
+    // rows t = 1..n of element e into the staging area
+#pragma unroll
+    for (int t = 1; t <= n; ++t) {
+      double x0, x1;
+      load_row((int64_t)n * e + t - 1, x0, x1);
+      stage(t - 1, x0, x1);
+    }
+    __syncthreads();
+    dd acc[n + 1];
+#pragma unroll
+    for (int q = 0; q <= n; ++q) acc[q] = dd{0, 0};
+    accumulate(acc, 0, v0, z0);
+    // one row at a time (not unrolled: unrolled, the scheduler starts the
+    // LDS reads of all rows at once and spills)
+#pragma unroll 1
+    for (int t = 1; t <= n; ++t) {
+      dd v, z;
+      rowvz(t - 1, v, z);
+      accumulate(acc, t, v, z);
+      if (t == n) {
+        v0 = v;
+        z0 = z;
+      }
+    }
+    // subtrahends of this element's outputs: row n e - 1 (its left node,
+    // t = 0) and its bubbles (t = 1..n-1); loaded after the products, which
+    // leaves the registers to the accumulators (other waves cover the wait)
+    double fc[n];
+#pragma unroll
+    for (int t = 0; t < n; ++t) fc[t] = load_f((int64_t)n * e + t - 1);
+    __syncthreads();  // the staging area is free for the next element
+    // the node between elements e - 1 and e (a row of this chunk when e > e0)
+    if (e > e0) {
+      dd y = carry;
+      dd_axpy(y, 1.0, acc[0]);
+      put((int64_t)n * e - 1, fc[0], y);
+    }
+    if (e < e1) {
+#pragma unroll
+      for (int t = 1; t < n; ++t) put((int64_t)n * e + t - 1, fc[t], acc[t]);
+    }
+    carry = acc[n];
+  }
+}
+
+// Waves per SIMD: 4 for the float64 pass (at most 128 VGPRs), 3 for the
+// double-double one (at most 168; its n + 1 double-double accumulators,
+// carried row and node partial spill at 128 for n >= 8).  The one-wave
+// workgroups on a CU hide each other's row loads.
+template <int NORD, bool DD>
+__global__ __launch_bounds__(64, DD ? 3 : 4) void resid2_kernel(Resid2Args a) {
+  resid2_body<NORD, DD>(a, blockIdx.x, gridDim.x);
+}
+
+// Grouped launch: block b runs tile b - start[j] of job j = job_of[b].
+template <int NORD, bool DD>
+__global__ __launch_bounds__(64, DD ? 3 : 4) void resid2_kernel_grouped(const Resid2Args* __restrict__ jobs,
+                                                                   const int* __restrict__ job_of,
+                                                                   const int* __restrict__ start) {
+  const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
+  const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
+  resid2_body<NORD, DD>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
+}
+
 template <int NORD, bool LO, bool DD>
 __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
   apply_body<NORD, LO, DD>(a, blockIdx.x, gridDim.x);
@@ -276,7 +477,11 @@ __global__ __launch_bounds__(kThreads) void apply_kernel_grouped(const ApplyArgs
 
 // ---------------------------------------------------------------------------
 // Refinement bookkeeping.  stats layout (doubles): [0] iterations applied,
-// [1] converged flag, [2 + i] relative correction of iteration i.
+// [1] state: 0 running (or no refinement), 1 tolerance reached, -1 a
+// non-finite correction or iterate, -2 a correction no smaller than the one
+// before; [2 + i] relative correction of iteration i.  The flag stops every
+// later launch of the solve when it is nonzero: 1 is set here, bit 2 by an
+// output pass that wrote a NaN or Inf.
 __device__ __forceinline__ void reset_body(int* flag, double* stats, int nstats) {
   int i = threadIdx.x;
   if (i == 0) *flag = 0;
@@ -311,11 +516,29 @@ __device__ __forceinline__ void reduce_body(const double* partials, int nparts, 
     __syncthreads();
   }
   if (tid == 0) {
-    double rel = r1[0] > 0 ? sqrt(r0[0] / r1[0]) : 0.0;
+    // ||c||^2 and ||u||^2 of this step; a NaN or Inf in either (non-finite
+    // data, a float32 overflow) makes rel NaN, a correction of a zero iterate
+    // makes it +Inf, and neither counts as converged
+    const double c2 = r0[0], u2 = r1[0];
+    double rel;
+    if (!(c2 - c2 == 0.0) || !(u2 - u2 == 0.0))
+      rel = __builtin_nan("");
+    else if (u2 > 0)
+      rel = sqrt(c2 / u2);
+    else
+      rel = c2 > 0 ? __builtin_inf() : 0.0;
     stats[2 + iter] = rel;
     stats[0] = iter;
-    if (iter > 0 && rel <= tol) {
+    if (!(rel - rel == 0.0)) {
+      stats[1] = -1;
+      *flag = 1;
+    } else if (iter > 0 && rel <= tol) {
       stats[1] = 1;
+      *flag = 1;
+    } else if (iter >= 2 && !(rel < stats[1 + iter])) {
+      // stationary refinement contracts every step; a correction that does
+      // not shrink means round-off level or divergence: stop
+      stats[1] = -2;
       *flag = 1;
     }
   }
@@ -475,6 +698,64 @@ hipError_t launch_reduce(const double* partials, int nparts, int iter, double to
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, iter, tol,
                      flag, stats);
   return hipGetLastError();
+}
+
+
+hipError_t launch_resid2_grouped(int n, bool dd, const GroupedOps& g, hipStream_t s) {
+  const Resid2Args* jobs = (const Resid2Args*)g.jobs;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                                      \
+  case N:                                                                                                   \
+    if (dd)                                                                                                 \
+      hipLaunchKernelGGL((resid2_kernel_grouped<N, true>), dim3(g.nblocks), dim3(64), 0, s, jobs,      \
+                         g.job_of, g.start);                                                                \
+    else                                                                                                    \
+      hipLaunchKernelGGL((resid2_kernel_grouped<N, false>), dim3(g.nblocks), dim3(64), 0, s, jobs,     \
+                         g.job_of, g.start);                                                                \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int64_t resid2_blocks(const Resid2Args& a) { return ((a.M1 + 63) / 64) * ((a.K0 + a.E - 1) / a.E); }
+
+hipError_t launch_resid2(int n, bool dd, const Resid2Args& a, hipStream_t s) {
+  if (a.K0 < 1 || a.E < 1 || a.M1 < 1) return hipErrorInvalidValue;
+  const int64_t ncb = (a.M1 + 63) / 64, nch = (a.K0 + a.E - 1) / a.E;
+  const int64_t nb = ncb * nch;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                              \
+  case N:                                                                                           \
+    if (dd)                                                                                         \
+      hipLaunchKernelGGL((resid2_kernel<N, true>), dim3((unsigned)nb), dim3(64), 0, s, a);     \
+    else                                                                                            \
+      hipLaunchKernelGGL((resid2_kernel<N, false>), dim3((unsigned)nb), dim3(64), 0, s, a);    \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace fftfem

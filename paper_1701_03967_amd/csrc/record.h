@@ -15,13 +15,13 @@
 namespace fftfem {
 
 // One launch a plan would issue, with its fully resolved arguments.
-enum RecKind { REC_LINE32 = 0, REC_LINE64, REC_APPLY, REC_TR32, REC_TR64, REC_RESET, REC_REDUCE };
+enum RecKind { REC_LINE32 = 0, REC_LINE64, REC_APPLY, REC_TR32, REC_TR64, REC_RESET, REC_REDUCE, REC_RESID2 };
 
 struct Rec {
   int phase;                        // position in the plan's schedule (see fftfem_solve)
   int kind;                         // RecKind
-  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo, dd
-  std::vector<unsigned char> args;  // LineArgs<T>, ApplyArgs, TransposeJob, ResetJob or ReduceJob
+  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo, dd;  resid2: n, dd
+  std::vector<unsigned char> args;  // LineArgs<T>, ApplyArgs, Resid2Args, TransposeJob, ResetJob or ReduceJob
   int nblocks;
   size_t lds;
 };
@@ -55,6 +55,7 @@ int plan_create(fftfem_plan_t* out, const fftfem_desc* d, TableCache* cache);
 void plan_set_recorder(fftfem_plan_t p, Recorder* r);
 // The stream the plan's stats are synchronized with.
 void plan_set_stream(fftfem_plan_t p, hipStream_t s);
+size_t plan_array_bytes(fftfem_plan_t p);  // bytes of one f (all right-hand sides)
 
 // Line-pass parameters chosen by measurement, for (precision, n, mode, lines
 // strided, element count).  Consulted by every line pass; empty by default.

@@ -64,7 +64,12 @@ class Stats(ctypes.Structure):
         ("iterations", ctypes.c_int),
         ("converged", ctypes.c_int),
         ("rel_correction", ctypes.c_double * (MAX_ITERS + 1)),
+        ("stop", ctypes.c_int),
     ]
+
+
+ENOCONV = -6
+STOP_REASONS = {0: "none", 1: "tol", 2: "max_iter", 3: "nonfinite", 4: "stalled"}
 
 
 _lib = None
@@ -209,7 +214,18 @@ def make_desc(K: Sequence[int], n, diff: Sequence[float], react: float = 0.0,
 
 def _stats_dict(s):
     return {"iterations": s.iterations, "converged": bool(s.converged),
-            "rel_correction": list(s.rel_correction)[:max(1, s.iterations + 1)]}
+            "rel_correction": list(s.rel_correction)[:max(1, s.iterations + 1)],
+            "stop": STOP_REASONS.get(s.stop, s.stop)}
+
+
+def _get_stats(fn, *args):
+    """Statistics; FFTFEM_ENOCONV (an unconverged or non-finite solve) is
+    reported in the result, not raised."""
+    s = Stats()
+    rc = fn(*args, ctypes.byref(s))
+    if rc != ENOCONV:
+        _check(rc, fn.__name__)
+    return _stats_dict(s)
 
 
 class Batch:
@@ -260,9 +276,7 @@ class Batch:
         return us
 
     def stats(self, i: int):
-        s = Stats()
-        _check(lib().fftfem_batch_get_stats(self._h, int(i), ctypes.byref(s)), "fftfem_batch_get_stats")
-        return _stats_dict(s)
+        return _get_stats(lib().fftfem_batch_get_stats, self._h, int(i))
 
     def workspace_bytes(self) -> int:
         return int(lib().fftfem_batch_workspace_bytes(self._h))
@@ -400,10 +414,10 @@ class Plan:
         _check(lib().fftfem_tune(self._h, _stream_ptr(stream)), "fftfem_tune")
 
     def stats(self):
-        s = Stats()
-        _check(lib().fftfem_get_stats(self._h, ctypes.byref(s)), "fftfem_get_stats")
-        return {"iterations": s.iterations, "converged": bool(s.converged),
-                "rel_correction": list(s.rel_correction)[:max(1, s.iterations + 1)]}
+        """Refinement statistics of the last solve: iterations, converged,
+        rel_correction (per iteration), stop (why the refinement stopped:
+        none, tol, max_iter, nonfinite, stalled)."""
+        return _get_stats(lib().fftfem_get_stats, self._h)
 
     def tables(self, axis: int):
         M = self.shape[axis]

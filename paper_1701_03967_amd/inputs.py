@@ -127,3 +127,21 @@ def batch_rhs(draw: BatchDraw, i: int) -> np.ndarray:
     p = draw.problems[i]
     g = generator(draw.seeds[i])
     return g.standard_normal((p.nrhs,) + p.shape, dtype=np.float64)
+
+
+# Random sign vectors for whole-array checks at sizes where a solution can be
+# stored only as samples: <w_i, u> over every entry of u, with w_i of i.i.d.
+# +-1 entries, moves by about ||delta|| under any perturbation delta of u,
+# wherever in the array it sits.
+NPROBE = 4
+
+
+def probe_vector(shape, i: int) -> np.ndarray:
+    """The i-th seeded +-1 vector of the given shape (float64)."""
+    g = generator(90000 + int(i))
+    size = int(np.prod(shape))
+    s = g.integers(0, 2, size=size, dtype=np.int8)
+    out = s.astype(np.float64)
+    out *= 2.0
+    out -= 1.0
+    return out.reshape(tuple(shape))

@@ -11,7 +11,10 @@ operator), then a text fixture ``fullsize_<name>.txt`` with
   * 4096 seeded random flat indices, the first and last dof of every axis
     line through the array's corners, and every local position (node and
     bubbles) of one element in the middle of the array, each with the
-    oracle's float64 value (17 significant digits).
+    oracle's float64 value (17 significant digits);
+  * the inner products ``proj<i>`` of the whole solution with the seeded
+    random sign vectors ``inputs.probe_vector(shape, i)``, i < NPROBE, which
+    any error of the solution moves by about its l2 norm wherever it sits.
 
 Only the oracle and the seeded input generator are used.  The C3 solve takes
 some minutes and ~15 GB of host memory; C4 ~30 GB.
@@ -85,6 +88,10 @@ def main(names):
             fh.write(f"l2 {float(np.linalg.norm(flat)):.17e}\n")
             fh.write(f"max {float(np.abs(flat).max()):.17e}\n")
             fh.write(f"sum {float(flat.sum()):.17e}\n")
+            for i in range(inputs.NPROBE):
+                w = inputs.probe_vector(prob.shape, i).reshape(-1)
+                fh.write(f"proj{i} {float(np.dot(w, flat)):.17e}\n")
+                del w
             for i in idx:
                 fh.write(f"{int(i)} {float(flat[i]):.17e}\n")
         print(f"[fullsize] {name}: {len(idx)} samples, eig {t1 - t0:.0f}s, solve {t2 - t1:.0f}s, "

@@ -44,7 +44,9 @@ def rel(a, b):
 CASES = [((64,), 5, 0.0), ((7,), 9, 2.0), ((40,), 1, 0.0),
          ((32, 24), (2, 5), 0.75), ((256, 16), 9, 0.0), ((17, 33), (7, 3), 3.0), ((20, 12), (4, 6), 0.0),
          ((8, 3), 1, 1.0), ((2, 9), (9, 2), 0.5), ((64, 64), 9, -10.0),
-         ((8, 12, 10), (3, 2, 4), 0.75), ((16, 16, 16), 9, 0.0), ((5, 6, 7), (2, 1, 3), 10.0)]
+         ((8, 12, 10), (3, 2, 4), 0.75), ((16, 16, 16), 9, 0.0), ((5, 6, 7), (2, 1, 3), 10.0),
+         # 64 < K_1 <= 128: the tiled form's 8-lines-per-workgroup kernel
+         ((96, 20), (9, 3), 0.0), ((128,), 5, 1.0), ((100, 6, 5), (4, 2, 3), 0.5)]
 
 
 @pytest.mark.parametrize("form", ["0", "1", "2"])

@@ -5,8 +5,16 @@ The oracle's solutions of the same seeded right-hand sides were computed
 once on the CPU (tests/golden/make_fullsize.py) and stored as ~4100 sampled
 values per workload: seeded random positions plus the dofs next to every
 corner and all local positions of one element per axis through the middle.
-Compared here: the samples (relative l2 over the sample set) and the global
-l2 norm and sum of the whole solution.
+Compared here: the samples (relative l2 over the sample set), the global
+l2 norm and sum of the whole solution, and its inner products with seeded
+random sign vectors (inputs.probe_vector), which any error of the solution
+moves by about its l2 norm wherever in the array it sits: a bound on those
+differences relative to ||u|| bounds an error confined to a few lines as
+well as a spread one.
+
+Every mode the benchmark times is covered: algorithm (a) in float64,
+float32 and float32 + refinement, and algorithm (b) in float64 in each of its
+banded-solve forms (the plan's choice, and the others forced).
 """
 import numpy as np
 import pytest
@@ -27,7 +35,7 @@ def load_fixture(golden, name):
     idx, val = [], []
     for r in rows:
         a, b = r.split()
-        if a in ("l2", "max", "sum"):
+        if a in ("l2", "max", "sum") or a.startswith("proj"):
             glob[a] = float(b)
         else:
             idx.append(int(a))
@@ -52,34 +60,60 @@ def rhs_cache():
     torch.cuda.empty_cache()
 
 
-MODES = [("fp64", 1e-10, 0), ("fp32_refine", 1e-10, 3), ("fp32", 1e-5, 0)]
-
-
-@pytest.mark.parametrize("name", ["c3_2d_n9_k1024", "c4_3d_n9_k64"])
-@pytest.mark.parametrize("prec,tol,iters", MODES)
-def test_fullsize(fm, rhs_cache, golden, name, prec, tol, iters):
-    say("full size", name, prec)
-    glob, idx, ref = load_fixture(golden, name)
-    prob = inputs.WORKLOADS[name].problem
-    if name not in rhs_cache:
-        rhs_cache.clear()
+def workload_arrays(cache, name):
+    """The workload's right-hand side and the probe vectors on the device
+    (one workload held at a time)."""
+    if name not in cache:
+        cache.clear()
         torch.cuda.empty_cache()
-        rhs_cache[name] = torch.from_numpy(inputs.workload_rhs(name)).cuda()
-    f = rhs_cache[name]
-    p = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=prec, max_iter=iters, tol=1e-12)
-    u = torch.empty_like(f)
-    p.solve(f, u)
-    torch.cuda.synchronize()
+        shape = inputs.WORKLOADS[name].problem.shape
+        cache[name] = (torch.from_numpy(inputs.workload_rhs(name)).cuda(),
+                       [torch.from_numpy(inputs.probe_vector(shape, i)).cuda().view(-1)
+                        for i in range(inputs.NPROBE)])
+    return cache[name]
+
+
+# (precision, algorithm, banded-solve form or None for the plan's choice,
+# tolerance, refinement steps)
+MODES = [("fp64", "a", None, 1e-10, 0), ("fp32_refine", "a", None, 1e-10, 3), ("fp32", "a", None, 1e-5, 0),
+         ("fp64", "b", None, 1e-10, 0), ("fp64", "b", "0", 1e-10, 0), ("fp64", "b", "1", 1e-10, 0)]
+
+
+def compare(golden, name, u, probes):
+    """Relative errors of a full-size solution against the oracle's samples,
+    norms and projections."""
+    glob, idx, ref = load_fixture(golden, name)
+    size = u.numel()
     flat = u.view(-1)
     got = flat[torch.from_numpy(idx).cuda()].cpu().numpy()
     l2 = float(torch.linalg.norm(flat))
-    tot = float(flat.sum())
-    e_s = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    e_l2 = abs(l2 - glob["l2"]) / glob["l2"]
-    e_sum = abs(tot - glob["sum"]) / (glob["l2"] * np.sqrt(prob.size))
-    say("  samples", e_s, "l2", e_l2, "sum", e_sum, p.stats() if iters else "")
+    out = {"finite": bool(np.all(np.isfinite(got))),
+           "samples": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+           "l2": abs(l2 - glob["l2"]) / glob["l2"],
+           "sum": abs(float(flat.sum()) - glob["sum"]) / (glob["l2"] * np.sqrt(size))}
+    if "proj0" in glob:
+        out["proj"] = max(abs(float(torch.dot(w, flat)) - glob[f"proj{i}"]) / glob["l2"]
+                          for i, w in enumerate(probes))
+    return out
+
+
+@pytest.mark.parametrize("name", ["c3_2d_n9_k1024", "c4_3d_n9_k64"])
+@pytest.mark.parametrize("prec,alg,form,tol,iters", MODES)
+def test_fullsize(fm, rhs_cache, golden, monkeypatch, name, prec, alg, form, tol, iters):
+    say("full size", name, prec, "algorithm", alg, "form", form)
+    if form is not None:
+        monkeypatch.setenv("FFTFEM_BAND_FORM", form)
+    prob = inputs.WORKLOADS[name].problem
+    f, probes = workload_arrays(rhs_cache, name)
+    p = fm.Plan(prob.K, prob.n, prob.diff, prob.react, precision=prec, max_iter=iters, tol=1e-12,
+                algorithm=alg)
+    u = torch.empty_like(f)
+    p.solve(f, u)
+    torch.cuda.synchronize()
+    e = compare(golden, name, u, probes)
+    say("  errors", e, p.stats() if iters else "")
     del u, p
-    assert np.all(np.isfinite(got))
-    assert e_s < tol
-    assert e_l2 < tol
-    assert e_sum < tol
+    assert e["finite"]
+    assert "proj" in e
+    for k in ("samples", "l2", "sum", "proj"):
+        assert e[k] < tol, k
