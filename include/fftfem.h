@@ -283,6 +283,21 @@ int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_
 int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
                           hipStream_t s);
 
+/*
+ * fftfem_dirichlet_load without the caller's work array, for callers that
+ * cannot allocate device memory (code under graph capture, serving loops,
+ * harnesses that forbid allocation): the 2 E_1 .. E_N doubles of work live
+ * in a static device array of the library of 2^21 doubles (16 MiB) per
+ * device, held until the process ends, so E_1 .. E_N <= 2^20
+ * (FFTFEM_EINVAL above).  The same kernels and results as
+ * fftfem_dirichlet_load.  It allocates nothing and calls no allocating
+ * routine; the first call on a device looks up the array's device address
+ * (hipGetSymbolAddress) and keeps it.  All calls on one device share the
+ * array: calls that overlap in time on one device (other streams, other
+ * threads) race.  Arguments as in fftfem_dirichlet_load; asynchronous on s.
+ */
+int fftfem_dirichlet_load_noalloc(fftfem_plan_t p, const double* b, const double* f, double* out,
+                                  hipStream_t s);
 
 /*
  * Implicit Euler time stepping of the semi-discrete heat equation of the

@@ -1290,6 +1290,16 @@ int fftfem_dirichlet_load(fftfem_plan_t p, const double* b, const double* f, dou
   return dirichlet_load_impl(p, b, f, out, work, s);
 }
 
+int fftfem_dirichlet_load_noalloc(fftfem_plan_t p, const double* b, const double* f, double* out,
+                                  hipStream_t s) {
+  if (!p || !b || !f || !out || p->rec) return FFTFEM_EINVAL;
+  if (2 * (size_t)dirichlet_extended_size(p) > kLiftScratchDoubles) return FFTFEM_EINVAL;
+  double* work = nullptr;
+  int rc = from_hip(lift_scratch(&work));
+  if (rc) return rc;
+  return dirichlet_load_impl(p, b, f, out, work, s);
+}
+
 static int dirichlet_load_impl(fftfem_plan_t p, const double* b, const double* f, double* out, double* work,
                                hipStream_t s) {
   const int N = p->N;

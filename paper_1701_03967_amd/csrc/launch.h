@@ -189,6 +189,10 @@ hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
 hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
+// The Dirichlet lifting's static work area (doubles per device) and its
+// device address on the current device.
+constexpr size_t kLiftScratchDoubles = size_t(1) << 21;
+hipError_t lift_scratch(double** ptr);
 int band_tile_lines(int K);  // lines per workgroup of launch_band_tile for K elements, 0: K too large
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);

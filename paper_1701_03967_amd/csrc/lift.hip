@@ -9,10 +9,17 @@
 // M_d = E_d - 2 interior rows by the element-wise 1D product.  One thread per
 // output value; the axis' neighbours are strided by `inner`, so a wave's
 // threads read consecutive values along the fastest axis.
+#include <mutex>
+
 #include "device_common.h"
 #include "launch.h"
 
 namespace fftfem {
+
+// Work arrays of fftfem_dirichlet_load_noalloc: the axis passes' two
+// intermediate arrays, in this file-scope device array instead of caller
+// memory.  Each device holds its own copy for the life of the process.
+static __device__ __align__(256) double scratch[kLiftScratchDoubles];
 
 __global__ __launch_bounds__(kBlock) void lift_kernel(LiftArgs a) {
   const int n = a.n, K = a.K;
@@ -62,6 +69,29 @@ hipError_t launch_lift(const LiftArgs& a, hipStream_t s) {
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(lift_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
   return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device.  The array's name is a
+// host-side stand-in in host code; its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current and
+// kept.
+hipError_t lift_scratch(double** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace fftfem

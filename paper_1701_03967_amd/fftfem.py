@@ -30,7 +30,7 @@ EXPORTS = [
     "fftfem_set_timing", "fftfem_get_timing",
     "fftfem_plan_batch", "fftfem_solve_batch", "fftfem_batch_get_stats", "fftfem_batch_workspace_bytes",
     "fftfem_destroy_batch", "fftfem_tune", "fftfem_implicit_euler", "fftfem_tune_save", "fftfem_tune_load",
-    "fftfem_coefficients", "fftfem_synthesize", "fftfem_dirichlet_load",
+    "fftfem_coefficients", "fftfem_synthesize", "fftfem_dirichlet_load", "fftfem_dirichlet_load_noalloc",
 ]
 BATCH_TUNE = 1
 ALGORITHM_B = 1  # fftfem_desc.flags: algorithm (b) of Sect. 4
@@ -118,6 +118,7 @@ def lib():
         L.fftfem_coefficients.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.fftfem_synthesize.argtypes = [vp, vp, vp, vp]
         L.fftfem_dirichlet_load.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fftfem_dirichlet_load_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.fftfem_tune_load.argtypes = [ctypes.c_char_p]
         _lib = L
     return _lib
@@ -391,6 +392,20 @@ class Plan:
             raise ValueError(f"work must be a contiguous float64 device tensor of at least {2 * ne} values")
         _check(lib().fftfem_dirichlet_load(self._h, _tptr(b), _tptr(f), _tptr(out), _tptr(work),
                                            _stream_ptr(stream)), "fftfem_dirichlet_load")
+        return out
+
+    def dirichlet_load_noalloc(self, b, f, out, stream=None):
+        """dirichlet_load with the library's static device work area instead of
+        a work array (fftfem_dirichlet_load_noalloc): nothing is allocated,
+        so `out` must be given."""
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()
+                and tuple(b.shape) == self.extended_shape):
+            raise ValueError(f"b must be a contiguous float64 device tensor of shape {self.extended_shape}")
+        self._check_tensor(f, "f")
+        self._check_tensor(out, "out")
+        _check(lib().fftfem_dirichlet_load_noalloc(self._h, _tptr(b), _tptr(f), _tptr(out), _stream_ptr(stream)),
+               "fftfem_dirichlet_load_noalloc")
         return out
 
     def implicit_euler(self, u, nsteps: int, F=None, work=None, stream=None):
