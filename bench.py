@@ -53,6 +53,10 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
         if ax > 0:
             return size * 4.0 * v
         return size * (2 * v + 8.0 + 8.0)
+    if name.startswith("resid3p"):
+        # 3D plane pass: reads u (or the correction), writes the two products
+        # (double-double: hi and lo planes)
+        return size * (40.0 if name.startswith("resid3pdd") else 24.0)
     if name.startswith("resid2"):
         # fused 2D residual: reads u (or the correction) and f (or r),
         # writes r
@@ -112,6 +116,8 @@ def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
             # the tiled kernel also carries its lines per workgroup: match
             # the symbol's prefix
             return f"{sym}<{n}, " if pre == "bandtile" else f"{sym}<{n}>"
+    if head.startswith("resid3p"):
+        return f"resid3p_kernel<{n}, {'true' if head == 'resid3pdd' else 'false'}>"
     if head.startswith("resid2"):
         return f"resid2_kernel<{n}, {'true' if head == 'resid2dd' else 'false'}>"
     if head.startswith("apply"):
@@ -418,6 +424,17 @@ def run_batch(args, torch, fm):
         "refinement": {"iterations_min": min(its), "iterations_max": max(its), "converged": conv},
         "workspace_bytes": b.workspace_bytes(),
     }
+    # HBM roofline of the whole batch on the per-dof pass model of a 2D
+    # solve: float64 3 passes x 16 B; float32 12 + 8 + 12 B; each refinement
+    # step 20 + 8 + 20 B (residual, float32 chain, update), at the mean
+    # number of steps taken
+    per = {"fp64": 48.0, "fp32": 32.0}.get(prec, 32.0 + 48.0 * float(np.mean(its)))
+    gbs = line["value"] * per / 1e9
+    line["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                        "model_bytes_per_unknown": per, "kernel": "whole batch"}
+    if getattr(args, "quiet", False):
+        return line
     print(json.dumps(line))
 
 
@@ -538,6 +555,7 @@ def main():
     ap.add_argument("--workload", default="c3_2d_n9_k1024")
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload in the default line")
     ap.add_argument("--modes", default="fp64,fp32,fp32_refine,fp64_b",
                     help="fp64, fp32, fp32_refine (algorithm (a)), fp64_b (algorithm (b))")
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")
@@ -672,6 +690,14 @@ def main():
                                     for m in res2 if m != "unknowns"}}
         line["also"][args.also]["unknowns"] = p2.size
         del sols2
+    if args.also and not args.no_batch:
+        # the batched heat-step workload, 3 timed replays after 1 warm-up
+        torch.cuda.empty_cache()
+        ba = argparse.Namespace(**vars(args))
+        ba.steps, ba.warmup, ba.quiet = 3, 1, True
+        bl = run_batch(ba, torch, fm)
+        line["also"]["c5_batch"] = {k: bl[k] for k in ("metric", "value", "unit", "ms_per_step", "dtype", "config",
+                                                      "refinement", "roofline", "plan_s", "first_solve_s")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.workload)
     print(json.dumps(line))

@@ -533,6 +533,62 @@ static int resid2(fftfem_plan_t p, const double* u, const double* f, double* out
   return from_hip(launch_resid2(p->nd[0], dd, a, s));
 }
 
+// The last pass of the 3D operator: out = f - (c_0 A_0 P + C_0 Q) (or
+// without f: the product), P and Q from the first two passes or the plane
+// pass in tmp[4..7]; double-double or plain float64 (out = r in place).
+static int operator_apply_axis0(fftfem_plan_t p, const double* f, void* out, int out_kind, const int* flag,
+                                hipStream_t s, int ph, bool dd) {
+  double** T = p->tmp;
+  p->phase = ph + 2;
+  const double c1[4] = {p->coef[0], 0, 0, 1};
+  if (dd)
+    return apply_pass(p, 0, {T[4], T[5]}, {T[6], T[7]}, f, out, nullptr, out_kind, nullptr, nullptr, c1, nullptr,
+                      flag, s);
+  return apply_pass(p, 0, {T[4], nullptr}, {T[6], nullptr}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
+                    nullptr, flag, s, false);
+}
+
+// The 3D plane pass (resid3p_kernel): axes 1 and 2 of one order, in batches
+// too; FFTFEM_RESID2=0 selects the three-pass form.
+static bool fused3d(fftfem_plan_t p) {
+  if (p->N != 3 || p->nd[1] != p->nd[2]) return false;
+  const char* e = std::getenv("FFTFEM_RESID2");
+  return !(e && e[0] == '0');
+}
+
+// Passes 1 and 2 of the 3D operator in one: P = (C_1 x C_2) u into tmp[4]
+// (and tmp[5], double-double lo), Q = (c_1 A_1 x C_2 + c_2 C_1 x A_2 +
+// react C_1 x C_2) u into tmp[6] (tmp[7]).
+static int resid3p(fftfem_plan_t p, const double* u, bool dd, const int* flag, hipStream_t s) {
+  double** T = p->tmp;
+  Resid2Args a{};
+  a.u = u;
+  a.out = T[4];
+  a.out_l = dd ? T[5] : nullptr;
+  a.out2 = T[6];
+  a.out2_l = dd ? T[7] : nullptr;
+  a.planes = p->M[0];
+  a.M0 = p->M[1];
+  a.M1 = p->M[2];
+  a.K0 = (int)p->K[1];
+  a.c0 = p->coef[1];
+  a.c1 = p->coef[2];
+  a.react = p->desc.react;
+  a.Ael = p->Ael[1];
+  a.Cel = p->Cel[1];
+  a.flag = flag;
+  const int64_t per_plane = (a.M1 + 63) / 64;
+  int E = 16;
+  while (E > 1 && a.planes * per_plane * ((a.K0 + E - 1) / E) < 8192) E /= 2;
+  a.E = E;
+  if (p->rec) {
+    record(p, REC_RESID3P, {p->nd[1], dd ? 1 : 0, 0, 0, 0}, a, (int)resid2_blocks(a), 0);
+    return FFTFEM_OK;
+  }
+  Timed tm(p, s, dd ? "resid3pdd" : "resid3pf64");
+  return from_hip(launch_resid3p(p->nd[1], dd, a, s));
+}
+
 int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out, int out_kind,
                    const int* flag, hipStream_t s, int ph = 0) {
   const double* c = p->coef;
@@ -542,6 +598,11 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   int rc;
   p->phase = ph;
   if (out_kind == 1 && fused2d(p)) return resid2(p, u, f, (double*)out, true, flag, s);
+  if (fused3d(p)) {
+    rc = resid3p(p, u, true, flag, s);
+    if (rc) return rc;
+    return operator_apply_axis0(p, f, out, out_kind, flag, s, ph, true);
+  }
   if (p->N == 1) {
     double c1[4] = {c[0], react, 0, 0};
     return apply_pass(p, 0, {u, nullptr}, none, f, out, nullptr, out_kind, nullptr, nullptr, c1, nullptr,
@@ -559,10 +620,7 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   double c4[4] = {c[1], react, 0, c[2]};
   rc = apply_pass(p, 1, {T[0], T[1]}, {T[2], T[3]}, nullptr, T[4], T[5], 2, T[6], T[7], cC, c4, flag, s);
   if (rc) return rc;
-  p->phase = ph + 2;
-  double c1[4] = {c[0], 0, 0, 1};
-  return apply_pass(p, 0, {T[4], T[5]}, {T[6], T[7]}, f, out, nullptr, out_kind, nullptr, nullptr, c1,
-                    nullptr, flag, s);
+  return operator_apply_axis0(p, f, out, out_kind, flag, s, ph, true);
 }
 
 // out = F + scale C u with C = C_1 x ... x C_N (F may be null), in plain
@@ -607,6 +665,11 @@ int operator_apply_incr(fftfem_plan_t p, double* r, const int* flag, hipStream_t
   int rc;
   p->phase = ph;
   if (fused2d(p)) return resid2(p, T[1], nullptr, r, false, flag, s);
+  if (fused3d(p)) {
+    rc = resid3p(p, T[1], false, flag, s);
+    if (rc) return rc;
+    return operator_apply_axis0(p, r, r, 1, flag, s, ph, false);
+  }
   rc = apply_pass(p, p->N - 1, {T[1], nullptr}, none, nullptr, T[0], nullptr, 1, T[2], nullptr, cC, cA, flag, s,
                   false);
   if (rc) return rc;

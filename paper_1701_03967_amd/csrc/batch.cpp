@@ -206,6 +206,9 @@ int build_graph(fftfem_batch_s* b, const double* const* f, double* const* u, hip
         e = launch_apply_grouped(g.key[0], g.key[1] != 0, g.key[2] != 0, GroupedOps{jobs, jobof, start, g.nblocks, g.lds},
                                  b->cap);
         break;
+      case REC_RESID3P:
+        e = launch_resid3p_grouped(g.key[0], g.key[1] != 0, GroupedOps{jobs, jobof, start, g.nblocks, 0}, b->cap);
+        break;
       case REC_RESID2:
         e = launch_resid2_grouped(g.key[0], g.key[1] != 0, GroupedOps{jobs, jobof, start, g.nblocks, 0}, b->cap);
         break;

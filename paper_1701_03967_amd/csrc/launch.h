@@ -80,6 +80,14 @@ struct Resid2Args {
   const double* Ael;      // element stiffness: (n+1)^2 hi values, then (n+1)^2 lo values
   const double* Cel;      // element mass, the same layout
   const int* flag;
+  // plane pass of a 3D array (axes 1 and 2 of one order; M0, M1, K0 and c0,
+  // c1 then refer to axes 1 and 2): planes = M_0, and the two products
+  // (C_1 x C_2) u into out (hi) / out_l (lo, double-double) and
+  // (c0 A_1 x C_2 + c1 C_1 x A_2 + react C_1 x C_2) u into out2 / out2_l
+  int64_t planes;
+  double* out_l;
+  double* out2;
+  double* out2_l;
 };
 
 // The banded solve along axis 0 (algorithm (b)): per line, the shifted 1D
@@ -184,7 +192,9 @@ inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, i
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
 hipError_t launch_resid2(int n, bool dd, const Resid2Args& a, hipStream_t s);
 hipError_t launch_resid2_grouped(int n, bool dd, const GroupedOps& g, hipStream_t s);
-int64_t resid2_blocks(const Resid2Args& a);  // workgroups of one launch
+int64_t resid2_blocks(const Resid2Args& a);  // workgroups of one launch (both forms)
+hipError_t launch_resid3p(int n, bool dd, const Resid2Args& a, hipStream_t s);
+hipError_t launch_resid3p_grouped(int n, bool dd, const GroupedOps& g, hipStream_t s);
 hipError_t launch_band(int n, const BandArgs& a, hipStream_t s);
 hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s);  // step 0, 1, 2
 hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s);

@@ -109,6 +109,40 @@ __device__ __forceinline__ dd row_apply(const double* vh, const double* vl, int 
   return s;
 }
 
+// Both products of a row, C v and A v, at position g of a float64 line
+// (the fused 2D pass): four independent partial sums (the two matrices,
+// even and odd t) instead of two serial chains of n + 1 error-free
+// multiply-adds, joined at the end.
+template <int NORD>
+__device__ __forceinline__ void row_apply2(const double* v, int g, const double* Xc, const double* Xa, dd& C,
+                                           dd& A) {
+#pragma clang fp contract(off)
+  constexpr int n = NORD;
+  constexpr int XX = (NORD + 1) * (NORD + 1);
+  const bool node = (g + 1) % n == 0;
+  const int l = node ? n : g % n + 1;
+  dd c0{0, 0}, c1{0, 0}, a0{0, 0}, a1{0, 0};
+#pragma unroll
+  for (int t = 0; t <= n; ++t) {
+    const int o = l * (n + 1) + t;
+    const double x = v[g - l + t];
+    dd_fma<false>((t & 1) ? c1 : c0, Xc[o], Xc[XX + o], x, 0.0);
+    dd_fma<false>((t & 1) ? a1 : a0, Xa[o], Xa[XX + o], x, 0.0);
+  }
+  if (node) {
+#pragma unroll
+    for (int t = 0; t <= n; ++t) {
+      const double x = v[g + t];
+      dd_fma<false>((t & 1) ? c1 : c0, Xc[t], Xc[XX + t], x, 0.0);
+      dd_fma<false>((t & 1) ? a1 : a0, Xa[t], Xa[XX + t], x, 0.0);
+    }
+  }
+  dd_axpy(c0, 1.0, c1);
+  dd_axpy(a0, 1.0, a1);
+  C = c0;
+  A = a0;
+}
+
 // ---------------------------------------------------------------------------
 // 1D operator pass along one axis.  With a and c the stiffness and mass rows
 // above, for each position of each line:
@@ -335,8 +369,8 @@ __device__ __forceinline__ void resid2_body(const Resid2Args& a, int bid, int nb
     const double* Xa_ = Xa + o0;
     const double* Xc_ = Xc + o0;
     if constexpr (DD) {
-      const dd C = row_apply<NORD, false>(vrow, nullptr, (int)col, Xc_);
-      const dd A = row_apply<NORD, false>(vrow, nullptr, (int)col, Xa_);
+      dd C, A;
+      row_apply2<NORD>(vrow, (int)col, Xc_, Xa_, C, A);
       v = dd{0, 0};
       z = dd{0, 0};
       dd_axpy(v, a.c0, C);
@@ -394,16 +428,34 @@ __device__ __forceinline__ void resid2_body(const Resid2Args& a, int bid, int nb
     rowvz(0, v0, z0);
     __syncthreads();
   }
+  // float64 pass: the next element's rows are loaded one element ahead
+  // (registers allow it; the double-double pass has no room for them)
+  constexpr bool PF = !DD;
+  double ux[PF ? n : 1][2];
+  if constexpr (PF) {
+#pragma unroll
+    for (int t = 1; t <= n; ++t) load_row((int64_t)n * e0 + t - 1, ux[t - 1][0], ux[t - 1][1]);
+  }
   dd carry{0, 0};  // the previous element's contribution to its right node
   for (int e = e0; e <= elast; ++e) {
     // rows t = 1..n of element e into the staging area
 #pragma unroll
     for (int t = 1; t <= n; ++t) {
-      double x0, x1;
-      load_row((int64_t)n * e + t - 1, x0, x1);
-      stage(t - 1, x0, x1);
+      if constexpr (PF) {
+        stage(t - 1, ux[t - 1][0], ux[t - 1][1]);
+      } else {
+        double x0, x1;
+        load_row((int64_t)n * e + t - 1, x0, x1);
+        stage(t - 1, x0, x1);
+      }
     }
     __syncthreads();
+    if constexpr (PF) {
+      if (e < elast) {
+#pragma unroll
+        for (int t = 1; t <= n; ++t) load_row((int64_t)n * (e + 1) + t - 1, ux[t - 1][0], ux[t - 1][1]);
+      }
+    }
     dd acc[n + 1];
 #pragma unroll
     for (int q = 0; q <= n; ++q) acc[q] = dd{0, 0};
@@ -445,6 +497,180 @@ __device__ __forceinline__ void resid2_body(const Resid2Args& a, int bid, int nb
 // double-double one (at most 168; its n + 1 double-double accumulators,
 // carried row and node partial spill at 128 for n >= 8).  The one-wave
 // workgroups on a CU hide each other's row loads.
+// Plane pass of the 3D operator (axes 1 and 2 of one order n), the first of
+// the two passes of the 3D residual: per plane i_0, with the same walk as
+// resid2_body (one wave per 64 columns of axis 2 and a chunk of E elements
+// of axis 1), the two products
+//   P = (C_1 x C_2) u,   Q = (c0 A_1 x C_2 + c1 C_1 x A_2 + react C_1 x C_2) u
+// (c0, c1: the coefficients of axes 1 and 2), from the rows' C_2 u and
+// A_2 u: P accumulates C_1 (C_2 u), Q accumulates A_1 (c0 C_2 u) and
+// C_1 (c1 A_2 u + react C_2 u).  The axis-0 pass then forms
+// f - (diff_0 4/h_0^2) A_0 P - C_0 Q.  DD: both in double-double (hi, lo
+// planes); otherwise float64.
+template <int NORD, bool DD>
+__device__ __forceinline__ void resid3p_body(const Resid2Args& a, int bid, int nblk) {
+#pragma clang fp contract(off)
+  if (a.flag && *a.flag) return;
+  constexpr int n = NORD, XX = (n + 1) * (n + 1), W = 64 + 2 * n;
+  __shared__ double Xa[2 * XX], Xc[2 * XX];
+  __shared__ double stg[n * W];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < 2 * XX; i += 64) {
+    Xa[i] = a.Ael[i];
+    Xc[i] = a.Cel[i];
+  }
+  const int64_t M0 = a.M0, M1 = a.M1;
+  const int ncb = (int)((M1 + 63) / 64);
+  const int nch = (a.K0 + a.E - 1) / a.E;
+  const int tile = xcd_remap(bid, nblk);
+  const int per = ncb * nch;
+  const int plane = tile / per, rest = tile - plane * per;
+  const int ch = rest / ncb, cb = rest - ch * ncb;
+  const int64_t pb = (int64_t)plane * M0 * M1;
+  const double* u = a.u + pb;
+  const int e0 = ch * a.E;
+  const int e1 = e0 + a.E < a.K0 ? e0 + a.E : a.K0;
+  const int elast = e1 < a.K0 ? e1 : e1 - 1;
+  const int64_t col0 = (int64_t)cb * 64, col = col0 + lane;
+  const bool colok = col < M1;
+
+  auto load_row = [&](int64_t r, double& x0, double& x1) {
+    x0 = x1 = 0.0;
+    if (r < 0 || r >= M0) return;
+    const int64_t c0 = col0 - n + lane, c1 = c0 + 64;
+    const double* row = u + r * M1;
+    if (c0 >= 0 && c0 < M1) x0 = row[c0];
+    if (lane < W - 64 && c1 < M1) x1 = row[c1];
+  };
+  auto stage = [&](int sr, double x0, double x1) {
+    stg[sr * W + lane] = x0;
+    if (lane < W - 64) stg[sr * W + 64 + lane] = x1;
+  };
+  auto opaque0 = []() {
+    int z = 0;
+    __asm__ volatile("" : "+v"(z));
+    return z;
+  };
+  // the row's inputs of the two accumulations: zp = C_2 u (for P), vq =
+  // c0 C_2 u and zq = c1 A_2 u + react C_2 u (for Q)
+  auto rowvz = [&](int sr, dd& zp, dd& vq, dd& zq) {
+    const double* vrow = stg + sr * W + n - col0;
+    const int o0 = opaque0();
+    const double* Xa_ = Xa + o0;
+    const double* Xc_ = Xc + o0;
+    if constexpr (DD) {
+      dd C, A;
+      row_apply2<NORD>(vrow, (int)col, Xc_, Xa_, C, A);
+      zp = dd_norm(C);
+      vq = dd{0, 0};
+      zq = dd{0, 0};
+      dd_axpy(vq, a.c0, C);
+      dd_axpy(zq, a.c1, A);
+      dd_axpy(zq, a.react, C);
+      vq = dd_norm(vq);
+      zq = dd_norm(zq);
+    } else {
+      const double C = row_apply_f64<NORD>(vrow, (int)col, Xc_);
+      const double A = row_apply_f64<NORD>(vrow, (int)col, Xa_);
+      zp = dd{C, 0};
+      vq = dd{a.c0 * C, 0};
+      zq = dd{__builtin_fma(a.c1, A, a.react * C), 0};
+    }
+  };
+  auto accumulate = [&](dd* ap, dd* aq, int t, const dd& zp, const dd& vq, const dd& zq) {
+    const int o0 = opaque0();
+#pragma unroll
+    for (int q = 0; q <= n; ++q) {
+      const int o = q * (n + 1) + t + o0;
+      if constexpr (DD) {
+        dd_fma<true>(ap[q], Xc[o], Xc[XX + o], zp.h, zp.l);
+        dd_fma<true>(aq[q], Xa[o], Xa[XX + o], vq.h, vq.l);
+        dd_fma<true>(aq[q], Xc[o], Xc[XX + o], zq.h, zq.l);
+      } else {
+        ap[q].h = __builtin_fma(Xc[o], zp.h, ap[q].h);
+        aq[q].h = __builtin_fma(Xa[o], vq.h, aq[q].h);
+        aq[q].h = __builtin_fma(Xc[o], zq.h, aq[q].h);
+      }
+    }
+  };
+  auto put = [&](int64_t g, const dd& P, const dd& Q) {
+    if (!colok || g < 0 || g >= M0) return;
+    const int64_t idx = pb + g * M1 + col;
+    if constexpr (DD) {
+      const dd p2 = dd_norm(P), q2 = dd_norm(Q);
+      a.out[idx] = p2.h;
+      a.out_l[idx] = p2.l;
+      a.out2[idx] = q2.h;
+      a.out2_l[idx] = q2.l;
+    } else {
+      a.out[idx] = P.h;
+      a.out2[idx] = Q.h;
+    }
+  };
+
+  dd zp0, vq0, zq0;
+  {
+    double x0, x1;
+    load_row((int64_t)n * e0 - 1, x0, x1);
+    stage(0, x0, x1);
+    __syncthreads();
+    rowvz(0, zp0, vq0, zq0);
+    __syncthreads();
+  }
+  dd carp{0, 0}, carq{0, 0};
+  for (int e = e0; e <= elast; ++e) {
+#pragma unroll
+    for (int t = 1; t <= n; ++t) {
+      double x0, x1;
+      load_row((int64_t)n * e + t - 1, x0, x1);
+      stage(t - 1, x0, x1);
+    }
+    __syncthreads();
+    dd ap[n + 1], aq[n + 1];
+#pragma unroll
+    for (int q = 0; q <= n; ++q) ap[q] = aq[q] = dd{0, 0};
+    accumulate(ap, aq, 0, zp0, vq0, zq0);
+#pragma unroll 1
+    for (int t = 1; t <= n; ++t) {
+      dd zp, vq, zq;
+      rowvz(t - 1, zp, vq, zq);
+      accumulate(ap, aq, t, zp, vq, zq);
+      if (t == n) {
+        zp0 = zp;
+        vq0 = vq;
+        zq0 = zq;
+      }
+    }
+    __syncthreads();
+    if (e > e0) {
+      dd P = carp, Q = carq;
+      dd_axpy(P, 1.0, ap[0]);
+      dd_axpy(Q, 1.0, aq[0]);
+      put((int64_t)n * e - 1, P, Q);
+    }
+    if (e < e1) {
+#pragma unroll
+      for (int t = 1; t < n; ++t) put((int64_t)n * e + t - 1, ap[t], aq[t]);
+    }
+    carp = ap[n];
+    carq = aq[n];
+  }
+}
+
+template <int NORD, bool DD>
+__global__ __launch_bounds__(64, DD ? 2 : 4) void resid3p_kernel(Resid2Args a) {
+  resid3p_body<NORD, DD>(a, blockIdx.x, gridDim.x);
+}
+
+template <int NORD, bool DD>
+__global__ __launch_bounds__(64, DD ? 2 : 4) void resid3p_kernel_grouped(const Resid2Args* __restrict__ jobs,
+                                                                         const int* __restrict__ job_of,
+                                                                         const int* __restrict__ start) {
+  const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
+  const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
+  resid3p_body<NORD, DD>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
+}
+
 template <int NORD, bool DD>
 __global__ __launch_bounds__(64, DD ? 3 : 4) void resid2_kernel(Resid2Args a) {
   resid2_body<NORD, DD>(a, blockIdx.x, gridDim.x);
@@ -728,7 +954,63 @@ hipError_t launch_resid2_grouped(int n, bool dd, const GroupedOps& g, hipStream_
   }
 }
 
-int64_t resid2_blocks(const Resid2Args& a) { return ((a.M1 + 63) / 64) * ((a.K0 + a.E - 1) / a.E); }
+int64_t resid2_blocks(const Resid2Args& a) {
+  return (a.planes > 0 ? a.planes : 1) * ((a.M1 + 63) / 64) * ((a.K0 + a.E - 1) / a.E);
+}
+
+hipError_t launch_resid3p(int n, bool dd, const Resid2Args& a, hipStream_t s) {
+  if (a.K0 < 1 || a.E < 1 || a.M1 < 1 || a.planes < 1) return hipErrorInvalidValue;
+  const int64_t nb = resid2_blocks(a);
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                              \
+  case N:                                                                                           \
+    if (dd)                                                                                         \
+      hipLaunchKernelGGL((resid3p_kernel<N, true>), dim3((unsigned)nb), dim3(64), 0, s, a);        \
+    else                                                                                            \
+      hipLaunchKernelGGL((resid3p_kernel<N, false>), dim3((unsigned)nb), dim3(64), 0, s, a);       \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_resid3p_grouped(int n, bool dd, const GroupedOps& g, hipStream_t s) {
+  const Resid2Args* jobs = (const Resid2Args*)g.jobs;
+  switch (n) {
+#define FFTFEM_CASE(N)                                                                                       \
+  case N:                                                                                                    \
+    if (dd)                                                                                                  \
+      hipLaunchKernelGGL((resid3p_kernel_grouped<N, true>), dim3(g.nblocks), dim3(64), 0, s, jobs, g.job_of, \
+                         g.start);                                                                           \
+    else                                                                                                     \
+      hipLaunchKernelGGL((resid3p_kernel_grouped<N, false>), dim3(g.nblocks), dim3(64), 0, s, jobs,          \
+                         g.job_of, g.start);                                                                 \
+    return hipGetLastError();
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_resid2(int n, bool dd, const Resid2Args& a, hipStream_t s) {
   if (a.K0 < 1 || a.E < 1 || a.M1 < 1) return hipErrorInvalidValue;

@@ -15,12 +15,12 @@
 namespace fftfem {
 
 // One launch a plan would issue, with its fully resolved arguments.
-enum RecKind { REC_LINE32 = 0, REC_LINE64, REC_APPLY, REC_TR32, REC_TR64, REC_RESET, REC_REDUCE, REC_RESID2 };
+enum RecKind { REC_LINE32 = 0, REC_LINE64, REC_APPLY, REC_TR32, REC_TR64, REC_RESET, REC_REDUCE, REC_RESID2, REC_RESID3P };
 
 struct Rec {
   int phase;                        // position in the plan's schedule (see fftfem_solve)
   int kind;                         // RecKind
-  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo, dd;  resid2: n, dd
+  int key[5];                       // line: n, mode, upd, lf, pow2;  apply: n, lo, dd;  resid2, resid3p: n, dd
   std::vector<unsigned char> args;  // LineArgs<T>, ApplyArgs, Resid2Args, TransposeJob, ResetJob or ReduceJob
   int nblocks;
   size_t lds;

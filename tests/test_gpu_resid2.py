@@ -1,5 +1,6 @@
-"""The fused 2D operator pass (one kernel over both axes) against the
-oracle: the double-double apply y = A u within about one float64 ulp per
+"""The fused 2D operator pass (one kernel over both axes) and the fused
+plane pass of the 3D operator (axes 1 and 2 in one kernel, then the axis-0
+pass) against the oracle: the double-double apply y = A u within about one float64 ulp per
 entry of the oracle's extended-precision (or exact rational) apply, for
 every element order, chunkings of axis 0 that leave partial chunks, column
 counts that are not multiples of the 64-column tile, tiny meshes and a
@@ -119,4 +120,62 @@ def test_refine_with_fused_residuals(fm, monkeypatch, n, K, diff, react, kind):
     u2 = p.solve(fd).cpu().numpy()
     st2 = p.stats()
     say("  two-pass", st2)
+    assert np.linalg.norm(u2 - u_ref) / np.linalg.norm(u_ref) < 1e-10
+
+
+CASES3 = [
+    (2, (3, 8, 12), (1.0, 2.0, 0.5), 0.0),
+    (3, (4, 5, 7), (0.5, 1.0, 2.0), 3.0),
+    ((2, 4, 4), (5, 6, 3), (1.0, 1.0, 1.0), 0.0),
+    (9, (2, 3, 2), (1.0, 0.5, 2.0), 1.0),
+    (5, (3, 4, 9), (1.0, 1.0, 1.0), 100.0),
+]
+
+
+@pytest.mark.parametrize("kind", ["smooth", "normal"])
+@pytest.mark.parametrize("n,K,diff,react", CASES3)
+def test_fused3d_apply_exact(fm, monkeypatch, n, K, diff, react, kind):
+    """3D operator apply with the plane pass: every entry within about one
+    ulp of exact rational arithmetic, and equal to the three-pass apply to
+    that accuracy (axis 0 may have another order than axes 1 and 2)."""
+    say("fused 3D apply", n, K, diff, react, kind)
+    ns = osolve.orders(n, 3)
+    shape = [m * k - 1 for m, k in zip(ns, K)]
+    if kind == "smooth":
+        u = np.ones(())
+        for d, (m, k) in enumerate(zip(ns, K)):
+            x = fem1d.dof_positions(m, k)
+            u = np.multiply.outer(u, np.sin((d + 1) * np.pi * x))
+    else:
+        u = inputs.draw_rhs(shape, 2400 + sum(ns), "normal")
+    y_ex = osolve.apply_A_exact(u, ns, K, diff, react)
+    p = fm.Plan(K, n, diff, react)
+    ud = torch.from_numpy(np.ascontiguousarray(u)).cuda()
+    y = p.apply_A(ud).cpu().numpy()
+    err = np.abs(y - y_ex)
+    assert np.all(err <= 2.3e-16 * np.abs(y_ex) + 1e-24 * np.abs(y_ex).max()), \
+        float((err / (np.abs(y_ex) + 1e-300)).max())
+    monkeypatch.setenv("FFTFEM_RESID2", "0")
+    y2 = p.apply_A(ud).cpu().numpy()
+    d = np.abs(y - y2)
+    assert np.all(d <= 4.5e-16 * np.abs(y2) + 1e-22 * float(np.abs(y2).max())), float(d.max())
+
+
+@pytest.mark.parametrize("n,K,diff,react,kind", [
+    (9, (8, 12, 16), (1.0, 2.0, 0.5), 0.0, "normal"),
+    (3, (20, 17, 33), (1.0, 1.0, 1.0), 0.0, "uniform"),
+    ((4, 2, 2), (16, 40, 24), (1.0, 0.5, 2.0), 1000.0, "normal"),
+])
+def test_refine_3d_with_fused_residuals(fm, monkeypatch, n, K, diff, react, kind):
+    say("refine fused 3D", n, K, diff, react, kind)
+    ns = osolve.orders(n, 3)
+    f = inputs.draw_rhs([m * k - 1 for m, k in zip(ns, K)], 2500 + sum(ns), kind)
+    u_ref = osolve.solve(f, n, K, diff, react)
+    fd = torch.from_numpy(f).cuda()
+    p = fm.Plan(K, n, diff, react, precision="fp32_refine", max_iter=6, tol=1e-13)
+    u = p.solve(fd).cpu().numpy()
+    say("  ", p.stats())
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-10
+    monkeypatch.setenv("FFTFEM_RESID2", "0")
+    u2 = p.solve(fd).cpu().numpy()
     assert np.linalg.norm(u2 - u_ref) / np.linalg.norm(u_ref) < 1e-10
