@@ -82,7 +82,9 @@ enum {
 /* Full plan description.  Fields left zero take the documented defaults. */
 typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
-  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above) */
+  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; one-axis
+                                     FFTFEM_FP64 plans of algorithm (a) also accept powers of two
+                                     up to 2^20: multi-pass transforms, not in batches) */
   int n;                          /* element order (every axis without n_axis), 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */
@@ -191,6 +193,8 @@ int fftfem_plan_tables(const fftfem_plan_t p, int axis, double* lam, double* Q);
  * inverse F_n transform (spectral -> physical); dir = 0: forward, divide by
  * the axis-only denominator react + diff[d] 4/h_d^2 lambda, inverse.  dtype:
  * 0 = compute in float64, 1 = compute in float32.  in and out may be equal.
+ * One-axis plans with K > 1024 (float64 only) transform the lines of all nrhs
+ * right-hand sides, by the multi-pass path.
  */
 int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in, double* out,
                            int dtype, hipStream_t s);

@@ -60,6 +60,25 @@ def load_vector(fun: Callable, n: int, K: Sequence[int], X=None, npts: int = Non
     return F
 
 
+def load_vector_1d(fun: Callable, n: int, K: int, X: float = 1.0, npts: int = None) -> np.ndarray:
+    """f^h of one axis, element by element (the sum over elements of the
+    module docstring written out without the dense M x (K npts) matrix of
+    ``quad_matrix``), for long lines."""
+    npts = n + 1 if npts is None else npts
+    xi, w = np.polynomial.legendre.leggauss(npts)
+    basis = lagrange_basis(n)
+    vals = np.array([_poly_eval(basis[i], xi) for i in range(n + 1)])  # (n+1, npts)
+    h = X / K
+    x0 = np.arange(K, dtype=np.float64) * h
+    xq = x0[:, None] + (xi[None, :] + 1) * h / 2  # (K, npts)
+    local = fun(xq) @ (w[None, :] * vals).T  # (K, n+1): sum_q w_q f(x_eq) e_i(xi_q)
+    M = n * K - 1
+    out = np.zeros(M + 2)  # slots -1 and M (the boundary nodes) at both ends
+    for i in range(n + 1):
+        out[i:i + n * K:n] += local[:, i]  # global dof (e - 1) n - 1 + i, shifted by one
+    return out[1:M + 1]
+
+
 def interpolate(fun: Callable, n: int, K: Sequence[int], X=None) -> np.ndarray:
     """Values of f at all dof points (the vector of S_K^(n) of f)."""
     X = [1.0] * len(K) if X is None else list(X)

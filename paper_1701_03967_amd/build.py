@@ -102,6 +102,7 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
     units.append(("ops.hip", "ops.o", []))
     units.append(("band.hip", "band.o", []))
     units.append(("lift.hip", "lift.o", []))
+    units.append(("long.hip", "long.o", []))
 
     def compile_unit(u):
         src, o, extra = u

@@ -55,6 +55,10 @@ struct fftfem_plan_s {
   int band_form = 0;         // ... 0: one sweep per line, 1: three kernels (few lines),
                              // 2: one LDS-tiled kernel (short lines)
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
+  bool longK = false;        // 1D, K > 1024: the multi-pass transforms of long.hip
+  double* Wl[2] = {nullptr, nullptr};  // their work arrays: nrhs x (1 + n/2) x K complex each
+  double* ltw[2] = {nullptr, nullptr}; // their sub-DFT twiddles, lengths K1 and K2
+  int lk1 = 0, lk2 = 0;
                              // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
@@ -869,15 +873,24 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     if (d.n_axis[i] == 0) d.n_axis[i] = d.n;
   for (int i = 0; i < d.N; ++i)
     if (d.n_axis[i] > kMaxLineOrder) return FFTFEM_ENOTIMPL;
-  // a line-kernel tile holds at most kLineTasks element tasks
-  for (int i = 0; i < d.N; ++i)
-    if (d.K[i] > kLineTasks) return FFTFEM_ENOTIMPL;
   const bool algb = (d.flags & FFTFEM_ALGORITHM_B) != 0;
+  // a line-kernel tile holds at most kLineTasks element tasks; longer lines
+  // take the multi-pass transforms (one axis, float64, K a power of two up
+  // to kLongMaxK, algorithm (a), not in batches)
+  bool longK = false;
+  for (int i = 0; i < d.N; ++i)
+    if (d.K[i] > kLineTasks) {
+      if (d.N == 1 && is_pow2(d.K[0]) && d.K[0] <= kLongMaxK && d.precision == FFTFEM_FP64 && !algb && !cache)
+        longK = true;
+      else
+        return FFTFEM_ENOTIMPL;
+    }
   if (algb && (d.precision != FFTFEM_FP64 || cache)) return FFTFEM_ENOTIMPL;
   fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
   if (!p) return FFTFEM_ENOMEM;
   p->desc = d;
   p->algb = algb;
+  p->longK = longK;
   p->N = d.N;
   p->n = d.n;
   p->nrhs = d.nrhs;
@@ -1002,6 +1015,25 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   }
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
+  if (!rc && p->longK) {
+    // work arrays and the sub-DFT twiddles (every (K/K_i)-th entry of the
+    // length-K table)
+    const int lk = ilog2(p->K[0]);
+    p->lk1 = lk / 2;
+    p->lk2 = lk - p->lk1;
+    const size_t w = (size_t)p->nrhs * (1 + p->nd[0] / 2) * 2 * (size_t)p->K[0];
+    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
+    const AxisTables& t = p->host[0];
+    for (int i = 0; i < 2 && !rc; ++i) {
+      const int64_t Ki = int64_t(1) << (i == 0 ? p->lk1 : p->lk2), st = p->K[0] / Ki;
+      std::vector<double> tw((size_t)2 * Ki);
+      for (int64_t q = 0; q < Ki; ++q) {
+        tw[2 * q] = t.twf[2 * q * st];
+        tw[2 * q + 1] = t.twf[2 * q * st + 1];
+      }
+      rc = upload<double>(p, &p->ltw[i], tw);
+    }
+  }
   p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 4 : 8);
   for (int i = 0; i < p->ntmp && !rc; ++i)
     rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
@@ -1104,12 +1136,76 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
   return rc;
 }
 
+// The FC_n transform (FWD: lines -> spectral coefficients), its inverse
+// (INV) or both with the division by react + the axis' denominators in
+// between (MID: the 1D solve) of nlines consecutive lines of a long-line
+// plan, by the multi-pass kernels of long.hip.
+static int long_transform(fftfem_plan_t p, int mode, const double* in, double* out, int64_t nlines,
+                          hipStream_t s, int* bad = nullptr) {
+  LongArgs a{};
+  a.bad = bad;
+  a.K = (int)p->K[0];
+  a.lk1 = p->lk1;
+  a.lk2 = p->lk2;
+  a.K1 = 1 << p->lk1;
+  a.K2 = 1 << p->lk2;
+  a.M = p->M[0];
+  a.nlines = nlines;
+  a.Q = tab<double>(p, 0, 0);
+  a.twf = tab<double>(p, 0, 1);
+  a.twm = tab<double>(p, 0, 2);
+  a.twd = tab<double>(p, 0, 3);
+  a.mu = tab<double>(p, 0, 4);
+  a.tw1 = p->ltw[0];
+  a.tw2 = p->ltw[1];
+  a.react = p->desc.react;
+  a.wa = p->Wl[0];
+  a.wb = p->Wl[1];
+  const int n = p->nd[0];
+  int rc = FFTFEM_OK;
+  auto step = [&](int st, bool inv, const char* name) {
+    if (rc) return;
+    Timed tm(p, s, name);
+    rc = from_hip(launch_long(n, st, inv, a, a.wa, a.wb, s));
+  };
+  if (mode == FWD || mode == MID) {
+    a.in = in;
+    a.out = out;
+    step(LONG_GATHER, false, "lgather64");
+    step(LONG_COLS, false, "lcols64");
+    step(LONG_ROWS, false, "lrows64");
+    step(LONG_CONTRACT_FWD, false, "lcfwd64");
+  }
+  if (mode == MID) {
+    a.in = out;
+    a.out = out;
+    step(LONG_DIVIDE, false, "ldiv64");
+  }
+  if (mode == INV || mode == MID) {
+    a.in = mode == INV ? in : out;
+    a.out = out;
+    step(LONG_CONTRACT_INV, false, "lcinv64");
+    step(LONG_COLS, true, "lcols64i");
+    step(LONG_ROWS, true, "lrows64i");
+    step(LONG_SCATTER, false, "lscatter64");
+  }
+  return rc;
+}
+
 int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
   if (!p || !f || !u) return FFTFEM_EINVAL;
   size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
   if (overlap(f, u, bytes)) return FFTFEM_EINVAL;
   p->last = s;
   int rc = FFTFEM_OK;
+  if (p->longK) {
+    // float64, no refinement: reset the statistics, then every right-hand
+    // side at once
+    for (int r = 0; r < p->nrhs && !rc; ++r)
+      rc = from_hip(launch_reset(p->flags + r, p->stats + (size_t)r * kStatsLen, kStatsLen, s));
+    if (!rc) rc = long_transform(p, MID, f, u, p->nrhs, s, p->flags);
+    return rc;
+  }
   for (int r = 0; r < p->nrhs && !rc; ++r) {
     const double* fr = f + (size_t)r * p->size;
     double* ur = u + (size_t)r * p->size;
@@ -1316,6 +1412,12 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
   if (kind == 0 && in == out) return FFTFEM_EINVAL;
   p->last = s;
   int rc = FFTFEM_OK;
+  if (p->longK) {
+    // long lines: every right-hand side's line in one multi-pass transform
+    for (int r = 0; r < p->nrhs && !rc && kind == 0; ++r)
+      rc = mass_apply(p, in + (size_t)r * p->size, nullptr, out + (size_t)r * p->size, 1.0, s);
+    return rc ? rc : long_transform(p, FWD, kind == 0 ? out : in, out, p->nrhs, s);
+  }
   for (int r = 0; r < p->nrhs && !rc; ++r) {
     const size_t o = (size_t)r * p->size;
     const double* src = in + o;
@@ -1418,6 +1520,7 @@ int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_
   const size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
   if (in != out && overlap(in, out, bytes)) return FFTFEM_EINVAL;
   p->last = s;
+  if (p->longK) return long_transform(p, INV, in, out, p->nrhs, s);
   int rc = FFTFEM_OK;
   for (int r = 0; r < p->nrhs && !rc; ++r) {
     const size_t o = (size_t)r * p->size;
@@ -1474,6 +1577,12 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
   if (dtype != 0 && dtype != 1) return FFTFEM_EINVAL;
   int mode = dir > 0 ? FWD : (dir < 0 ? INV : MID);
   p->last = s;
+  if (p->longK) {
+    // long lines: float64 only, every right-hand side's line
+    if (dtype != 0) return FFTFEM_ENOTIMPL;
+    if (in != out && overlap(in, out, (size_t)p->size * p->nrhs * sizeof(double))) return FFTFEM_EINVAL;
+    return long_transform(p, mode, in, out, p->nrhs, s);
+  }
   Geom g = natural_geom(p, axis, false);
   if (dtype == 0) return line_pass<double>(p, g, mode, in, 1, out, 1, nullptr, nullptr, s, false);
   return line_pass<float>(p, g, mode, in, 1, out, 1, nullptr, nullptr, s, false);

@@ -110,6 +110,31 @@ struct BandArgs {
   int nother;
 };
 
+// Multi-pass transforms of long lines (1D plans, K = K1 K2 > 1024): work
+// arrays wa and wb of nlines x (1 + n/2) buffers of K complex values.
+enum { LONG_GATHER = 0, LONG_COLS, LONG_ROWS, LONG_CONTRACT_FWD, LONG_CONTRACT_INV, LONG_SCATTER, LONG_DIVIDE };
+struct LongArgs {
+  const double* in;       // lines (gather, inverse contraction, divide)
+  double* out;            // lines (forward contraction, scatter, divide)
+  double* wa;             // gather / inverse-contraction output, column-pass buffers
+  double* wb;             // row-pass output (natural order)
+  int K, K1, K2, lk1, lk2;
+  int64_t M, nlines;
+  const double* Q;        // (c n + l) K + k, float64
+  const double* twf;      // K complex exp(-2 pi i q / K)
+  const double* twm;      // K complex exp(-i pi k / (2K))
+  const double* twd;      // K complex exp(-i pi k / K)
+  const double* tw1;      // K1 complex exp(-2 pi i q / K1)
+  const double* tw2;      // K2 complex exp(-2 pi i q / K2)
+  const double* mu;       // M: the axis' spectral denominators (divide)
+  double react;
+  int* bad;               // scatter: when set, bit 2 of bad[l] marks NaN / Inf in line l
+};
+// step LONG_COLS / LONG_ROWS work on buffer array w (rows: into out), the
+// others on the arrays of a
+hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, double* out, hipStream_t s);
+size_t long_lds_bytes(int K1, int K2);
+
 // One axis pass of the Dirichlet lifting (extended axis of E = nK + 1 points
 // -> its M = nK - 1 interior rows): out[o, i, ii] = sum_q X_ext[i + 1, q] in[o, q, ii].
 struct LiftArgs {
@@ -212,6 +237,7 @@ hipError_t launch_reduce(const double* partials, int nparts, int iter, double to
 
 constexpr int kBlock = 256;        // threads per workgroup of every kernel
 constexpr int kLineTasks = 1024;   // G * K limit of one line-kernel tile
+constexpr int64_t kLongMaxK = int64_t(1) << 20;  // largest K of the long-line transforms (1D)
 constexpr int kMaxLineOrder = 9;   // element orders compiled into the line kernels
 
 }  // namespace fftfem

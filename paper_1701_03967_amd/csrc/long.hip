@@ -1,0 +1,386 @@
+// Transforms of long lines (gfx950): the direct FC_n transform and its
+// inverse (Sect. 3, Theorem 2) for one-dimensional plans whose element count
+// K exceeds what one LDS tile holds (K = K1 K2 a power of two up to 2^20,
+// K1, K2 <= 1024).  The steps of a line pass run as separate passes over
+// global work arrays of NB = 1 + floor(n/2) complex buffers of K slots per
+// line, packed as in the line passes (the node channel's odd extension of
+// length 2K, then the bubble channel pairs in the reordering that makes
+// their DCT-II a K-point DFT):
+//
+//   forward:  gather -> columns -> rows -> contraction
+//   inverse:  contraction -> columns -> rows -> scatter
+//
+// "columns" and "rows" are the two halves of a four-step DFT of length K:
+// the buffer viewed as K1 x K2 (index i1 K2 + i2), length-K1 DFTs down the
+// columns with the twiddles exp(-+2 pi i i2 k1 / K), then length-K2 DFTs
+// along the rows, stored transposed so that frequency k1 + K1 k2 lands at
+// index k1 + K1 k2 (natural order).  The sub-DFTs run in LDS with the
+// Stockham stages of fft.h; the forward and inverse DFTs differ only in the
+// sign of the twiddles.  The per-frequency untangling and the contractions
+// with Q_k are those of the line passes (spectral.h).
+#include "device_common.h"
+#include "fft.h"
+#include "launch.h"
+#include "spectral.h"
+
+namespace fftfem {
+
+extern __shared__ double2 fftfem_long_lds[];
+
+constexpr int kLongThreads = 256;
+constexpr int kLongG = 4;  // columns (rows) per four-step tile: 4 x 1025 x 16 B = 66 KB of LDS
+
+using CD = C2<double>;
+
+__device__ __forceinline__ CD* long_buf(double* w, int64_t line, int b, int NB, int K) {
+  return reinterpret_cast<CD*>(w) + ((size_t)line * NB + b) * (size_t)K;
+}
+
+// Element jp of line l: node jp + 1 and the bubble channels into the work
+// buffers (as the gather of the line passes).
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
+  constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NB = 1 + P;
+  const int K = a.K;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  if (t >= a.nlines * K) return;
+  const int64_t l = t / K;
+  const int jp = (int)(t - l * K);
+  const double* r = a.in + l * a.M + (int64_t)jp * n;
+  double y[NORD], hv[NORD];
+#pragma unroll
+  for (int m = 0; m < n - 1; ++m) y[m] = r[m];
+  y[n - 1] = jp < K - 1 ? r[n - 1] : 0.0;
+  const double sg = (jp & 1) ? -1.0 : 1.0;
+  hv[0] = y[n - 1];
+#pragma unroll
+  for (int m = 1; m <= ne; ++m) hv[m] = sg * ((2 * m == n) ? y[m - 1] : y[m - 1] + y[n - m - 1]);
+#pragma unroll
+  for (int m = 1; m <= no; ++m) hv[ne + m] = y[m - 1] - y[n - m - 1];
+  CD* Z = long_buf(a.wa, l, 0, NB, K);
+  if (jp < K - 1) {
+    const int j = jp + 1, t2 = 2 * K - j;
+    setc<false>(Z, j >> 1, j & 1, hv[0]);
+    setc<false>(Z, t2 >> 1, t2 & 1, -hv[0]);
+  } else {
+    write_nodal_zeros<double, false>(Z, K);
+  }
+  const int q = (jp & 1) ? K - 1 - (jp >> 1) : (jp >> 1);
+#pragma unroll
+  for (int b = 0; b < n - 1; ++b) setc<false>(Z + (1 + b / 2) * (size_t)K, q, b & 1, hv[1 + b]);
+  if ((n - 1) & 1) setc<false>(Z + P * (size_t)K, q, 1, 0.0);
+}
+
+// Four-step DFT, first half: kLongG adjacent columns (i2) of one buffer,
+// length-K1 DFTs over i1, then the twiddles exp(-+2 pi i i2 k1 / K); in place.
+template <bool INV>
+__global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, double* w) {
+  constexpr int G = kLongG;
+  const int K1 = a.K1, K2 = a.K2, K = a.K;
+  const int ncb = K2 / G;
+  const int64_t tile = blockIdx.x;
+  const int64_t buf = tile / ncb;
+  const int c0 = (int)(tile - buf * ncb) * G;
+  CD* X = reinterpret_cast<CD*>(w) + buf * (size_t)K;
+  CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
+  const int ls = K1 + 1;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < G * K1; i += kLongThreads) {
+    const int i1 = i / G, g = i - i1 * G;
+    slot(L + g * ls, i1) = X[(size_t)i1 * K2 + c0 + g];
+  }
+  __syncthreads();
+  fft_all<double, INV, kLongThreads>(L, G, a.lk1, reinterpret_cast<const CD*>(a.tw1), ls, 4);
+  const CD* twf = reinterpret_cast<const CD*>(a.twf);
+  for (int i = tid; i < G * K1; i += kLongThreads) {
+    const int k1 = i / G, g = i - k1 * G;
+    CD v = slot(L + g * ls, k1);
+    const CD tw = twf[((int64_t)(c0 + g) * k1) & (K - 1)];
+    X[(size_t)k1 * K2 + c0 + g] = INV ? cmulc(v, tw) : cmul(v, tw);
+  }
+}
+
+// Four-step DFT, second half: kLongG adjacent rows (k1) of one buffer of w,
+// length-K2 DFTs over i2, stored into the same buffer of out at k1 + K1 k2.
+template <bool INV>
+__global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, const double* w, double* out) {
+  constexpr int G = kLongG;
+  const int K1 = a.K1, K2 = a.K2, K = a.K;
+  const int nrb = K1 / G;
+  const int64_t tile = blockIdx.x;
+  const int64_t buf = tile / nrb;
+  const int r0 = (int)(tile - buf * nrb) * G;
+  const CD* X = reinterpret_cast<const CD*>(w) + buf * (size_t)K;
+  CD* Y = reinterpret_cast<CD*>(out) + buf * (size_t)K;
+  CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
+  const int ls = K2 + 1;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < G * K2; i += kLongThreads) {
+    const int g = i / K2, i2 = i - g * K2;
+    slot(L + g * ls, i2) = X[(size_t)(r0 + g) * K2 + i2];
+  }
+  __syncthreads();
+  fft_all<double, INV, kLongThreads>(L, G, a.lk2, reinterpret_cast<const CD*>(a.tw2), ls, 4);
+  for (int i = tid; i < G * K2; i += kLongThreads) {
+    const int k2 = i / G, g = i - k2 * G;
+    Y[(size_t)(r0 + g) + (size_t)K1 * k2] = slot(L + g * ls, k2);
+  }
+}
+
+// Frequencies kap and K - kap (kap = 0: the bubble-only block and K/2) of
+// line l: untangled spectra of wb -> coefficients (y, s~) in the spectral
+// order of the line (k = 0 block of n - 1, then n per k).
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArgs a) {
+  constexpr int n = NORD, NC = NORD > 1 ? NORD - 1 : 1;
+  const int K = a.K, kh = K >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  if (t >= a.nlines * kh) return;
+  const int64_t l = t / kh;
+  const int kap = (int)(t - l * kh);
+  const int ka = kap, kb = kap == 0 ? kh : K - kap;
+  const CD* B = long_buf(a.wb, l, 0, 1 + NORD / 2, K);
+  const CD* twm = reinterpret_cast<const CD*>(a.twm);
+  const CD* twd = reinterpret_cast<const CD*>(a.twd);
+  double ca[NC], cb[NC], cha[NORD], chb[NORD], wa[NORD], wb[NORD];
+  if (kap == 0) {
+    if constexpr (NORD > 1) {
+      bubble_post<double, NORD, false>(B, K, 0, 0, twm, ca, cb);
+#pragma unroll
+      for (int b = 0; b < NORD - 1; ++b) cha[b] = ca[b];
+      bubble_post<double, NORD, false>(B, K, kb, kb, twm, ca, cb);
+    }
+    cha[NORD - 1] = 0;
+    channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), ca, ca, chb);
+  } else {
+    if constexpr (NORD > 1) bubble_post<double, NORD, false>(B, K, ka, kb, twm, ca, cb);
+    channel_vec<double, NORD>(nodal_post<double, false>(B, K, ka, twd, false), ca, cb, cha);
+    channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), cb, ca, chb);
+  }
+  const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
+  contract_fwd<double, NORD>(qtab, K, ka, cha, wa);
+  contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
+  double* rs = a.out + l * a.M;
+  const int ra = ka == 0 ? n - 1 : n;
+  const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
+  const int offb = n - 1 + (kb - 1) * n;
+#pragma unroll
+  for (int c = 0; c < NORD; ++c) {
+    if (c < ra) rs[offa + c] = wa[c];
+    rs[offb + c] = wb[c];
+  }
+}
+
+// The inverse: coefficients of frequencies kap and K - kap -> channel
+// spectra with the Hermitian pre-twiddles -> slots of the buffers of wa.
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArgs a) {
+  constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NC = NORD > 1 ? NORD - 1 : 1;
+  const int K = a.K, kh = K >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  if (t >= a.nlines * kh) return;
+  const int64_t l = t / kh;
+  const int kap = (int)(t - l * kh);
+  const int ka = kap, kb = kap == 0 ? kh : K - kap;
+  const double* rs = a.in + l * a.M;
+  const int ra = ka == 0 ? n - 1 : n;
+  const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
+  const int offb = n - 1 + (kb - 1) * n;
+  double wa[NORD], wb[NORD], h0[NORD], h1[NORD];
+#pragma unroll
+  for (int c = 0; c < NORD; ++c) {
+    wa[c] = c < ra ? rs[offa + c] : 0.0;
+    wb[c] = rs[offb + c];
+  }
+  const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
+  contract_inv<double, NORD>(qtab, K, ka, wa, h0);
+  contract_inv<double, NORD>(qtab, K, kb, wb, h1);
+  CD* B = long_buf(a.wa, l, 0, 1 + P, K);
+  const CD* twm = reinterpret_cast<const CD*>(a.twm);
+  if (kap == 0) {
+    write_nodal_zeros<double, false>(B, K);
+    write_nodal_inv<double, false>(B, K, kh, h1[0]);
+  } else {
+    write_nodal_inv<double, false>(B, K, kap, h0[0]);
+    write_nodal_inv<double, false>(B, K, K - kap, h1[0]);
+  }
+  if constexpr (NORD > 1) {
+    double ya[NC], yb[NC];
+    if (kap == 0) {
+#pragma unroll
+      for (int b = 0; b < NORD - 1; ++b) ya[b] = h0[b];
+#pragma unroll
+      for (int m = 1; m <= ne; ++m) yb[m - 1] = h1[m];
+#pragma unroll
+      for (int m = 1; m <= no; ++m) yb[ne + m - 1] = h1[ne + m];
+#pragma unroll
+      for (int p = 1; p <= P; ++p) {
+        const int b0 = 2 * (p - 1), b1 = b0 + 1;
+        const bool has1 = b1 < NORD - 1;
+        B[p * (size_t)K + 0] = CD{ya[b0], has1 ? ya[b1] : 0.0};
+        const CD va = herm<double>(yb[b0], yb[b0], kh, twm);
+        const CD vb = has1 ? herm<double>(yb[b1], yb[b1], kh, twm) : CD{0, 0};
+        B[p * (size_t)K + kh] = CD{va.x - vb.y, va.y + vb.x};
+      }
+    } else {
+#pragma unroll
+      for (int m = 1; m <= ne; ++m) {
+        ya[m - 1] = h1[m];
+        yb[m - 1] = h0[m];
+      }
+#pragma unroll
+      for (int m = 1; m <= no; ++m) {
+        ya[ne + m - 1] = h0[ne + m];
+        yb[ne + m - 1] = h1[ne + m];
+      }
+#pragma unroll
+      for (int p = 1; p <= P; ++p) {
+        const int b0 = 2 * (p - 1), b1 = b0 + 1;
+        const bool has1 = b1 < NORD - 1;
+        CD va = herm<double>(ya[b0], yb[b0], kap, twm);
+        CD vb = has1 ? herm<double>(ya[b1], yb[b1], kap, twm) : CD{0, 0};
+        B[p * (size_t)K + kap] = CD{va.x - vb.y, va.y + vb.x};
+        va = herm<double>(yb[b0], ya[b0], K - kap, twm);
+        vb = has1 ? herm<double>(yb[b1], ya[b1], K - kap, twm) : CD{0, 0};
+        B[p * (size_t)K + (K - kap)] = CD{va.x - vb.y, va.y + vb.x};
+      }
+    }
+  }
+}
+
+// Element jp of line l from the inverse-transformed buffers of wb: node
+// jp + 1 and the element's bubbles (as the scatter of the line passes).
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_scatter_kernel(LongArgs a) {
+  constexpr int n = NORD, ne = NORD / 2, P = NORD / 2, NB = 1 + P;
+  const int K = a.K;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  if (t >= a.nlines * K) return;
+  const int64_t l = t / K;
+  const int jp = (int)(t - l * K);
+  const CD* Z = long_buf(a.wb, l, 0, NB, K);
+  const CD* twd = reinterpret_cast<const CD*>(a.twd);
+  double hv[NORD];
+  hv[n - 1] = jp < K - 1 ? nodal_post<double, false>(Z, K, jp + 1, twd, true) : 0.0;
+  const int q = (jp & 1) ? K - 1 - (jp >> 1) : (jp >> 1);
+  const double sg = (jp & 1) ? -1.0 : 1.0;
+#pragma unroll
+  for (int m = 1; m <= ne; ++m) {
+    const int be = m - 1;
+    const double E = sg * reinterpret_cast<const double*>(Z + (1 + be / 2) * (size_t)K + q)[be & 1];
+    if (2 * m == n) {
+      hv[m - 1] = E;
+    } else {
+      const int bo = ne + m - 1;
+      const double O = reinterpret_cast<const double*>(Z + (1 + bo / 2) * (size_t)K + q)[bo & 1];
+      hv[m - 1] = E + O;
+      hv[n - m - 1] = E - O;
+    }
+  }
+  double* r = a.out + l * a.M + (int64_t)jp * n;
+#pragma unroll
+  for (int m = 0; m < n - 1; ++m) r[m] = hv[m];
+  if (jp < K - 1) r[n - 1] = hv[n - 1];
+  if (a.bad) {
+    // K is a multiple of the block size: every wave lies in one line
+    bool nonfinite = false;
+#pragma unroll
+    for (int m = 0; m < n; ++m) nonfinite |= !(hv[m] - hv[m] == 0.0);
+    if (__ballot(nonfinite) != 0 && (threadIdx.x & 63) == 0) atomicOr(a.bad + l, 2);
+  }
+}
+
+// Spectral coefficients of every line divided by react + mu (the axis'
+// denominators): the middle step of a 1D solve.
+__global__ __launch_bounds__(kLongThreads) void long_divide_kernel(LongArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  if (t >= a.nlines * a.M) return;
+  const int64_t i = t % a.M;
+  a.out[t] = a.in[t] / (a.react + a.mu[i]);
+}
+
+static hipError_t grid_launch_check(int64_t threads, unsigned* nb) {
+  const int64_t b = (threads + kLongThreads - 1) / kLongThreads;
+  if (b < 1 || b > 0x7fffffff) return hipErrorInvalidValue;
+  *nb = (unsigned)b;
+  return hipSuccess;
+}
+
+template <int NORD>
+static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
+  unsigned nb = 0;
+  hipError_t e;
+  switch (step) {
+    case LONG_GATHER:
+      if ((e = grid_launch_check(a.nlines * a.K, &nb))) return e;
+      hipLaunchKernelGGL((long_gather_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
+      break;
+    case LONG_CONTRACT_FWD:
+      if ((e = grid_launch_check(a.nlines * (a.K / 2), &nb))) return e;
+      hipLaunchKernelGGL((long_contract_fwd_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
+      break;
+    case LONG_CONTRACT_INV:
+      if ((e = grid_launch_check(a.nlines * (a.K / 2), &nb))) return e;
+      hipLaunchKernelGGL((long_contract_inv_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
+      break;
+    case LONG_SCATTER:
+      if ((e = grid_launch_check(a.nlines * a.K, &nb))) return e;
+      hipLaunchKernelGGL((long_scatter_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t long_lds_bytes(int K1, int K2) {
+  const int m = K1 > K2 ? K1 : K2;
+  return (size_t)kLongG * (m + 1) * sizeof(CD);
+}
+
+hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, double* out, hipStream_t s) {
+  if (a.K != a.K1 * a.K2 || a.K1 % kLongG || a.K2 % kLongG || a.K % kLongThreads || a.nlines < 1)
+    return hipErrorInvalidValue;
+  const int NB = 1 + n / 2;
+  if (step == LONG_COLS || step == LONG_ROWS) {
+    const int64_t tiles = a.nlines * NB * (int64_t)((step == LONG_COLS ? a.K2 : a.K1) / kLongG);
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = long_lds_bytes(a.K1, a.K2);
+    if (step == LONG_COLS) {
+      auto fn = inv ? long_cols_kernel<true> : long_cols_kernel<false>;
+      (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(kLongThreads), lds, s, a, w);
+    } else {
+      auto fn = inv ? long_rows_kernel<true> : long_rows_kernel<false>;
+      (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(kLongThreads), lds, s, a, (const double*)w, out);
+    }
+    return hipGetLastError();
+  }
+  if (step == LONG_DIVIDE) {
+    unsigned nb = 0;
+    hipError_t e = grid_launch_check(a.nlines * a.M, &nb);
+    if (e) return e;
+    hipLaunchKernelGGL(long_divide_kernel, dim3(nb), dim3(kLongThreads), 0, s, a);
+    return hipGetLastError();
+  }
+  switch (n) {
+#define FFTFEM_CASE(N) \
+  case N:              \
+    return long_step_n<N>(step, a, s);
+    FFTFEM_CASE(1)
+    FFTFEM_CASE(2)
+    FFTFEM_CASE(3)
+    FFTFEM_CASE(4)
+    FFTFEM_CASE(5)
+    FFTFEM_CASE(6)
+    FFTFEM_CASE(7)
+    FFTFEM_CASE(8)
+    FFTFEM_CASE(9)
+#undef FFTFEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fftfem

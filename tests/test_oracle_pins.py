@@ -280,6 +280,25 @@ def test_load_of_polynomial_is_exact():
     assert np.allclose(fh, C @ loads.interpolate(f, n, (K,)), atol=1e-15)
 
 
+def test_elementwise_1d_load():
+    """The element-by-element load of long lines: f = 1 gives the textbook
+    weights (n = 1: the hat functions integrate to h, so f^h = 2; n = 2:
+    Simpson, node 2/3 from two elements, midpoint 4/3); polynomial loads are
+    exact (Ccal I_h f); and it agrees with the dense form on a non-unit box."""
+    one = lambda x: np.ones_like(x)
+    assert np.allclose(loads.load_vector_1d(one, 1, 6), 2.0, atol=1e-15)
+    f2 = loads.load_vector_1d(one, 2, 5, X=3.0)
+    assert np.allclose(f2[1::2], 2.0 / 3.0, atol=1e-15) and np.allclose(f2[0::2], 4.0 / 3.0, atol=1e-15)
+    n, K = 4, 6
+    f = lambda x: x * (1 - x) * (x - 0.3) * (x + 0.2)
+    _, C = fem1d.assemble(n, K)
+    assert np.allclose(loads.load_vector_1d(f, n, K), C @ loads.interpolate(f, n, (K,)), atol=1e-15)
+    _, fe = loads.sin_product((3,), (1.0,), X=[2.5])
+    for n, K in ((1, 7), (5, 3), (9, 4)):
+        a = loads.load_vector(fe, n, (K,), X=[2.5])
+        assert np.abs(loads.load_vector_1d(fe, n, K, X=2.5) - a).max() <= 1e-14 * np.abs(a).max()
+
+
 def _table_case(N, n, K):
     ue, fe = loads.paper_2d() if N == 2 else loads.paper_3d()
     Ks = (K,) * N
