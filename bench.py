@@ -485,48 +485,70 @@ def run_heat(args, torch, fm):
 
 
 TRANSFORM_K = {"pow2": (32, 64, 128, 256, 512, 1024), "prime": (31, 61, 127, 257, 509, 1021),
-               "composite": (48, 96, 200, 384, 600, 1000)}
+               "composite": (48, 96, 200, 384, 600, 1000),
+               "long": (1 << 11, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20)}
 
 
 def run_transform1d(args, torch, fm):
     """1D FC_n (forward) and F_n (inverse) transforms, n = 5, along the
     contiguous axis of a 3D array of about 2^26 dofs (the lines are the other
     two axes), for element counts that are powers of two, primes and
-    composites (the latter two through chirp-z DFTs); float64.  Per K: the
-    mean time of one transform of all lines, dofs/s and GB/s (one read and one
-    write of 8 bytes per dof)."""
+    composites (the latter two through chirp-z DFTs); float64.  Long lines
+    (K = 2^11 .. 2^20, "long"): one-axis plans whose right-hand sides are the
+    lines, through the multi-pass four-step transforms, with the mean time of
+    each of their kernels.  Per K: the mean time of one transform of all
+    lines, dofs/s and GB/s (one read and one write of 8 bytes per dof)."""
     n = 5
     rows = []
-    for kind, Ks in TRANSFORM_K.items():
-        for K in Ks:
+    kinds = [k.strip() for k in args.transform_kinds.split(",") if k.strip()]
+    for kind in kinds:
+        for K in TRANSFORM_K[kind]:
             M = n * K - 1
             lines = max(1, (1 << 26) // M)
-            k0 = max(2, min(1024, int(round(np.sqrt(lines) / n))))
-            k1 = max(2, min(1024, int(round(lines / (n * k0 - 1) / n))))
-            plan = fm.Plan((k0, k1, K), n, (1.0, 1.0, 1.0), 0.0)
+            if kind == "long":
+                plan = fm.Plan((K,), n, (1.0,), 0.0, nrhs=lines)
+                axis, nl = 0, lines
+            else:
+                k0 = max(2, min(1024, int(round(np.sqrt(lines) / n))))
+                k1 = max(2, min(1024, int(round(lines / (n * k0 - 1) / n))))
+                plan = fm.Plan((k0, k1, K), n, (1.0, 1.0, 1.0), 0.0)
+                axis, nl = 2, plan.shape[0] * plan.shape[1]
+            shape = (lines, M) if kind == "long" else plan.shape
             g = torch.Generator(device="cuda")
             g.manual_seed(K)
-            x = torch.randn(plan.shape, generator=g, dtype=torch.float64, device="cuda")
+            x = torch.randn(shape, generator=g, dtype=torch.float64, device="cuda")
             y = torch.empty_like(x)
-            rec = {"kind": kind, "K": K, "lines": plan.shape[0] * plan.shape[1], "dofs": x.numel()}
+            rec = {"kind": kind, "K": K, "lines": nl, "dofs": x.numel()}
             for name, d in (("fc_n", +1), ("f_n", -1)):
                 for _ in range(args.warmup):
-                    plan.debug_transform(2, d, x, y)
+                    plan.debug_transform(axis, d, x, y)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
                 for _ in range(args.steps):
-                    plan.debug_transform(2, d, x, y)
+                    plan.debug_transform(axis, d, x, y)
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / args.steps
                 rec[name] = {"ms": ms, "dofs_per_s": x.numel() / (ms * 1e-3),
                              "GB_per_s": 16 * x.numel() / (ms * 1e-3) / 1e9}
+                if kind == "long":
+                    plan.get_timing()
+                    plan.set_timing(True)
+                    for _ in range(min(args.steps, 5)):
+                        plan.debug_transform(axis, d, x, y)
+                    torch.cuda.synchronize()
+                    rec[name]["kernels_ms"] = {k: v[0] for k, v in plan.get_timing().items()}
+                    plan.set_timing(False)
             rows.append(rec)
             print(f"[bench] transform1d {kind} K={K}: fc_n {rec['fc_n']['ms']:.3f} ms, "
                   f"f_n {rec['f_n']['ms']:.3f} ms ({rec['dofs']} dofs)", file=sys.stderr, flush=True)
+            if kind == "long":
+                for name in ("fc_n", "f_n"):
+                    ks = ", ".join(f"{k} {v:.3f}" for k, v in rec[name]["kernels_ms"].items())
+                    print(f"[bench]   {name} kernels (ms): {ks}", file=sys.stderr, flush=True)
             del plan, x, y
-    fwd = [r["fc_n"]["dofs_per_s"] for r in rows if r["kind"] == "pow2"]
+    fwd = [r["fc_n"]["dofs_per_s"] for r in rows if r["kind"] == "pow2"] or [r["fc_n"]["dofs_per_s"] for r in rows]
     line = {
         "metric": "1D FC_n / F_n transform throughput, n=5 (dofs/s)",
         "value": float(np.exp(np.mean(np.log(fwd)))),
@@ -541,7 +563,7 @@ def run_transform1d(args, torch, fm):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "transform1d_n5", "n": 5, "value": "geometric mean of the forward "
-                   "transform over the power-of-two K"},
+                   "transform over the power-of-two K up to 1024 (all K measured when those are not)"},
         "per_K": rows,
     }
     print(json.dumps(line))
@@ -556,6 +578,8 @@ def main():
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload in the default line")
+    ap.add_argument("--transform-kinds", default="pow2,prime,composite,long",
+                    help="element-count families of the transform1d workload")
     ap.add_argument("--modes", default="fp64,fp32,fp32_refine,fp64_b",
                     help="fp64, fp32, fp32_refine (algorithm (a)), fp64_b (algorithm (b))")
     ap.add_argument("--batch-count", type=int, default=512, help="c5_batch: number of problems")

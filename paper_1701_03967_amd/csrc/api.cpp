@@ -57,8 +57,9 @@ struct fftfem_plan_s {
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
   bool longK = false;        // 1D, K > 1024: the multi-pass transforms of long.hip
   double* Wl[2] = {nullptr, nullptr};  // their work arrays: nrhs x (1 + n/2) x K complex each
-  double* ltw[2] = {nullptr, nullptr}; // their sub-DFT twiddles, lengths K1 and K2
-  int lk1 = 0, lk2 = 0;
+  double* ltw[4] = {nullptr, nullptr, nullptr, nullptr};  // their twiddles: sub-DFTs (K1, K2), low and high
+                                                          // parts of exp(-2 pi i m / K) (1024, K / 1024)
+  int lk1 = 0, lk2 = 0, lgc = 0, lgr = 0;
                              // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
@@ -1023,13 +1024,18 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     p->lk2 = lk - p->lk1;
     const size_t w = (size_t)p->nrhs * (1 + p->nd[0] / 2) * 2 * (size_t)p->K[0];
     for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
+    long_tiles(p->lk1, p->lk2, &p->lgc, &p->lgr);
     const AxisTables& t = p->host[0];
-    for (int i = 0; i < 2 && !rc; ++i) {
-      const int64_t Ki = int64_t(1) << (i == 0 ? p->lk1 : p->lk2), st = p->K[0] / Ki;
-      std::vector<double> tw((size_t)2 * Ki);
-      for (int64_t q = 0; q < Ki; ++q) {
-        tw[2 * q] = t.twf[2 * q * st];
-        tw[2 * q + 1] = t.twf[2 * q * st + 1];
+    // entries q st of the length-K table, q < len: the sub-DFT tables (st =
+    // K / K_i), the low part (st = 1, 1024 entries) and the high part (st =
+    // 1024, K / 1024 entries)
+    const int64_t len[4] = {int64_t(1) << p->lk1, int64_t(1) << p->lk2, 1024, p->K[0] / 1024};
+    const int64_t st[4] = {p->K[0] / len[0], p->K[0] / len[1], 1, 1024};
+    for (int i = 0; i < 4 && !rc; ++i) {
+      std::vector<double> tw((size_t)2 * len[i]);
+      for (int64_t q = 0; q < len[i]; ++q) {
+        tw[2 * q] = t.twf[2 * q * st[i]];
+        tw[2 * q + 1] = t.twf[2 * q * st[i] + 1];
       }
       rc = upload<double>(p, &p->ltw[i], tw);
     }
@@ -1158,6 +1164,13 @@ static int long_transform(fftfem_plan_t p, int mode, const double* in, double* o
   a.mu = tab<double>(p, 0, 4);
   a.tw1 = p->ltw[0];
   a.tw2 = p->ltw[1];
+  a.twlo = p->ltw[2];
+  a.twhi = p->ltw[3];
+  a.lgc = p->lgc;
+  a.lgr = p->lgr;
+  // lines per contraction thread: enough threads to fill the chip (about
+  // 2^18), the rest of the lines in a loop that reuses the cached Q rows
+  a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nlines, nlines * (a.K / 2) >> 18));
   a.react = p->desc.react;
   a.wa = p->Wl[0];
   a.wb = p->Wl[1];

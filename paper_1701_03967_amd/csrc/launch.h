@@ -129,11 +129,15 @@ struct LongArgs {
   const double* mu;       // M: the axis' spectral denominators (divide)
   double react;
   int* bad;               // scatter: when set, bit 2 of bad[l] marks NaN / Inf in line l
+  const double* twlo;     // 1024 complex exp(-2 pi i q / K)
+  const double* twhi;     // K / 1024 complex exp(-2 pi i 1024 q / K)
+  int lgc, lgr;           // log2 of the columns per column tile and of the rows per row tile (long_tiles)
+  int lpt;                // lines per contraction thread
 };
 // step LONG_COLS / LONG_ROWS work on buffer array w (rows: into out), the
 // others on the arrays of a
 hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, double* out, hipStream_t s);
-size_t long_lds_bytes(int K1, int K2);
+void long_tiles(int lk1, int lk2, int* lgc, int* lgr);
 
 // One axis pass of the Dirichlet lifting (extended axis of E = nK + 1 points
 // -> its M = nK - 1 interior rows): out[o, i, ii] = sum_q X_ext[i + 1, q] in[o, q, ii].

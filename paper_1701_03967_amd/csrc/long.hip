@@ -16,8 +16,15 @@
 // along the rows, stored transposed so that frequency k1 + K1 k2 lands at
 // index k1 + K1 k2 (natural order).  The sub-DFTs run in LDS with the
 // Stockham stages of fft.h; the forward and inverse DFTs differ only in the
-// sign of the twiddles.  The per-frequency untangling and the contractions
-// with Q_k are those of the line passes (spectral.h).
+// sign of the twiddles.  A tile holds Gc columns (Gr rows) of about 4096
+// points: the global reads and writes of one tile row are runs of Gc (Gr)
+// complex values, and consecutive tiles share one XCD so that the halves of
+// a 128-byte line read or written by neighbouring tiles meet in one L2.  The
+// twiddle exp(-2 pi i m / K) is the product of two 1024-entry tables (high
+// and low ten bits of m), which stay cached.  The per-frequency untangling
+// and the contractions with Q_k are those of the line passes (spectral.h);
+// a contraction thread takes one frequency pair of several lines, so the Q
+// rows it reads are fetched from HBM once for all of them.
 #include "device_common.h"
 #include "fft.h"
 #include "launch.h"
@@ -28,7 +35,10 @@ namespace fftfem {
 extern __shared__ double2 fftfem_long_lds[];
 
 constexpr int kLongThreads = 256;
-constexpr int kLongG = 4;  // columns (rows) per four-step tile: 4 x 1025 x 16 B = 66 KB of LDS
+constexpr int kLongTilePts = 4096;  // points per four-step tile (one chunk of the Stockham stages)
+constexpr int kLongGmin = 4;        // at least 4 columns (rows) per tile: 4 x 1025 x 16 B = 66 KB of LDS
+constexpr int kLongTwBits = 10;     // low bits of the twiddle index (table of 1024)
+static_assert(kLongTilePts == kLongThreads * 16, "a tile is one chunk of the Stockham stages");
 
 using CD = C2<double>;
 
@@ -71,58 +81,58 @@ __global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
   if ((n - 1) & 1) setc<false>(Z + P * (size_t)K, q, 1, 0.0);
 }
 
-// Four-step DFT, first half: kLongG adjacent columns (i2) of one buffer,
+// Four-step DFT, first half: 2^lgc adjacent columns (i2) of one buffer,
 // length-K1 DFTs over i1, then the twiddles exp(-+2 pi i i2 k1 / K); in place.
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, double* w) {
-  constexpr int G = kLongG;
-  const int K1 = a.K1, K2 = a.K2, K = a.K;
-  const int ncb = K2 / G;
-  const int64_t tile = blockIdx.x;
+  const int K1 = a.K1, K2 = a.K2, K = a.K, lg = a.lgc, G = 1 << lg;
+  const int ncb = K2 >> lg;
+  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t buf = tile / ncb;
-  const int c0 = (int)(tile - buf * ncb) * G;
+  const int c0 = (int)(tile - buf * ncb) << lg;
   CD* X = reinterpret_cast<CD*>(w) + buf * (size_t)K;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
   const int ls = K1 + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < G * K1; i += kLongThreads) {
-    const int i1 = i / G, g = i - i1 * G;
+    const int i1 = i >> lg, g = i & (G - 1);
     slot(L + g * ls, i1) = X[(size_t)i1 * K2 + c0 + g];
   }
   __syncthreads();
   fft_all<double, INV, kLongThreads>(L, G, a.lk1, reinterpret_cast<const CD*>(a.tw1), ls, 4);
-  const CD* twf = reinterpret_cast<const CD*>(a.twf);
+  const CD* twlo = reinterpret_cast<const CD*>(a.twlo);
+  const CD* twhi = reinterpret_cast<const CD*>(a.twhi);
   for (int i = tid; i < G * K1; i += kLongThreads) {
-    const int k1 = i / G, g = i - k1 * G;
+    const int k1 = i >> lg, g = i & (G - 1);
     CD v = slot(L + g * ls, k1);
-    const CD tw = twf[((int64_t)(c0 + g) * k1) & (K - 1)];
+    const int m = (c0 + g) * k1;  // < K <= 2^20
+    const CD tw = cmul(twhi[m >> kLongTwBits], twlo[m & ((1 << kLongTwBits) - 1)]);
     X[(size_t)k1 * K2 + c0 + g] = INV ? cmulc(v, tw) : cmul(v, tw);
   }
 }
 
-// Four-step DFT, second half: kLongG adjacent rows (k1) of one buffer of w,
+// Four-step DFT, second half: 2^lgr adjacent rows (k1) of one buffer of w,
 // length-K2 DFTs over i2, stored into the same buffer of out at k1 + K1 k2.
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, const double* w, double* out) {
-  constexpr int G = kLongG;
-  const int K1 = a.K1, K2 = a.K2, K = a.K;
-  const int nrb = K1 / G;
-  const int64_t tile = blockIdx.x;
+  const int K1 = a.K1, K2 = a.K2, K = a.K, lg = a.lgr, G = 1 << lg;
+  const int nrb = K1 >> lg;
+  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t buf = tile / nrb;
-  const int r0 = (int)(tile - buf * nrb) * G;
+  const int r0 = (int)(tile - buf * nrb) << lg;
   const CD* X = reinterpret_cast<const CD*>(w) + buf * (size_t)K;
   CD* Y = reinterpret_cast<CD*>(out) + buf * (size_t)K;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
   const int ls = K2 + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < G * K2; i += kLongThreads) {
-    const int g = i / K2, i2 = i - g * K2;
+    const int g = i >> a.lk2, i2 = i & (K2 - 1);
     slot(L + g * ls, i2) = X[(size_t)(r0 + g) * K2 + i2];
   }
   __syncthreads();
   fft_all<double, INV, kLongThreads>(L, G, a.lk2, reinterpret_cast<const CD*>(a.tw2), ls, 4);
   for (int i = tid; i < G * K2; i += kLongThreads) {
-    const int k2 = i / G, g = i - k2 * G;
+    const int k2 = i >> lg, g = i & (G - 1);
     Y[(size_t)(r0 + g) + (size_t)K1 * k2] = slot(L + g * ls, k2);
   }
 }
@@ -131,13 +141,9 @@ __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, con
 // line l: untangled spectra of wb -> coefficients (y, s~) in the spectral
 // order of the line (k = 0 block of n - 1, then n per k).
 template <int NORD>
-__global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArgs a) {
+__device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_t l, int kap) {
   constexpr int n = NORD, NC = NORD > 1 ? NORD - 1 : 1;
   const int K = a.K, kh = K >> 1;
-  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
-  if (t >= a.nlines * kh) return;
-  const int64_t l = t / kh;
-  const int kap = (int)(t - l * kh);
   const int ka = kap, kb = kap == 0 ? kh : K - kap;
   const CD* B = long_buf(a.wb, l, 0, 1 + NORD / 2, K);
   const CD* twm = reinterpret_cast<const CD*>(a.twm);
@@ -171,16 +177,24 @@ __global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArg
   }
 }
 
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArgs a) {
+  const int kh = a.K >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
+  if (t >= ngrp * kh) return;
+  const int64_t grp = t / kh;
+  const int kap = (int)(t - grp * kh);
+  const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
+  for (int64_t l = grp * a.lpt; l < lend; ++l)
+    long_contract_fwd_line<NORD>(a, l, kap);
+}
 // The inverse: coefficients of frequencies kap and K - kap -> channel
 // spectra with the Hermitian pre-twiddles -> slots of the buffers of wa.
 template <int NORD>
-__global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArgs a) {
+__device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_t l, int kap) {
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NC = NORD > 1 ? NORD - 1 : 1;
   const int K = a.K, kh = K >> 1;
-  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
-  if (t >= a.nlines * kh) return;
-  const int64_t l = t / kh;
-  const int kap = (int)(t - l * kh);
   const int ka = kap, kb = kap == 0 ? kh : K - kap;
   const double* rs = a.in + l * a.M;
   const int ra = ka == 0 ? n - 1 : n;
@@ -246,6 +260,19 @@ __global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArg
       }
     }
   }
+}
+
+template <int NORD>
+__global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArgs a) {
+  const int kh = a.K >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
+  const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
+  if (t >= ngrp * kh) return;
+  const int64_t grp = t / kh;
+  const int kap = (int)(t - grp * kh);
+  const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
+  for (int64_t l = grp * a.lpt; l < lend; ++l)
+    long_contract_inv_line<NORD>(a, l, kap);
 }
 
 // Element jp of line l from the inverse-transformed buffers of wb: node
@@ -316,11 +343,11 @@ static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((long_gather_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_FWD:
-      if ((e = grid_launch_check(a.nlines * (a.K / 2), &nb))) return e;
+      if ((e = grid_launch_check((a.nlines + a.lpt - 1) / a.lpt * (a.K / 2), &nb))) return e;
       hipLaunchKernelGGL((long_contract_fwd_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_INV:
-      if ((e = grid_launch_check(a.nlines * (a.K / 2), &nb))) return e;
+      if ((e = grid_launch_check((a.nlines + a.lpt - 1) / a.lpt * (a.K / 2), &nb))) return e;
       hipLaunchKernelGGL((long_contract_inv_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_SCATTER:
@@ -333,19 +360,33 @@ static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t long_lds_bytes(int K1, int K2) {
-  const int m = K1 > K2 ? K1 : K2;
-  return (size_t)kLongG * (m + 1) * sizeof(CD);
+void long_tiles(int lk1, int lk2, int* lgc, int* lgr) {
+  // log2 of the columns (rows) per tile: about kLongTilePts points, at least
+  // kLongGmin, at most the other dimension
+  auto pick = [](int lk, int lother) {
+    int lg = 0;
+    while ((1 << lg) < kLongGmin || ((1 << (lg + 1)) << lk) <= kLongTilePts) ++lg;
+    return lg < lother ? lg : lother;
+  };
+  *lgc = pick(lk1, lk2);
+  *lgr = pick(lk2, lk1);
 }
 
+static size_t tile_lds_bytes(int K, int lg) { return (size_t)((K + 1) << lg) * sizeof(CD); }
+
 hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, double* out, hipStream_t s) {
-  if (a.K != a.K1 * a.K2 || a.K1 % kLongG || a.K2 % kLongG || a.K % kLongThreads || a.nlines < 1)
+  if (a.K != a.K1 * a.K2 || a.K1 != 1 << a.lk1 || a.K2 != 1 << a.lk2 || a.K % kLongThreads ||
+      a.K > (1 << (2 * kLongTwBits)) || a.nlines < 1 || a.lpt < 1)
+    return hipErrorInvalidValue;
+  // a tile is one chunk of the Stockham stages (whole buffers, in place)
+  if (a.lgc < 0 || a.lgc > a.lk2 || a.lgr < 0 || a.lgr > a.lk1 || (a.K1 << a.lgc) > kLongTilePts ||
+      (a.K2 << a.lgr) > kLongTilePts)
     return hipErrorInvalidValue;
   const int NB = 1 + n / 2;
   if (step == LONG_COLS || step == LONG_ROWS) {
-    const int64_t tiles = a.nlines * NB * (int64_t)((step == LONG_COLS ? a.K2 : a.K1) / kLongG);
+    const int64_t tiles = a.nlines * NB * (int64_t)(step == LONG_COLS ? a.K2 >> a.lgc : a.K1 >> a.lgr);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = long_lds_bytes(a.K1, a.K2);
+    const size_t lds = step == LONG_COLS ? tile_lds_bytes(a.K1, a.lgc) : tile_lds_bytes(a.K2, a.lgr);
     if (step == LONG_COLS) {
       auto fn = inv ? long_cols_kernel<true> : long_cols_kernel<false>;
       (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
