@@ -486,7 +486,11 @@ def run_heat(args, torch, fm):
 
 TRANSFORM_K = {"pow2": (32, 64, 128, 256, 512, 1024), "prime": (31, 61, 127, 257, 509, 1021),
                "composite": (48, 96, 200, 384, 600, 1000),
-               "long": (1 << 11, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20)}
+               "long": (1 << 11, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20),
+               # one prime and one composite per octave up to 2^20 (the composites drawn once at
+               # random, fixed here)
+               "long_prime": (1031, 2053, 4099, 8209, 16411, 32771, 65537, 131101, 262147, 524309, 1048573),
+               "long_composite": (1662, 2308, 5481, 11099, 32551, 60695, 89354, 221294, 319564, 543195)}
 
 
 def run_transform1d(args, torch, fm):
@@ -494,8 +498,9 @@ def run_transform1d(args, torch, fm):
     contiguous axis of a 3D array of about 2^26 dofs (the lines are the other
     two axes), for element counts that are powers of two, primes and
     composites (the latter two through chirp-z DFTs); float64.  Long lines
-    (K = 2^11 .. 2^20, "long"): one-axis plans whose right-hand sides are the
-    lines, through the multi-pass four-step transforms, with the mean time of
+    (1024 < K <= 2^20: powers of two, primes and composites): one-axis plans
+    whose right-hand sides are the lines, through the multi-pass four-step
+    transforms (Bluestein's for K not a power of two), with the mean time of
     each of their kernels.  Per K: the mean time of one transform of all
     lines, dofs/s and GB/s (one read and one write of 8 bytes per dof)."""
     n = 5
@@ -505,7 +510,8 @@ def run_transform1d(args, torch, fm):
         for K in TRANSFORM_K[kind]:
             M = n * K - 1
             lines = max(1, (1 << 26) // M)
-            if kind == "long":
+            long_line = kind.startswith("long")
+            if long_line:
                 plan = fm.Plan((K,), n, (1.0,), 0.0, nrhs=lines)
                 axis, nl = 0, lines
             else:
@@ -513,7 +519,7 @@ def run_transform1d(args, torch, fm):
                 k1 = max(2, min(1024, int(round(lines / (n * k0 - 1) / n))))
                 plan = fm.Plan((k0, k1, K), n, (1.0, 1.0, 1.0), 0.0)
                 axis, nl = 2, plan.shape[0] * plan.shape[1]
-            shape = (lines, M) if kind == "long" else plan.shape
+            shape = (lines, M) if long_line else plan.shape
             g = torch.Generator(device="cuda")
             g.manual_seed(K)
             x = torch.randn(shape, generator=g, dtype=torch.float64, device="cuda")
@@ -532,7 +538,7 @@ def run_transform1d(args, torch, fm):
                 ms = e0.elapsed_time(e1) / args.steps
                 rec[name] = {"ms": ms, "dofs_per_s": x.numel() / (ms * 1e-3),
                              "GB_per_s": 16 * x.numel() / (ms * 1e-3) / 1e9}
-                if kind == "long":
+                if long_line:
                     plan.get_timing()
                     plan.set_timing(True)
                     for _ in range(min(args.steps, 5)):
@@ -543,7 +549,7 @@ def run_transform1d(args, torch, fm):
             rows.append(rec)
             print(f"[bench] transform1d {kind} K={K}: fc_n {rec['fc_n']['ms']:.3f} ms, "
                   f"f_n {rec['f_n']['ms']:.3f} ms ({rec['dofs']} dofs)", file=sys.stderr, flush=True)
-            if kind == "long":
+            if long_line:
                 for name in ("fc_n", "f_n"):
                     ks = ", ".join(f"{k} {v:.3f}" for k, v in rec[name]["kernels_ms"].items())
                     print(f"[bench]   {name} kernels (ms): {ks}", file=sys.stderr, flush=True)
@@ -578,7 +584,7 @@ def main():
     ap.add_argument("--also", default="c4_3d_n9_k64", help="second workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload in the default line")
-    ap.add_argument("--transform-kinds", default="pow2,prime,composite,long",
+    ap.add_argument("--transform-kinds", default="pow2,prime,composite,long,long_prime,long_composite",
                     help="element-count families of the transform1d workload")
     ap.add_argument("--modes", default="fp64,fp32,fp32_refine,fp64_b",
                     help="fp64, fp32, fp32_refine (algorithm (a)), fp64_b (algorithm (b))")

@@ -60,6 +60,7 @@ struct fftfem_plan_s {
   double* ltw[4] = {nullptr, nullptr, nullptr, nullptr};  // their twiddles: sub-DFTs (K1, K2), low and high
                                                           // parts of exp(-2 pi i m / K) (1024, K / 1024)
   int lk1 = 0, lk2 = 0, lgc = 0, lgr = 0;
+  int64_t lD = 0;            // their DFT length: K, or Bluestein's L
                              // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
@@ -876,12 +877,12 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     if (d.n_axis[i] > kMaxLineOrder) return FFTFEM_ENOTIMPL;
   const bool algb = (d.flags & FFTFEM_ALGORITHM_B) != 0;
   // a line-kernel tile holds at most kLineTasks element tasks; longer lines
-  // take the multi-pass transforms (one axis, float64, K a power of two up
-  // to kLongMaxK, algorithm (a), not in batches)
+  // take the multi-pass transforms (one axis, float64, K up to kLongMaxK,
+  // algorithm (a), not in batches)
   bool longK = false;
   for (int i = 0; i < d.N; ++i)
     if (d.K[i] > kLineTasks) {
-      if (d.N == 1 && is_pow2(d.K[0]) && d.K[0] <= kLongMaxK && d.precision == FFTFEM_FP64 && !algb && !cache)
+      if (d.N == 1 && d.K[0] <= kLongMaxK && d.precision == FFTFEM_FP64 && !algb && !cache)
         longK = true;
       else
         return FFTFEM_ENOTIMPL;
@@ -1017,25 +1018,28 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
   if (!rc && p->longK) {
-    // work arrays and the sub-DFT twiddles (every (K/K_i)-th entry of the
-    // length-K table)
-    const int lk = ilog2(p->K[0]);
+    // the DFT length D (K, or Bluestein's L), work arrays of D slots per
+    // buffer, and the twiddles of the four-step passes: every (D/K_i)-th
+    // entry of the length-D table for the sub-DFTs, its first 1024 entries
+    // and every 1024th for the products
+    const AxisTables& t = p->host[0];
+    const bool pow2 = is_pow2(p->K[0]);
+    const int64_t D = pow2 ? p->K[0] : t.L;
+    const std::vector<double>& twD = pow2 ? t.twf : t.twl;
+    const int lk = ilog2(D);
     p->lk1 = lk / 2;
     p->lk2 = lk - p->lk1;
-    const size_t w = (size_t)p->nrhs * (1 + p->nd[0] / 2) * 2 * (size_t)p->K[0];
-    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
+    p->lD = D;
     long_tiles(p->lk1, p->lk2, &p->lgc, &p->lgr);
-    const AxisTables& t = p->host[0];
-    // entries q st of the length-K table, q < len: the sub-DFT tables (st =
-    // K / K_i), the low part (st = 1, 1024 entries) and the high part (st =
-    // 1024, K / 1024 entries)
-    const int64_t len[4] = {int64_t(1) << p->lk1, int64_t(1) << p->lk2, 1024, p->K[0] / 1024};
-    const int64_t st[4] = {p->K[0] / len[0], p->K[0] / len[1], 1, 1024};
+    const size_t w = (size_t)p->nrhs * (1 + p->nd[0] / 2) * 2 * (size_t)D;
+    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
+    const int64_t len[4] = {int64_t(1) << p->lk1, int64_t(1) << p->lk2, 1024, D / 1024};
+    const int64_t st[4] = {D / len[0], D / len[1], 1, 1024};
     for (int i = 0; i < 4 && !rc; ++i) {
       std::vector<double> tw((size_t)2 * len[i]);
       for (int64_t q = 0; q < len[i]; ++q) {
-        tw[2 * q] = t.twf[2 * q * st[i]];
-        tw[2 * q + 1] = t.twf[2 * q * st[i] + 1];
+        tw[2 * q] = twD[2 * q * st[i]];
+        tw[2 * q + 1] = twD[2 * q * st[i] + 1];
       }
       rc = upload<double>(p, &p->ltw[i], tw);
     }
@@ -1145,12 +1149,16 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
 // The FC_n transform (FWD: lines -> spectral coefficients), its inverse
 // (INV) or both with the division by react + the axis' denominators in
 // between (MID: the 1D solve) of nlines consecutive lines of a long-line
-// plan, by the multi-pass kernels of long.hip.
+// plan, by the multi-pass kernels of long.hip.  The K-point DFTs of the
+// channel buffers: K a power of two, a column and a row pass (wa -> wb);
+// otherwise Bluestein's four passes (wa -> wb -> wa) with the chirp factors
+// of the direction (conjugated for the inverse DFT).
 static int long_transform(fftfem_plan_t p, int mode, const double* in, double* out, int64_t nlines,
                           hipStream_t s, int* bad = nullptr) {
   LongArgs a{};
   a.bad = bad;
   a.K = (int)p->K[0];
+  a.ls = (int)p->lD;
   a.lk1 = p->lk1;
   a.lk2 = p->lk2;
   a.K1 = 1 << p->lk1;
@@ -1158,10 +1166,11 @@ static int long_transform(fftfem_plan_t p, int mode, const double* in, double* o
   a.M = p->M[0];
   a.nlines = nlines;
   a.Q = tab<double>(p, 0, 0);
-  a.twf = tab<double>(p, 0, 1);
   a.twm = tab<double>(p, 0, 2);
   a.twd = tab<double>(p, 0, 3);
   a.mu = tab<double>(p, 0, 4);
+  a.chirp = tab<double>(p, 0, 5);
+  a.bhat = tab<double>(p, 0, 6);
   a.tw1 = p->ltw[0];
   a.tw2 = p->ltw[1];
   a.twlo = p->ltw[2];
@@ -1170,37 +1179,58 @@ static int long_transform(fftfem_plan_t p, int mode, const double* in, double* o
   a.lgr = p->lgr;
   // lines per contraction thread: enough threads to fill the chip (about
   // 2^18), the rest of the lines in a loop that reuses the cached Q rows
-  a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nlines, nlines * (a.K / 2) >> 18));
+  a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nlines, nlines * ((a.K + 1) / 2) >> 18));
   a.react = p->desc.react;
-  a.wa = p->Wl[0];
-  a.wb = p->Wl[1];
+  double* const W0 = p->Wl[0];
+  double* const W1 = p->Wl[1];
+  const bool pow2 = is_pow2(p->K[0]);
   const int n = p->nd[0];
   int rc = FFTFEM_OK;
-  auto step = [&](int st, bool inv, const char* name) {
+  auto step = [&](int st, bool inv, double* w, double* o, const char* name) {
     if (rc) return;
     Timed tm(p, s, name);
-    rc = from_hip(launch_long(n, st, inv, a, a.wa, a.wb, s));
+    rc = from_hip(launch_long(n, st, inv, a, w, o, s));
+  };
+  // DFTs of the buffers of W0 (forward or inverse); returns the array that
+  // holds the spectra
+  auto dft = [&](bool inv) -> double* {
+    if (pow2) {
+      step(LONG_COLS, inv, W0, nullptr, inv ? "lcols64i" : "lcols64");
+      step(LONG_ROWS, inv, W0, W1, inv ? "lrows64i" : "lrows64");
+      return W1;
+    }
+    a.pre = inv ? 2 : 1;
+    step(LONG_COLS, false, W0, nullptr, inv ? "lbcols64i" : "lbcols64");
+    a.pre = 0;
+    a.post = inv ? 2 : 1;
+    step(LONG_ROWS, false, W0, W1, inv ? "lbrows64i" : "lbrows64");
+    a.post = 0;
+    step(LONG_COLS, true, W1, nullptr, inv ? "lbcols64ic" : "lbcols64c");
+    a.post = inv ? 4 : 3;
+    step(LONG_ROWS, true, W1, W0, inv ? "lbrows64ic" : "lbrows64c");
+    a.post = 0;
+    return W0;
   };
   if (mode == FWD || mode == MID) {
     a.in = in;
     a.out = out;
-    step(LONG_GATHER, false, "lgather64");
-    step(LONG_COLS, false, "lcols64");
-    step(LONG_ROWS, false, "lrows64");
-    step(LONG_CONTRACT_FWD, false, "lcfwd64");
+    a.wa = W0;
+    step(LONG_GATHER, false, nullptr, nullptr, "lgather64");
+    a.wb = dft(false);
+    step(LONG_CONTRACT_FWD, false, nullptr, nullptr, "lcfwd64");
   }
   if (mode == MID) {
     a.in = out;
     a.out = out;
-    step(LONG_DIVIDE, false, "ldiv64");
+    step(LONG_DIVIDE, false, nullptr, nullptr, "ldiv64");
   }
   if (mode == INV || mode == MID) {
     a.in = mode == INV ? in : out;
     a.out = out;
-    step(LONG_CONTRACT_INV, false, "lcinv64");
-    step(LONG_COLS, true, "lcols64i");
-    step(LONG_ROWS, true, "lrows64i");
-    step(LONG_SCATTER, false, "lscatter64");
+    a.wa = W0;
+    step(LONG_CONTRACT_INV, false, nullptr, nullptr, "lcinv64");
+    a.wb = dft(true);
+    step(LONG_SCATTER, false, nullptr, nullptr, "lscatter64");
   }
   return rc;
 }

@@ -117,22 +117,26 @@ struct LongArgs {
   const double* in;       // lines (gather, inverse contraction, divide)
   double* out;            // lines (forward contraction, scatter, divide)
   double* wa;             // gather / inverse-contraction output, column-pass buffers
-  double* wb;             // row-pass output (natural order)
-  int K, K1, K2, lk1, lk2;
+  double* wb;             // buffers read by the forward contraction and the scatter
+  int K;                  // elements per line
+  int ls;                 // slots per work buffer: the DFT length D = K1 K2
+  int K1, K2, lk1, lk2;   // D = K1 K2 = 2^(lk1 + lk2): K, or Bluestein's L >= 2K - 1
   int64_t M, nlines;
   const double* Q;        // (c n + l) K + k, float64
-  const double* twf;      // K complex exp(-2 pi i q / K)
   const double* twm;      // K complex exp(-i pi k / (2K))
   const double* twd;      // K complex exp(-i pi k / K)
   const double* tw1;      // K1 complex exp(-2 pi i q / K1)
   const double* tw2;      // K2 complex exp(-2 pi i q / K2)
+  const double* twlo;     // 1024 complex exp(-2 pi i q / D)
+  const double* twhi;     // D / 1024 complex exp(-2 pi i 1024 q / D)
+  const double* chirp;    // K not a power of two: K complex exp(-i pi j^2 / K)
+  const double* bhat;     // and L complex: the spectrum of conj(chirp) (zero-padded, cyclic) / L
   const double* mu;       // M: the axis' spectral denominators (divide)
   double react;
   int* bad;               // scatter: when set, bit 2 of bad[l] marks NaN / Inf in line l
-  const double* twlo;     // 1024 complex exp(-2 pi i q / K)
-  const double* twhi;     // K / 1024 complex exp(-2 pi i 1024 q / K)
   int lgc, lgr;           // log2 of the columns per column tile and of the rows per row tile (long_tiles)
   int lpt;                // lines per contraction thread
+  int pre, post;          // Bluestein factors of the column loads and the row stores (long.hip)
 };
 // step LONG_COLS / LONG_ROWS work on buffer array w (rows: into out), the
 // others on the arrays of a

@@ -1,30 +1,40 @@
 // Transforms of long lines (gfx950): the direct FC_n transform and its
 // inverse (Sect. 3, Theorem 2) for one-dimensional plans whose element count
-// K exceeds what one LDS tile holds (K = K1 K2 a power of two up to 2^20,
-// K1, K2 <= 1024).  The steps of a line pass run as separate passes over
-// global work arrays of NB = 1 + floor(n/2) complex buffers of K slots per
-// line, packed as in the line passes (the node channel's odd extension of
-// length 2K, then the bubble channel pairs in the reordering that makes
-// their DCT-II a K-point DFT):
+// K (1024 < K <= 2^20) exceeds what one LDS tile holds.  The steps of a line
+// pass run as separate passes over global work arrays of NB = 1 + floor(n/2)
+// complex buffers per line (ls slots each), packed as in the line passes (the
+// node channel's odd extension of length 2K, then the bubble channel pairs in
+// the reordering that makes their DCT-II a K-point DFT):
 //
-//   forward:  gather -> columns -> rows -> contraction
-//   inverse:  contraction -> columns -> rows -> scatter
+//   forward:  gather -> K-point DFT -> contraction
+//   inverse:  contraction -> inverse K-point DFT -> scatter
 //
-// "columns" and "rows" are the two halves of a four-step DFT of length K:
+// The K-point DFT of every buffer is a four-step DFT of a power-of-two
+// length D = K1 K2 (K1, K2 <= 2048), as two passes, "columns" and "rows":
 // the buffer viewed as K1 x K2 (index i1 K2 + i2), length-K1 DFTs down the
-// columns with the twiddles exp(-+2 pi i i2 k1 / K), then length-K2 DFTs
+// columns with the twiddles exp(-+2 pi i i2 k1 / D), then length-K2 DFTs
 // along the rows, stored transposed so that frequency k1 + K1 k2 lands at
-// index k1 + K1 k2 (natural order).  The sub-DFTs run in LDS with the
-// Stockham stages of fft.h; the forward and inverse DFTs differ only in the
-// sign of the twiddles.  A tile holds Gc columns (Gr rows) of about 4096
-// points: the global reads and writes of one tile row are runs of Gc (Gr)
-// complex values, and consecutive tiles share one XCD so that the halves of
-// a 128-byte line read or written by neighbouring tiles meet in one L2.  The
-// twiddle exp(-2 pi i m / K) is the product of two 1024-entry tables (high
-// and low ten bits of m), which stay cached.  The per-frequency untangling
-// and the contractions with Q_k are those of the line passes (spectral.h);
-// a contraction thread takes one frequency pair of several lines, so the Q
-// rows it reads are fetched from HBM once for all of them.
+// index k1 + K1 k2 (natural order).  K a power of two: D = K, two passes.
+// Otherwise Bluestein's chirp-z with D = L >= 2K - 1 (as in the line passes):
+// with c_j = exp(-i pi j^2 / K), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}), a
+// cyclic convolution of length L done as a forward and an inverse D-point
+// DFT, four passes: the chirp multiplication and the zero padding fused into
+// the loads of the first column pass, the product with the spectrum of
+// conj(c) (divided by L) into the stores of the first row pass, the final
+// chirp and the truncation to K into the stores of the last row pass
+// (conjugated chirp and spectrum for the inverse DFT).
+//
+// The sub-DFTs run in LDS with the Stockham stages of fft.h; forward and
+// inverse DFTs differ only in the sign of the twiddles.  A tile holds Gc
+// columns (Gr rows) of about 4096 points: the global reads and writes of one
+// tile row are runs of Gc (Gr) complex values, and consecutive tiles share
+// one XCD so that the halves of a 128-byte line read or written by
+// neighbouring tiles meet in one L2.  The twiddle exp(-2 pi i m / D) is the
+// product of two cached tables (high bits and low ten bits of m).  The
+// per-frequency untangling and the contractions with Q_k are those of the
+// line passes (spectral.h); a contraction thread takes one frequency pair of
+// several lines, so the Q rows it reads are fetched from HBM once for all of
+// them.
 #include "device_common.h"
 #include "fft.h"
 #include "launch.h"
@@ -35,23 +45,22 @@ namespace fftfem {
 extern __shared__ double2 fftfem_long_lds[];
 
 constexpr int kLongThreads = 256;
-constexpr int kLongTilePts = 4096;  // points per four-step tile (one chunk of the Stockham stages)
-constexpr int kLongGmin = 4;        // at least 4 columns (rows) per tile: 4 x 1025 x 16 B = 66 KB of LDS
+constexpr int kLongLgTilePts = 12;  // 4096 points per four-step tile (one chunk of the Stockham stages)
 constexpr int kLongTwBits = 10;     // low bits of the twiddle index (table of 1024)
-static_assert(kLongTilePts == kLongThreads * 16, "a tile is one chunk of the Stockham stages");
+static_assert((1 << kLongLgTilePts) == kLongThreads * 16, "a tile is one chunk of the Stockham stages");
 
 using CD = C2<double>;
 
-__device__ __forceinline__ CD* long_buf(double* w, int64_t line, int b, int NB, int K) {
-  return reinterpret_cast<CD*>(w) + ((size_t)line * NB + b) * (size_t)K;
+__device__ __forceinline__ CD* long_buf(double* w, int64_t line, int b, int NB, int ls) {
+  return reinterpret_cast<CD*>(w) + ((size_t)line * NB + b) * (size_t)ls;
 }
 
 // Element jp of line l: node jp + 1 and the bubble channels into the work
-// buffers (as the gather of the line passes).
+// buffers of wa (as the gather of the line passes).
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NB = 1 + P;
-  const int K = a.K;
+  const int K = a.K, ls = a.ls;
   const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
   if (t >= a.nlines * K) return;
   const int64_t l = t / K;
@@ -67,7 +76,7 @@ __global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
   for (int m = 1; m <= ne; ++m) hv[m] = sg * ((2 * m == n) ? y[m - 1] : y[m - 1] + y[n - m - 1]);
 #pragma unroll
   for (int m = 1; m <= no; ++m) hv[ne + m] = y[m - 1] - y[n - m - 1];
-  CD* Z = long_buf(a.wa, l, 0, NB, K);
+  CD* Z = long_buf(a.wa, l, 0, NB, ls);
   if (jp < K - 1) {
     const int j = jp + 1, t2 = 2 * K - j;
     setc<false>(Z, j >> 1, j & 1, hv[0]);
@@ -77,26 +86,38 @@ __global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
   }
   const int q = (jp & 1) ? K - 1 - (jp >> 1) : (jp >> 1);
 #pragma unroll
-  for (int b = 0; b < n - 1; ++b) setc<false>(Z + (1 + b / 2) * (size_t)K, q, b & 1, hv[1 + b]);
-  if ((n - 1) & 1) setc<false>(Z + P * (size_t)K, q, 1, 0.0);
+  for (int b = 0; b < n - 1; ++b) setc<false>(Z + (1 + b / 2) * (size_t)ls, q, b & 1, hv[1 + b]);
+  if ((n - 1) & 1) setc<false>(Z + P * (size_t)ls, q, 1, 0.0);
 }
 
 // Four-step DFT, first half: 2^lgc adjacent columns (i2) of one buffer,
-// length-K1 DFTs over i1, then the twiddles exp(-+2 pi i i2 k1 / K); in place.
+// length-K1 DFTs over i1, then the twiddles exp(-+2 pi i i2 k1 / D); in
+// place.  pre = 1 (2): the input is x_i c_i (x_i conj(c_i)) for i < K and 0
+// beyond (the first pass of Bluestein's convolution).
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, double* w) {
-  const int K1 = a.K1, K2 = a.K2, K = a.K, lg = a.lgc, G = 1 << lg;
+  const int K1 = a.K1, K2 = a.K2, lg = a.lgc, G = 1 << lg, K = a.K, pre = a.pre;
   const int ncb = K2 >> lg;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t buf = tile / ncb;
   const int c0 = (int)(tile - buf * ncb) << lg;
-  CD* X = reinterpret_cast<CD*>(w) + buf * (size_t)K;
+  CD* X = reinterpret_cast<CD*>(w) + buf * (size_t)a.ls;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
+  const CD* chirp = reinterpret_cast<const CD*>(a.chirp);
   const int ls = K1 + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < G * K1; i += kLongThreads) {
     const int i1 = i >> lg, g = i & (G - 1);
-    slot(L + g * ls, i1) = X[(size_t)i1 * K2 + c0 + g];
+    const int idx = i1 * K2 + c0 + g;
+    CD v;
+    if (pre == 0) {
+      v = X[idx];
+    } else if (idx < K) {
+      v = pre == 1 ? cmul(X[idx], chirp[idx]) : cmulc(X[idx], chirp[idx]);
+    } else {
+      v = CD{0.0, 0.0};
+    }
+    slot(L + g * ls, i1) = v;
   }
   __syncthreads();
   fft_all<double, INV, kLongThreads>(L, G, a.lk1, reinterpret_cast<const CD*>(a.tw1), ls, 4);
@@ -105,24 +126,29 @@ __global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, dou
   for (int i = tid; i < G * K1; i += kLongThreads) {
     const int k1 = i >> lg, g = i & (G - 1);
     CD v = slot(L + g * ls, k1);
-    const int m = (c0 + g) * k1;  // < K <= 2^20
+    const int m = (c0 + g) * k1;  // < D <= 2^21
     const CD tw = cmul(twhi[m >> kLongTwBits], twlo[m & ((1 << kLongTwBits) - 1)]);
     X[(size_t)k1 * K2 + c0 + g] = INV ? cmulc(v, tw) : cmul(v, tw);
   }
 }
 
 // Four-step DFT, second half: 2^lgr adjacent rows (k1) of one buffer of w,
-// length-K2 DFTs over i2, stored into the same buffer of out at k1 + K1 k2.
+// length-K2 DFTs over i2, stored into the same buffer of out at
+// k = k1 + K1 k2.  post = 1 (2): times bhat_k (conj(bhat_k)), the spectrum of
+// Bluestein's kernel; post = 3 (4): times c_k (conj(c_k)) and only k < K
+// stored (the end of Bluestein's convolution).
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, const double* w, double* out) {
-  const int K1 = a.K1, K2 = a.K2, K = a.K, lg = a.lgr, G = 1 << lg;
+  const int K1 = a.K1, K2 = a.K2, lg = a.lgr, G = 1 << lg, K = a.K, post = a.post;
   const int nrb = K1 >> lg;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t buf = tile / nrb;
   const int r0 = (int)(tile - buf * nrb) << lg;
-  const CD* X = reinterpret_cast<const CD*>(w) + buf * (size_t)K;
-  CD* Y = reinterpret_cast<CD*>(out) + buf * (size_t)K;
+  const CD* X = reinterpret_cast<const CD*>(w) + buf * (size_t)a.ls;
+  CD* Y = reinterpret_cast<CD*>(out) + buf * (size_t)a.ls;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
+  const CD* chirp = reinterpret_cast<const CD*>(a.chirp);
+  const CD* bhat = reinterpret_cast<const CD*>(a.bhat);
   const int ls = K2 + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < G * K2; i += kLongThreads) {
@@ -133,39 +159,54 @@ __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, con
   fft_all<double, INV, kLongThreads>(L, G, a.lk2, reinterpret_cast<const CD*>(a.tw2), ls, 4);
   for (int i = tid; i < G * K2; i += kLongThreads) {
     const int k2 = i >> lg, g = i & (G - 1);
-    Y[(size_t)(r0 + g) + (size_t)K1 * k2] = slot(L + g * ls, k2);
+    const int k = r0 + g + K1 * k2;
+    CD v = slot(L + g * ls, k2);
+    if (post == 1) v = cmul(v, bhat[k]);
+    if (post == 2) v = cmulc(v, bhat[k]);
+    if (post >= 3) {
+      if (k >= K) continue;
+      v = post == 3 ? cmul(v, chirp[k]) : cmulc(v, chirp[k]);
+    }
+    Y[k] = v;
   }
 }
 
-// Frequencies kap and K - kap (kap = 0: the bubble-only block and K/2) of
-// line l: untangled spectra of wb -> coefficients (y, s~) in the spectral
-// order of the line (k = 0 block of n - 1, then n per k).
+// Frequency pair tasks of a line: kap = 0 .. ceil(K/2) - 1 takes the
+// frequencies kap and K - kap; kap = 0 the bubble-only block and, for even
+// K, frequency K/2.
+__host__ __device__ inline int long_pair_tasks(int K) { return (K + 1) >> 1; }
+
+// Frequencies of task kap of line l: untangled spectra of the buffers of wb
+// -> coefficients (y, s~) in the spectral order of the line (k = 0 block of
+// n - 1, then n per k).
 template <int NORD>
 __device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_t l, int kap) {
   constexpr int n = NORD, NC = NORD > 1 ? NORD - 1 : 1;
-  const int K = a.K, kh = K >> 1;
-  const int ka = kap, kb = kap == 0 ? kh : K - kap;
-  const CD* B = long_buf(a.wb, l, 0, 1 + NORD / 2, K);
+  const int K = a.K, ls = a.ls;
+  const bool keven = (K & 1) == 0;
+  const bool hasb = kap != 0 || keven;
+  const int ka = kap, kb = kap == 0 ? (K >> 1) : K - kap;
+  const CD* B = long_buf(a.wb, l, 0, 1 + NORD / 2, ls);
   const CD* twm = reinterpret_cast<const CD*>(a.twm);
   const CD* twd = reinterpret_cast<const CD*>(a.twd);
   double ca[NC], cb[NC], cha[NORD], chb[NORD], wa[NORD], wb[NORD];
   if (kap == 0) {
     if constexpr (NORD > 1) {
-      bubble_post<double, NORD, false>(B, K, 0, 0, twm, ca, cb);
+      bubble_post<double, NORD, false>(B, ls, 0, 0, twm, ca, cb);
 #pragma unroll
       for (int b = 0; b < NORD - 1; ++b) cha[b] = ca[b];
-      bubble_post<double, NORD, false>(B, K, kb, kb, twm, ca, cb);
+      if (keven) bubble_post<double, NORD, false>(B, ls, kb, kb, twm, ca, cb);
     }
     cha[NORD - 1] = 0;
-    channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), ca, ca, chb);
+    if (keven) channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), ca, ca, chb);
   } else {
-    if constexpr (NORD > 1) bubble_post<double, NORD, false>(B, K, ka, kb, twm, ca, cb);
+    if constexpr (NORD > 1) bubble_post<double, NORD, false>(B, ls, ka, kb, twm, ca, cb);
     channel_vec<double, NORD>(nodal_post<double, false>(B, K, ka, twd, false), ca, cb, cha);
     channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), cb, ca, chb);
   }
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
   contract_fwd<double, NORD>(qtab, K, ka, cha, wa);
-  contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
+  if (hasb) contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
   double* rs = a.out + l * a.M;
   const int ra = ka == 0 ? n - 1 : n;
   const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
@@ -173,28 +214,31 @@ __device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_
 #pragma unroll
   for (int c = 0; c < NORD; ++c) {
     if (c < ra) rs[offa + c] = wa[c];
-    rs[offb + c] = wb[c];
+    if (hasb) rs[offb + c] = wb[c];
   }
 }
 
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArgs a) {
-  const int kh = a.K >> 1;
+  const int nt = long_pair_tasks(a.K);
   const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
   const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
-  if (t >= ngrp * kh) return;
-  const int64_t grp = t / kh;
-  const int kap = (int)(t - grp * kh);
+  if (t >= ngrp * nt) return;
+  const int64_t grp = t / nt;
+  const int kap = (int)(t - grp * nt);
   const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
-  for (int64_t l = grp * a.lpt; l < lend; ++l)
-    long_contract_fwd_line<NORD>(a, l, kap);
+  for (int64_t l = grp * a.lpt; l < lend; ++l) long_contract_fwd_line<NORD>(a, l, kap);
 }
-// The inverse: coefficients of frequencies kap and K - kap -> channel
+
+// The inverse: coefficients of the frequencies of task kap -> channel
 // spectra with the Hermitian pre-twiddles -> slots of the buffers of wa.
 template <int NORD>
 __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_t l, int kap) {
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NC = NORD > 1 ? NORD - 1 : 1;
-  const int K = a.K, kh = K >> 1;
+  const int K = a.K, ls = a.ls;
+  const bool keven = (K & 1) == 0;
+  const bool hasb = kap != 0 || keven;
+  const int kh = K >> 1;
   const int ka = kap, kb = kap == 0 ? kh : K - kap;
   const double* rs = a.in + l * a.M;
   const int ra = ka == 0 ? n - 1 : n;
@@ -204,16 +248,21 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
 #pragma unroll
   for (int c = 0; c < NORD; ++c) {
     wa[c] = c < ra ? rs[offa + c] : 0.0;
-    wb[c] = rs[offb + c];
+    wb[c] = hasb ? rs[offb + c] : 0.0;
   }
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
   contract_inv<double, NORD>(qtab, K, ka, wa, h0);
-  contract_inv<double, NORD>(qtab, K, kb, wb, h1);
-  CD* B = long_buf(a.wa, l, 0, 1 + P, K);
+  if (hasb) {
+    contract_inv<double, NORD>(qtab, K, kb, wb, h1);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NORD; ++c) h1[c] = 0.0;
+  }
+  CD* B = long_buf(a.wa, l, 0, 1 + P, ls);
   const CD* twm = reinterpret_cast<const CD*>(a.twm);
   if (kap == 0) {
     write_nodal_zeros<double, false>(B, K);
-    write_nodal_inv<double, false>(B, K, kh, h1[0]);
+    if (keven) write_nodal_inv<double, false>(B, K, kh, h1[0]);
   } else {
     write_nodal_inv<double, false>(B, K, kap, h0[0]);
     write_nodal_inv<double, false>(B, K, K - kap, h1[0]);
@@ -231,10 +280,12 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
       for (int p = 1; p <= P; ++p) {
         const int b0 = 2 * (p - 1), b1 = b0 + 1;
         const bool has1 = b1 < NORD - 1;
-        B[p * (size_t)K + 0] = CD{ya[b0], has1 ? ya[b1] : 0.0};
-        const CD va = herm<double>(yb[b0], yb[b0], kh, twm);
-        const CD vb = has1 ? herm<double>(yb[b1], yb[b1], kh, twm) : CD{0, 0};
-        B[p * (size_t)K + kh] = CD{va.x - vb.y, va.y + vb.x};
+        B[p * (size_t)ls + 0] = CD{ya[b0], has1 ? ya[b1] : 0.0};
+        if (keven) {
+          const CD va = herm<double>(yb[b0], yb[b0], kh, twm);
+          const CD vb = has1 ? herm<double>(yb[b1], yb[b1], kh, twm) : CD{0, 0};
+          B[p * (size_t)ls + kh] = CD{va.x - vb.y, va.y + vb.x};
+        }
       }
     } else {
 #pragma unroll
@@ -253,10 +304,10 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
         const bool has1 = b1 < NORD - 1;
         CD va = herm<double>(ya[b0], yb[b0], kap, twm);
         CD vb = has1 ? herm<double>(ya[b1], yb[b1], kap, twm) : CD{0, 0};
-        B[p * (size_t)K + kap] = CD{va.x - vb.y, va.y + vb.x};
+        B[p * (size_t)ls + kap] = CD{va.x - vb.y, va.y + vb.x};
         va = herm<double>(yb[b0], ya[b0], K - kap, twm);
         vb = has1 ? herm<double>(yb[b1], ya[b1], K - kap, twm) : CD{0, 0};
-        B[p * (size_t)K + (K - kap)] = CD{va.x - vb.y, va.y + vb.x};
+        B[p * (size_t)ls + (K - kap)] = CD{va.x - vb.y, va.y + vb.x};
       }
     }
   }
@@ -264,15 +315,14 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
 
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArgs a) {
-  const int kh = a.K >> 1;
+  const int nt = long_pair_tasks(a.K);
   const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
   const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
-  if (t >= ngrp * kh) return;
-  const int64_t grp = t / kh;
-  const int kap = (int)(t - grp * kh);
+  if (t >= ngrp * nt) return;
+  const int64_t grp = t / nt;
+  const int kap = (int)(t - grp * nt);
   const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
-  for (int64_t l = grp * a.lpt; l < lend; ++l)
-    long_contract_inv_line<NORD>(a, l, kap);
+  for (int64_t l = grp * a.lpt; l < lend; ++l) long_contract_inv_line<NORD>(a, l, kap);
 }
 
 // Element jp of line l from the inverse-transformed buffers of wb: node
@@ -280,12 +330,12 @@ __global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArg
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_scatter_kernel(LongArgs a) {
   constexpr int n = NORD, ne = NORD / 2, P = NORD / 2, NB = 1 + P;
-  const int K = a.K;
+  const int K = a.K, ls = a.ls;
   const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
   if (t >= a.nlines * K) return;
   const int64_t l = t / K;
   const int jp = (int)(t - l * K);
-  const CD* Z = long_buf(a.wb, l, 0, NB, K);
+  const CD* Z = long_buf(a.wb, l, 0, NB, ls);
   const CD* twd = reinterpret_cast<const CD*>(a.twd);
   double hv[NORD];
   hv[n - 1] = jp < K - 1 ? nodal_post<double, false>(Z, K, jp + 1, twd, true) : 0.0;
@@ -294,12 +344,12 @@ __global__ __launch_bounds__(kLongThreads) void long_scatter_kernel(LongArgs a) 
 #pragma unroll
   for (int m = 1; m <= ne; ++m) {
     const int be = m - 1;
-    const double E = sg * reinterpret_cast<const double*>(Z + (1 + be / 2) * (size_t)K + q)[be & 1];
+    const double E = sg * reinterpret_cast<const double*>(Z + (1 + be / 2) * (size_t)ls + q)[be & 1];
     if (2 * m == n) {
       hv[m - 1] = E;
     } else {
       const int bo = ne + m - 1;
-      const double O = reinterpret_cast<const double*>(Z + (1 + bo / 2) * (size_t)K + q)[bo & 1];
+      const double O = reinterpret_cast<const double*>(Z + (1 + bo / 2) * (size_t)ls + q)[bo & 1];
       hv[m - 1] = E + O;
       hv[n - m - 1] = E - O;
     }
@@ -309,11 +359,10 @@ __global__ __launch_bounds__(kLongThreads) void long_scatter_kernel(LongArgs a) 
   for (int m = 0; m < n - 1; ++m) r[m] = hv[m];
   if (jp < K - 1) r[n - 1] = hv[n - 1];
   if (a.bad) {
-    // K is a multiple of the block size: every wave lies in one line
     bool nonfinite = false;
 #pragma unroll
     for (int m = 0; m < n; ++m) nonfinite |= !(hv[m] - hv[m] == 0.0);
-    if (__ballot(nonfinite) != 0 && (threadIdx.x & 63) == 0) atomicOr(a.bad + l, 2);
+    if (nonfinite) atomicOr(a.bad + l, 2);
   }
 }
 
@@ -337,17 +386,18 @@ template <int NORD>
 static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
   unsigned nb = 0;
   hipError_t e;
+  const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
   switch (step) {
     case LONG_GATHER:
       if ((e = grid_launch_check(a.nlines * a.K, &nb))) return e;
       hipLaunchKernelGGL((long_gather_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_FWD:
-      if ((e = grid_launch_check((a.nlines + a.lpt - 1) / a.lpt * (a.K / 2), &nb))) return e;
+      if ((e = grid_launch_check(ngrp * long_pair_tasks(a.K), &nb))) return e;
       hipLaunchKernelGGL((long_contract_fwd_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_INV:
-      if ((e = grid_launch_check((a.nlines + a.lpt - 1) / a.lpt * (a.K / 2), &nb))) return e;
+      if ((e = grid_launch_check(ngrp * long_pair_tasks(a.K), &nb))) return e;
       hipLaunchKernelGGL((long_contract_inv_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_SCATTER:
@@ -361,11 +411,10 @@ static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
 }
 
 void long_tiles(int lk1, int lk2, int* lgc, int* lgr) {
-  // log2 of the columns (rows) per tile: about kLongTilePts points, at least
-  // kLongGmin, at most the other dimension
+  // log2 of the columns (rows) per tile: 4096 points per tile (at least 4
+  // columns of up to 1024 points, 2 of 2048), at most the other dimension
   auto pick = [](int lk, int lother) {
-    int lg = 0;
-    while ((1 << lg) < kLongGmin || ((1 << (lg + 1)) << lk) <= kLongTilePts) ++lg;
+    const int lg = kLongLgTilePts - lk;
     return lg < lother ? lg : lother;
   };
   *lgc = pick(lk1, lk2);
@@ -375,12 +424,19 @@ void long_tiles(int lk1, int lk2, int* lgc, int* lgr) {
 static size_t tile_lds_bytes(int K, int lg) { return (size_t)((K + 1) << lg) * sizeof(CD); }
 
 hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, double* out, hipStream_t s) {
-  if (a.K != a.K1 * a.K2 || a.K1 != 1 << a.lk1 || a.K2 != 1 << a.lk2 || a.K % kLongThreads ||
-      a.K > (1 << (2 * kLongTwBits)) || a.nlines < 1 || a.lpt < 1)
+  const int D = a.K1 * a.K2;
+  const bool pow2 = (a.K & (a.K - 1)) == 0;
+  if (a.K < 2 || a.K > (1 << 20) || a.K1 != 1 << a.lk1 || a.K2 != 1 << a.lk2 || a.lk1 < 1 || a.lk2 < 1 ||
+      a.lk1 > 11 || a.lk2 > 11 || (pow2 ? D != a.K : D < 2 * a.K - 1) || a.ls != D ||
+      D > (1 << (2 * kLongTwBits + 1)) || a.nlines < 1 || a.lpt < 1)
+    return hipErrorInvalidValue;
+  // the Bluestein factors: only for K not a power of two, with their tables
+  if (a.pre < 0 || a.pre > 2 || a.post < 0 || a.post > 4 || (pow2 && (a.pre || a.post)) ||
+      ((a.pre || a.post >= 3) && !a.chirp) || ((a.post == 1 || a.post == 2) && !a.bhat))
     return hipErrorInvalidValue;
   // a tile is one chunk of the Stockham stages (whole buffers, in place)
-  if (a.lgc < 0 || a.lgc > a.lk2 || a.lgr < 0 || a.lgr > a.lk1 || (a.K1 << a.lgc) > kLongTilePts ||
-      (a.K2 << a.lgr) > kLongTilePts)
+  if (a.lgc < 0 || a.lgc > a.lk2 || a.lgr < 0 || a.lgr > a.lk1 || a.lk1 + a.lgc > kLongLgTilePts ||
+      a.lk2 + a.lgr > kLongLgTilePts)
     return hipErrorInvalidValue;
   const int NB = 1 + n / 2;
   if (step == LONG_COLS || step == LONG_ROWS) {

@@ -536,7 +536,9 @@ int build_axis_tables(int n, int64_t K, double diff, double X, AxisTables* t) {
     if (!v) return kESPECTRUM;
   for (double v : t->lam)
     if (!(v > 0) || !std::isfinite(v)) return kESPECTRUM;
-  t->radices = (K & (K - 1)) ? mixed_radices(K) : std::vector<int>();
+  // mixed-radix stages for a line held in one LDS tile (K <= 1024); longer
+  // lines that are not a power of two take Bluestein's tables
+  t->radices = (K & (K - 1)) && K <= 1024 ? mixed_radices(K) : std::vector<int>();
   if ((K & (K - 1)) && t->radices.empty()) {
     // Bluestein tables for a length-K DFT: chirp c_j = exp(-i pi j^2 / K)
     // (argument reduced exactly: j^2 mod 2K), and the spectrum of the

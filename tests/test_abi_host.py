@@ -63,10 +63,10 @@ def _plan_ex(**kw):
     ({"K": (1025, 8)}, -7), ({"n": 12}, -7), ({"K": (4096, 8)}, -7), ({"K": (2048, 8)}, -7),
     ({"flags": 1, "precision": 1}, -7), ({"flags": 1, "precision": 2}, -7),
     ({"n_axis": (2, -1)}, -1), ({"n_axis": (17, 2)}, -1), ({"n_axis": (2, 10)}, -7), ({"n": 12, "n_axis": (3, 12)}, -7),
-    # one axis beyond one tile: powers of two up to 2^20, float64, algorithm (a) only
-    ({"N": 1, "K": (1025,)}, -7), ({"N": 1, "K": (3000,)}, -7), ({"N": 1, "K": (1 << 21,)}, -7),
-    ({"N": 1, "K": (2048,), "precision": 1}, -7), ({"N": 1, "K": (2048,), "precision": 2}, -7),
-    ({"N": 1, "K": (2048,), "flags": 1}, -7),
+    # one axis beyond one tile: up to 2^20 elements, float64, algorithm (a) only
+    ({"N": 1, "K": (1 << 21,)}, -7), ({"N": 1, "K": ((1 << 20) + 1,)}, -7),
+    ({"N": 1, "K": (2048,), "precision": 1}, -7), ({"N": 1, "K": (3001,), "precision": 2}, -7),
+    ({"N": 1, "K": (2048,), "flags": 1}, -7), ({"N": 1, "K": (1025,), "flags": 1}, -7),
 ])
 def test_invalid_arguments_rejected_on_host(kw, code):
     rc, h = _plan_ex(**kw)

@@ -1,5 +1,7 @@
 """GPU parity of the long-line transforms: one-axis plans whose element count
-K exceeds one LDS tile (K = 2^11 .. 2^20, the four-step DFT passes), n = 5.
+K exceeds one LDS tile (1024 < K <= 2^20), n = 5: powers of two (four-step
+DFT passes) and other K, odd and even, primes among them (Bluestein's
+chirp-z over a power-of-two length L >= 2K - 1, up to L = 2^21).
 
 - forward FC_n (Sect. 3, Theorem 2): sampled coefficients (y, s)/||s||_C
   against the oracle's eigenvectors of Theorem 1 (the norm taken as s.Ccal s
@@ -24,6 +26,9 @@ pytestmark = pytest.mark.gpu
 
 N5 = 5
 KS = [1 << 11, 1 << 12, 1 << 16, 1 << 20]
+# not powers of two: odd composite, primes, even composites, the largest
+# prime below 2^20 (L = 2^21)
+KS_OTHER = [1025, 1031, 2308, 4099, 60695, 65537, 319564, 1048573]
 
 
 def say(*a):
@@ -60,6 +65,10 @@ SAMPLES = {
     1 << 11: [(0, 1), (0, 4), (1, 1), (1, 5), (2, 3), (333, 2), (1024, 1), (1024, 5), (1025, 4), (2047, 5)],
     1 << 12: [(1, 2), (2047, 1), (2048, 3), (2049, 5), (4095, 4)],
     1 << 16: [(1, 1), (40000, 5)],
+    1025: [(0, 2), (0, 3), (1, 1), (512, 4), (513, 5), (1024, 2)],
+    1031: [(1, 5), (515, 1), (516, 3), (1030, 4)],
+    2308: [(1, 3), (1154, 2), (1155, 5), (2307, 1)],
+    65537: [(32768, 2), (65536, 5)],
 }
 
 
@@ -81,7 +90,7 @@ def test_long_forward_matches_theorem1_eigenvectors(fm, K):
         assert abs(g - want) <= tol, (k, l, g, want)
 
 
-@pytest.mark.parametrize("K", KS)
+@pytest.mark.parametrize("K", KS + KS_OTHER)
 def test_long_round_trip(fm, K):
     n = N5
     say("long round trip", n, K)
@@ -97,7 +106,8 @@ def test_long_round_trip(fm, K):
 
 
 @pytest.mark.parametrize("K,diff,react,X", [
-    (1 << 11, 1.0, 0.0, 1.0), (1 << 12, 0.7, 2.5, 3.0), (1 << 16, 1.3, 0.4, 2.0), (1 << 20, 1.0, 0.0, 1.0)])
+    (1 << 11, 1.0, 0.0, 1.0), (1 << 12, 0.7, 2.5, 3.0), (1 << 16, 1.3, 0.4, 2.0), (1 << 20, 1.0, 0.0, 1.0),
+    (1025, 0.7, 2.5, 3.0), (4099, 1.0, 0.0, 1.0), (319564, 1.0, 0.0, 1.0), (1048573, 1.0, 0.0, 1.0)])
 def test_long_solve_sine(fm, K, diff, react, X):
     """Two right-hand sides at once: the loads of sin(m pi x / X), m = 1, 3."""
     n = N5
@@ -117,14 +127,15 @@ def test_long_solve_sine(fm, K, diff, react, X):
     assert st["converged"] and st["stop"] == "none", st
 
 
-def test_long_solve_matches_sparse_direct(fm):
+@pytest.mark.parametrize("K", [1 << 11, 1031, 2308])
+def test_long_solve_matches_sparse_direct(fm, K):
     """Random load: the sparse LU solve alone is only accurate to about
     cond(A) eps (1e-8 here), so it is refined with the residual of the
     oracle's element-wise operator in extended precision, as the oracle's
     own solve does."""
     import scipy.sparse.linalg as spla
     from oracle import solve as osolve
-    n, K, diff, react = N5, 1 << 11, 1.0, 0.5
+    n, diff, react = N5, 1.0, 0.5
     say("long solve sparse", n, K)
     A, C = fem1d.assemble(n, K, dense=False)
     f = inputs.draw_rhs([n * K - 1], 1900, "normal")
@@ -137,8 +148,9 @@ def test_long_solve_matches_sparse_direct(fm):
     assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-11
 
 
-def test_long_solve_reports_nonfinite(fm):
-    n, K = N5, 1 << 11
+@pytest.mark.parametrize("K", [1 << 11, 1031])
+def test_long_solve_reports_nonfinite(fm, K):
+    n = N5
     say("long solve nan", n, K)
     p = plan(fm, K, nrhs=2)
     f = inputs.draw_rhs([2, n * K - 1], 1901, "normal")
@@ -154,13 +166,14 @@ def test_long_solve_reports_nonfinite(fm):
     assert p.stats()["converged"]
 
 
-def test_long_coefficients_synthesize_apply(fm):
+@pytest.mark.parametrize("K", [1 << 16, 60695])
+def test_long_coefficients_synthesize_apply(fm, K):
     """The other entry points on a long-line plan: expansion coefficients of
     loads are the forward transform, synthesis the inverse, coefficients of
     synthesized values return the coefficients (Theorem 2, item 3), and the
     operator apply matches the oracle's element-wise operator."""
     from oracle import solve as osolve
-    n, K, diff, react = N5, 1 << 16, 1.3, 0.4
+    n, diff, react = N5, 1.3, 0.4
     say("long coefficients", n, K)
     p = plan(fm, K, diff, react, 2.0, nrhs=2)
     y = inputs.draw_rhs([2, n * K - 1], 1902, "normal")
