@@ -83,8 +83,8 @@ enum {
 typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
   int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; one-axis
-                                     FFTFEM_FP64 plans of algorithm (a) also accept powers of two
-                                     up to 2^20: multi-pass transforms, not in batches) */
+                                     FFTFEM_FP64 plans of algorithm (a) also accept any K up to
+                                     2^20: multi-pass transforms, not in batches) */
   int n;                          /* element order (every axis without n_axis), 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */

@@ -1202,11 +1202,11 @@ static int long_transform(fftfem_plan_t p, int mode, const double* in, double* o
     a.pre = inv ? 2 : 1;
     step(LONG_COLS, false, W0, nullptr, inv ? "lbcols64i" : "lbcols64");
     a.pre = 0;
-    a.post = inv ? 2 : 1;
     step(LONG_ROWS, false, W0, W1, inv ? "lbrows64i" : "lbrows64");
-    a.post = 0;
+    a.pre = inv ? 4 : 3;
     step(LONG_COLS, true, W1, nullptr, inv ? "lbcols64ic" : "lbcols64c");
-    a.post = inv ? 4 : 3;
+    a.pre = 0;
+    a.post = inv ? 2 : 1;
     step(LONG_ROWS, true, W1, W0, inv ? "lbrows64ic" : "lbrows64c");
     a.post = 0;
     return W0;

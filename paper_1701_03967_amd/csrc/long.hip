@@ -20,7 +20,7 @@
 // cyclic convolution of length L done as a forward and an inverse D-point
 // DFT, four passes: the chirp multiplication and the zero padding fused into
 // the loads of the first column pass, the product with the spectrum of
-// conj(c) (divided by L) into the stores of the first row pass, the final
+// conj(c) (divided by L) into the loads of the second column pass, the final
 // chirp and the truncation to K into the stores of the last row pass
 // (conjugated chirp and spectrum for the inverse DFT).
 //
@@ -48,6 +48,7 @@ constexpr int kLongThreads = 256;
 constexpr int kLongLgTilePts = 12;  // 4096 points per four-step tile (one chunk of the Stockham stages)
 constexpr int kLongTwBits = 10;     // low bits of the twiddle index (table of 1024)
 static_assert((1 << kLongLgTilePts) == kLongThreads * 16, "a tile is one chunk of the Stockham stages");
+constexpr int kLongPT = 16;  // tile points per thread at most
 
 using CD = C2<double>;
 
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(kLongThreads) void long_gather_kernel(LongArgs a) {
 // Four-step DFT, first half: 2^lgc adjacent columns (i2) of one buffer,
 // length-K1 DFTs over i1, then the twiddles exp(-+2 pi i i2 k1 / D); in
 // place.  pre = 1 (2): the input is x_i c_i (x_i conj(c_i)) for i < K and 0
-// beyond (the first pass of Bluestein's convolution).
+// beyond (the start of Bluestein's convolution); pre = 3 (4): x_i bhat_i
+// (x_i conj(bhat_i)), the product with the spectrum of its kernel.
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, double* w) {
   const int K1 = a.K1, K2 = a.K2, lg = a.lgc, G = 1 << lg, K = a.K, pre = a.pre;
@@ -103,40 +105,60 @@ __global__ __launch_bounds__(kLongThreads) void long_cols_kernel(LongArgs a, dou
   const int c0 = (int)(tile - buf * ncb) << lg;
   CD* X = reinterpret_cast<CD*>(w) + buf * (size_t)a.ls;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
-  const CD* chirp = reinterpret_cast<const CD*>(a.chirp);
   const int ls = K1 + 1;
   const int tid = threadIdx.x;
-  for (int i = tid; i < G * K1; i += kLongThreads) {
-    const int i1 = i >> lg, g = i & (G - 1);
-    const int idx = i1 * K2 + c0 + g;
-    CD v;
-    if (pre == 0) {
-      v = X[idx];
-    } else if (idx < K) {
-      v = pre == 1 ? cmul(X[idx], chirp[idx]) : cmulc(X[idx], chirp[idx]);
-    } else {
-      v = CD{0.0, 0.0};
+  const int total = G * K1;
+  // all of a thread's loads in flight before the first LDS store
+  CD v[kLongPT];
+  if (pre == 0) {
+#pragma unroll
+    for (int j = 0; j < kLongPT; ++j) {
+      const int i = tid + j * kLongThreads;
+      if (i < total) v[j] = X[(i >> lg) * K2 + c0 + (i & (G - 1))];
     }
-    slot(L + g * ls, i1) = v;
+  } else {
+    // x_i and the factor f_i for i < lim, 0 and 1 beyond
+    const CD* fac = reinterpret_cast<const CD*>(pre <= 2 ? a.chirp : a.bhat);
+    const int lim = pre <= 2 ? K : K1 * K2;
+    CD c[kLongPT];
+#pragma unroll
+    for (int j = 0; j < kLongPT; ++j) {
+      const int i = tid + j * kLongThreads;
+      const int idx = (i >> lg) * K2 + c0 + (i & (G - 1));
+      const bool in = i < total && idx < lim;
+      v[j] = in ? X[idx] : CD{0.0, 0.0};
+      c[j] = in ? fac[idx] : CD{1.0, 0.0};
+    }
+    const bool conj = (pre & 1) == 0;
+#pragma unroll
+    for (int j = 0; j < kLongPT; ++j) v[j] = conj ? cmulc(v[j], c[j]) : cmul(v[j], c[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < kLongPT; ++j) {
+    const int i = tid + j * kLongThreads;
+    if (i < total) slot(L + (i & (G - 1)) * ls, i >> lg) = v[j];
   }
   __syncthreads();
   fft_all<double, INV, kLongThreads>(L, G, a.lk1, reinterpret_cast<const CD*>(a.tw1), ls, 4);
   const CD* twlo = reinterpret_cast<const CD*>(a.twlo);
   const CD* twhi = reinterpret_cast<const CD*>(a.twhi);
-  for (int i = tid; i < G * K1; i += kLongThreads) {
-    const int k1 = i >> lg, g = i & (G - 1);
-    CD v = slot(L + g * ls, k1);
-    const int m = (c0 + g) * k1;  // < D <= 2^21
-    const CD tw = cmul(twhi[m >> kLongTwBits], twlo[m & ((1 << kLongTwBits) - 1)]);
-    X[(size_t)k1 * K2 + c0 + g] = INV ? cmulc(v, tw) : cmul(v, tw);
+#pragma unroll
+  for (int j = 0; j < kLongPT; ++j) {
+    const int i = tid + j * kLongThreads;
+    if (i < total) {
+      const int k1 = i >> lg, g = i & (G - 1);
+      const CD u = slot(L + g * ls, k1);
+      const int m = (c0 + g) * k1;  // < D <= 2^21
+      const CD tw = cmul(twhi[m >> kLongTwBits], twlo[m & ((1 << kLongTwBits) - 1)]);
+      X[(size_t)k1 * K2 + c0 + g] = INV ? cmulc(u, tw) : cmul(u, tw);
+    }
   }
 }
 
 // Four-step DFT, second half: 2^lgr adjacent rows (k1) of one buffer of w,
 // length-K2 DFTs over i2, stored into the same buffer of out at
-// k = k1 + K1 k2.  post = 1 (2): times bhat_k (conj(bhat_k)), the spectrum of
-// Bluestein's kernel; post = 3 (4): times c_k (conj(c_k)) and only k < K
-// stored (the end of Bluestein's convolution).
+// k = k1 + K1 k2.  post = 1 (2): times c_k (conj(c_k)) and only k < K stored
+// (the end of Bluestein's convolution).
 template <bool INV>
 __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, const double* w, double* out) {
   const int K1 = a.K1, K2 = a.K2, lg = a.lgr, G = 1 << lg, K = a.K, post = a.post;
@@ -148,26 +170,35 @@ __global__ __launch_bounds__(kLongThreads) void long_rows_kernel(LongArgs a, con
   CD* Y = reinterpret_cast<CD*>(out) + buf * (size_t)a.ls;
   CD* L = reinterpret_cast<CD*>(fftfem_long_lds);
   const CD* chirp = reinterpret_cast<const CD*>(a.chirp);
-  const CD* bhat = reinterpret_cast<const CD*>(a.bhat);
   const int ls = K2 + 1;
   const int tid = threadIdx.x;
-  for (int i = tid; i < G * K2; i += kLongThreads) {
-    const int g = i >> a.lk2, i2 = i & (K2 - 1);
-    slot(L + g * ls, i2) = X[(size_t)(r0 + g) * K2 + i2];
+  const int total = G * K2;
+  // the tile's rows are one contiguous segment of the buffer; all of a
+  // thread's loads in flight before the first LDS store
+  const CD* Xs = X + (size_t)r0 * K2;
+  CD v[kLongPT];
+#pragma unroll
+  for (int j = 0; j < kLongPT; ++j) {
+    const int i = tid + j * kLongThreads;
+    v[j] = i < total ? Xs[i] : CD{0.0, 0.0};
+  }
+#pragma unroll
+  for (int j = 0; j < kLongPT; ++j) {
+    const int i = tid + j * kLongThreads;
+    if (i < total) slot(L + (i >> a.lk2) * ls, i & (K2 - 1)) = v[j];
   }
   __syncthreads();
   fft_all<double, INV, kLongThreads>(L, G, a.lk2, reinterpret_cast<const CD*>(a.tw2), ls, 4);
-  for (int i = tid; i < G * K2; i += kLongThreads) {
-    const int k2 = i >> lg, g = i & (G - 1);
-    const int k = r0 + g + K1 * k2;
-    CD v = slot(L + g * ls, k2);
-    if (post == 1) v = cmul(v, bhat[k]);
-    if (post == 2) v = cmulc(v, bhat[k]);
-    if (post >= 3) {
-      if (k >= K) continue;
-      v = post == 3 ? cmul(v, chirp[k]) : cmulc(v, chirp[k]);
+  for (int i = tid; i < total; i += kLongThreads) {
+    {
+      const int k2 = i >> lg, g = i & (G - 1);
+      const int k = r0 + g + K1 * k2;
+      CD u = slot(L + g * ls, k2);
+      if (post == 0 || k < K) {
+        if (post != 0) u = post == 1 ? cmul(u, chirp[k]) : cmulc(u, chirp[k]);
+        Y[k] = u;
+      }
     }
-    Y[k] = v;
   }
 }
 
@@ -180,7 +211,8 @@ __host__ __device__ inline int long_pair_tasks(int K) { return (K + 1) >> 1; }
 // -> coefficients (y, s~) in the spectral order of the line (k = 0 block of
 // n - 1, then n per k).
 template <int NORD>
-__device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_t l, int kap) {
+__device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_t l, int kap, double* wa,
+                                                       double* wb) {
   constexpr int n = NORD, NC = NORD > 1 ? NORD - 1 : 1;
   const int K = a.K, ls = a.ls;
   const bool keven = (K & 1) == 0;
@@ -189,7 +221,7 @@ __device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_
   const CD* B = long_buf(a.wb, l, 0, 1 + NORD / 2, ls);
   const CD* twm = reinterpret_cast<const CD*>(a.twm);
   const CD* twd = reinterpret_cast<const CD*>(a.twd);
-  double ca[NC], cb[NC], cha[NORD], chb[NORD], wa[NORD], wb[NORD];
+  double ca[NC], cb[NC], cha[NORD], chb[NORD];
   if (kap == 0) {
     if constexpr (NORD > 1) {
       bubble_post<double, NORD, false>(B, ls, 0, 0, twm, ca, cb);
@@ -206,50 +238,92 @@ __device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_
   }
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
   contract_fwd<double, NORD>(qtab, K, ka, cha, wa);
-  if (hasb) contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
-  double* rs = a.out + l * a.M;
-  const int ra = ka == 0 ? n - 1 : n;
-  const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
-  const int offb = n - 1 + (kb - 1) * n;
+  if (hasb) {
+    contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
+  } else {
 #pragma unroll
-  for (int c = 0; c < NORD; ++c) {
-    if (c < ra) rs[offa + c] = wa[c];
-    if (hasb) rs[offb + c] = wb[c];
+    for (int c = 0; c < NORD; ++c) wb[c] = 0.0;
   }
+}
+
+// The spectral coefficients of the tasks of one block: workgroup b takes the
+// tasks kap0 .. kap0 + 255 of a group of lpt lines.  Without kap = 0 their
+// coefficients form two contiguous runs of a line, the frequencies kap
+// (ascending) and K - kap (descending): staged in LDS, they are read and
+// written by consecutive threads in 8-byte steps instead of n-strided ones.
+struct LongRuns {
+  int64_t grp;     // line group
+  int kap;         // this thread's task
+  int lo, cnt;     // tasks lo .. lo + cnt - 1 (lo >= 1) form the runs
+  int64_t baseA;   // offset of frequency lo's coefficients
+  int64_t baseB;   // offset of frequency K - (lo + cnt - 1)'s coefficients
+};
+
+__device__ __forceinline__ LongRuns long_runs(const LongArgs& a, int n) {
+  LongRuns r;
+  const int nt = long_pair_tasks(a.K);
+  const int nkb = (nt + kLongThreads - 1) / kLongThreads;
+  r.grp = blockIdx.x / nkb;
+  const int k0 = (int)(blockIdx.x - r.grp * nkb) * kLongThreads;
+  r.kap = k0 + (int)threadIdx.x;
+  r.lo = k0 > 0 ? k0 : 1;
+  const int hi = k0 + kLongThreads < nt ? k0 + kLongThreads : nt;
+  r.cnt = hi > r.lo ? hi - r.lo : 0;
+  r.baseA = n - 1 + (int64_t)(r.lo - 1) * n;
+  r.baseB = n - 1 + (int64_t)(a.K - (hi - 1) - 1) * n;
+  return r;
 }
 
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_contract_fwd_kernel(LongArgs a) {
-  const int nt = long_pair_tasks(a.K);
-  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
-  const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
-  if (t >= ngrp * nt) return;
-  const int64_t grp = t / nt;
-  const int kap = (int)(t - grp * nt);
-  const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
-  for (int64_t l = grp * a.lpt; l < lend; ++l) long_contract_fwd_line<NORD>(a, l, kap);
+  constexpr int n = NORD;
+  __shared__ double SA[kLongThreads * NORD], SB[kLongThreads * NORD];
+  const LongRuns r = long_runs(a, n);
+  const bool act = r.kap < long_pair_tasks(a.K);
+  const int pa = r.kap - r.lo, pb = r.lo + r.cnt - 1 - r.kap;
+  const int64_t lend = (r.grp + 1) * a.lpt < a.nlines ? (r.grp + 1) * a.lpt : a.nlines;
+  for (int64_t l = r.grp * a.lpt; l < lend; ++l) {
+    double wa[NORD], wb[NORD];
+    double* rs = a.out + l * a.M;
+    if (act) {
+      long_contract_fwd_line<NORD>(a, l, r.kap, wa, wb);
+      if (r.kap == 0) {
+        // the k = 0 block, and frequency K/2 for even K
+#pragma unroll
+        for (int c = 0; c < NORD - 1; ++c) rs[c] = wa[c];
+        if ((a.K & 1) == 0) {
+#pragma unroll
+          for (int c = 0; c < NORD; ++c) rs[n - 1 + (int64_t)((a.K >> 1) - 1) * n + c] = wb[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NORD; ++c) {
+          SA[pa * n + c] = wa[c];
+          SB[pb * n + c] = wb[c];
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r.cnt * n; i += kLongThreads) {
+      rs[r.baseA + i] = SA[i];
+      rs[r.baseB + i] = SB[i];
+    }
+    __syncthreads();
+  }
 }
 
 // The inverse: coefficients of the frequencies of task kap -> channel
 // spectra with the Hermitian pre-twiddles -> slots of the buffers of wa.
 template <int NORD>
-__device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_t l, int kap) {
+__device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_t l, int kap, const double* wa,
+                                                       const double* wb) {
   constexpr int n = NORD, ne = NORD / 2, no = (NORD - 1) / 2, P = NORD / 2, NC = NORD > 1 ? NORD - 1 : 1;
   const int K = a.K, ls = a.ls;
   const bool keven = (K & 1) == 0;
   const bool hasb = kap != 0 || keven;
   const int kh = K >> 1;
   const int ka = kap, kb = kap == 0 ? kh : K - kap;
-  const double* rs = a.in + l * a.M;
-  const int ra = ka == 0 ? n - 1 : n;
-  const int offa = ka == 0 ? 0 : n - 1 + (ka - 1) * n;
-  const int offb = n - 1 + (kb - 1) * n;
-  double wa[NORD], wb[NORD], h0[NORD], h1[NORD];
-#pragma unroll
-  for (int c = 0; c < NORD; ++c) {
-    wa[c] = c < ra ? rs[offa + c] : 0.0;
-    wb[c] = hasb ? rs[offb + c] : 0.0;
-  }
+  double h0[NORD], h1[NORD];
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
   contract_inv<double, NORD>(qtab, K, ka, wa, h0);
   if (hasb) {
@@ -315,14 +389,27 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
 
 template <int NORD>
 __global__ __launch_bounds__(kLongThreads) void long_contract_inv_kernel(LongArgs a) {
-  const int nt = long_pair_tasks(a.K);
-  const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
-  const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
-  if (t >= ngrp * nt) return;
-  const int64_t grp = t / nt;
-  const int kap = (int)(t - grp * nt);
-  const int64_t lend = (grp + 1) * a.lpt < a.nlines ? (grp + 1) * a.lpt : a.nlines;
-  for (int64_t l = grp * a.lpt; l < lend; ++l) long_contract_inv_line<NORD>(a, l, kap);
+  // n-strided loads of the coefficients: staging them through LDS (as the
+  // forward contraction does for its stores) measured slower here
+  constexpr int n = NORD;
+  const LongRuns r = long_runs(a, n);
+  if (r.kap >= long_pair_tasks(a.K)) return;
+  const bool keven = (a.K & 1) == 0;
+  const bool hasb = r.kap != 0 || keven;
+  const int64_t offa = r.kap == 0 ? 0 : n - 1 + (int64_t)(r.kap - 1) * n;
+  const int64_t offb = n - 1 + (int64_t)((r.kap == 0 ? a.K >> 1 : a.K - r.kap) - 1) * n;
+  const int ra = r.kap == 0 ? n - 1 : n;
+  const int64_t lend = (r.grp + 1) * a.lpt < a.nlines ? (r.grp + 1) * a.lpt : a.nlines;
+  for (int64_t l = r.grp * a.lpt; l < lend; ++l) {
+    const double* rs = a.in + l * a.M;
+    double wa[NORD], wb[NORD];
+#pragma unroll
+    for (int c = 0; c < NORD; ++c) {
+      wa[c] = c < ra ? rs[offa + c] : 0.0;
+      wb[c] = hasb ? rs[offb + c] : 0.0;
+    }
+    long_contract_inv_line<NORD>(a, l, r.kap, wa, wb);
+  }
 }
 
 // Element jp of line l from the inverse-transformed buffers of wb: node
@@ -387,17 +474,18 @@ static hipError_t long_step_n(int step, const LongArgs& a, hipStream_t s) {
   unsigned nb = 0;
   hipError_t e;
   const int64_t ngrp = (a.nlines + a.lpt - 1) / a.lpt;
+  const int64_t nkb = (long_pair_tasks(a.K) + kLongThreads - 1) / kLongThreads;  // contraction blocks per group
   switch (step) {
     case LONG_GATHER:
       if ((e = grid_launch_check(a.nlines * a.K, &nb))) return e;
       hipLaunchKernelGGL((long_gather_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_FWD:
-      if ((e = grid_launch_check(ngrp * long_pair_tasks(a.K), &nb))) return e;
+      if ((e = grid_launch_check(ngrp * nkb * kLongThreads, &nb))) return e;
       hipLaunchKernelGGL((long_contract_fwd_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_CONTRACT_INV:
-      if ((e = grid_launch_check(ngrp * long_pair_tasks(a.K), &nb))) return e;
+      if ((e = grid_launch_check(ngrp * nkb * kLongThreads, &nb))) return e;
       hipLaunchKernelGGL((long_contract_inv_kernel<NORD>), dim3(nb), dim3(kLongThreads), 0, s, a);
       break;
     case LONG_SCATTER:
@@ -431,8 +519,8 @@ hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, 
       D > (1 << (2 * kLongTwBits + 1)) || a.nlines < 1 || a.lpt < 1)
     return hipErrorInvalidValue;
   // the Bluestein factors: only for K not a power of two, with their tables
-  if (a.pre < 0 || a.pre > 2 || a.post < 0 || a.post > 4 || (pow2 && (a.pre || a.post)) ||
-      ((a.pre || a.post >= 3) && !a.chirp) || ((a.post == 1 || a.post == 2) && !a.bhat))
+  if (a.pre < 0 || a.pre > 4 || a.post < 0 || a.post > 2 || (pow2 && (a.pre || a.post)) ||
+      (((a.pre && a.pre <= 2) || a.post) && !a.chirp) || (a.pre >= 3 && !a.bhat))
     return hipErrorInvalidValue;
   // a tile is one chunk of the Stockham stages (whole buffers, in place)
   if (a.lgc < 0 || a.lgc > a.lk2 || a.lgr < 0 || a.lgr > a.lk1 || a.lk1 + a.lgc > kLongLgTilePts ||
