@@ -381,6 +381,36 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       const int nl = (int)(a.nlines - l0 < (int64_t)G ? a.nlines - l0 : (int64_t)G);
       const int nflat = nl * M;
       const int64_t base = l0 * (int64_t)M;
+      if constexpr (sizeof(T) == 8) {
+        // float64: 16-byte loads of value pairs (the first value alone when
+        // the segment does not start 16-byte aligned, the last when one is
+        // left over)
+        const double* sp = reinterpret_cast<const double*>(src) + base;
+        const int head = (reinterpret_cast<uintptr_t>(sp) & 15) ? 1 : 0;
+        const int np = (nflat - head) >> 1;
+        const double2* s2 = reinterpret_cast<const double2*>(sp + head);
+        for (int i0 = tid; i0 < np; i0 += 8 * kNT) {
+          double2 v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            int i = i0 + u * kNT;
+            v[u] = i < np ? s2[i] : double2{0.0, 0.0};
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            int i = i0 + u * kNT;
+            if (i < np) {
+              raw[head + 2 * i] = v[u].x;
+              raw[head + 2 * i + 1] = v[u].y;
+            }
+          }
+        }
+        if (tid == 0 && nflat > 0) {
+          if (head) raw[0] = sp[0];
+          if ((nflat - head) & 1) raw[nflat - 1] = sp[nflat - 1];
+        }
+        return;
+      }
       for (int i0 = tid; i0 < nflat; i0 += 16 * kNT) {
         T v[16];
 #pragma unroll
@@ -436,6 +466,25 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       const int nl = (int)(a.nlines - l0 < (int64_t)G ? a.nlines - l0 : (int64_t)G);
       const int nflat = nl * M;
       const int64_t base = l0 * (int64_t)M;
+      if constexpr (sizeof(T) == 8 && !UPD) {
+        if (a.out_kind != 2) {
+          // float64 output: 16-byte stores of value pairs
+          double* op = reinterpret_cast<double*>(a.out) + base;
+          const int head = (reinterpret_cast<uintptr_t>(op) & 15) ? 1 : 0;
+          const int np = (nflat - head) >> 1;
+          double2* o2 = reinterpret_cast<double2*>(op + head);
+          for (int i = tid; i < np; i += kNT) {
+            const double v0 = raw[head + 2 * i], v1 = raw[head + 2 * i + 1];
+            o2[i] = double2{v0, v1};
+            if (chk) nonfinite |= !(v0 - v0 == 0.0) || !(v1 - v1 == 0.0);
+          }
+          if (tid == 0 && nflat > 0) {
+            if (head) put(base, raw[0]);
+            if ((nflat - head) & 1) put(base + nflat - 1, raw[nflat - 1]);
+          }
+          return;
+        }
+      }
       for (int i = tid; i < nflat; i += kNT) put(base + i, raw[i]);
     }
   };
