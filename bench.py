@@ -93,7 +93,8 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
     return 0.0
 
 
-KERNEL_SOURCES = ("line.hip", "fft.h", "device_common.h", "launch.h", "ops.hip", "api.cpp", "band.hip")
+KERNEL_SOURCES = ("line.hip", "fft.h", "spectral.h", "device_common.h", "launch.h", "ops.hip", "api.cpp", "band.hip",
+                  "long.hip", "batch.cpp")
 
 
 def sources_sha256() -> str:
@@ -110,6 +111,8 @@ def sources_sha256() -> str:
 def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     """Symbol of the kernel that a per-pass timing name refers to."""
     head = name.split("_ax")[0]
+    if head.startswith("transpose"):
+        return f"transpose_kernel<{'float' if head.endswith('32') else 'double'}>"
     for pre, sym in (("bandcond", "band_cond_kernel"), ("bandnodes", "band_nodes_kernel"),
                      ("bandback", "band_back_kernel"), ("bandtile", "band_tile_kernel"), ("band", "band_kernel")):
         if head.startswith(pre):
@@ -134,11 +137,15 @@ def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}, {pow2}>"
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, mode: str = ""):
     """HBM bytes per dispatch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or
-    None when there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size) of the
+    mode's own runs (one kernel symbol can serve several modes with other
+    layouts), else of the workload's, or None when there is none or the
+    kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{mode}.txt")
+    if not mode or not os.path.exists(path):
+        path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     sha, rows = None, {}
@@ -575,7 +582,85 @@ def run_transform1d(args, torch, fm):
     print(json.dumps(line))
 
 
+def summarize_stats(d: str, title: str, cmd: str, out: str):
+    """profiles/kernel_stats_<name>.txt from the kernel_stats.csv of a
+    rocprofv3 --kernel-trace --stats run in directory d, longest total first."""
+    import csv
+    import glob
+    fn = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = []
+    with open(fn) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((float(r["TotalDurationNs"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"]), r["Name"]))
+    rows.sort(reverse=True)
+    lines = [f"# rocprofv3 --kernel-trace --stats summary (kernel_stats.csv), MI355X (gfx950): {title}",
+             f"# command: (from the repository root, TMPDIR=/tmp) {cmd}",
+             f"# summary: python bench.py summarize-stats <output dir> <title> <command> <this file>",
+             f"# kernel sources sha256: {sources_sha256()}",
+             " calls     avg_us     min_us     max_us    pct  kernel"]
+    for _, calls, avg, mn, mx, pct, name in rows:
+        if len(name) > 160:  # library kernels with long template names
+            name = name[:157] + "..."
+        lines.append(f"{calls:6d} {avg:10.1f} {mn:10.1f} {mx:10.1f} {pct:6.2f}  {name}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:30]))
+
+
+def summarize_traffic(workload: str, fetch_dir: str, write_dir: str, nbytes: str, fetch_cmd: str,
+                      write_cmd: str, out: str):
+    """profiles/traffic_<workload>.txt from two rocprofv3 --pmc runs of the
+    same bench command (FETCH_SIZE, WRITE_SIZE), scaled by what the counters
+    read for the calibration copy (the largest device copy of the run, a
+    plain copy of nbytes bytes)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    nbytes = int(nbytes)
+
+    def read(d, counter):
+        per = defaultdict(list)
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return per
+
+    fe, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    copy_f = max(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
+    ff, fw = nbytes / 1024.0 / copy_f, nbytes / 1024.0 / copy_w
+    lines = [f"# HBM traffic per dispatch, workload {workload}, MI355X (gfx950), rocprofv3 --pmc",
+             f"# fetch pass: (from the repository root, TMPDIR=/tmp) {fetch_cmd}",
+             f"# write pass: (from the repository root, TMPDIR=/tmp) {write_cmd}",
+             f"# summary: python bench.py summarize-traffic {workload} <fetch dir> <write dir> {nbytes} "
+             "<fetch command> <write command> <this file>",
+             f"# scale: a plain device copy of {nbytes} bytes read FETCH_SIZE {copy_f:.1f} KiB and WRITE_SIZE "
+             f"{copy_w:.1f} KiB; factors fetch x{ff:.4f}, write x{fw:.4f}",
+             "# bytes = (FETCH_SIZE * fetch factor + WRITE_SIZE * write factor) * 1024, mean over dispatches",
+             f"sources_sha256: {sources_sha256()}"]
+    rows = []
+    for k in fe:
+        if "fftfem::" not in k or k not in wr:
+            continue
+        f = sum(fe[k]) / len(fe[k]) * ff * 1024
+        w = sum(wr[k]) / len(wr[k]) * fw * 1024
+        rows.append((f + w, f"kernel: {k} | dispatches={len(fe[k])} | fetch_bytes={f:.4e} | "
+                            f"write_bytes={w:.4e} | bytes={f + w:.6e}"))
+    lines += [r for _, r in sorted(rows, reverse=True)]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic"):
+        # text summaries of rocprofv3 output for profiles/ (no GPU use)
+        fn = summarize_stats if sys.argv[1] == "summarize-stats" else summarize_traffic
+        fn(*sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
@@ -619,7 +704,7 @@ def main():
         run_batch(args, torch, fm)
         return
 
-    def roofline_of(kt, prob, workload, steps_timed):
+    def roofline_of(kt, prob, workload, steps_timed, mode=""):
         """Roofline of the dominant kernel of one mode (the most total time
         per step), from its mean HIP-event duration on the plan's stream."""
         if not kt:
@@ -632,7 +717,7 @@ def main():
         ax = int(name.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in name else 0
         kname = profiler_kernel_name(name, prob.n, prob.N, prob.K[ax])
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, kname),
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, kname, mode),
                 "kernel": name, "symbol": kname, "bytes_per_launch": by, "avg_ms": avg_ms,
                 "launches_per_step": cnt / steps_timed}
 
@@ -665,10 +750,16 @@ def main():
             rec["kernels_per_step"] = {k: v[1] / min(steps, 10) for k, v in kt.items()}
             rec["stage_GBps"] = {k: round(kernel_bytes(k, prob.size, prob.N, prob.n) / (avg * 1e-3) / 1e9, 1)
                                  for k, (avg, _) in kt.items() if kernel_bytes(k, prob.size, prob.N, prob.n) > 0}
+            # measured HBM bytes per launch of each kernel (committed counter
+            # summaries; null when absent or taken on other sources)
+            rec["stage_traffic_bytes"] = {
+                k: measured_traffic(name, profiler_kernel_name(
+                    k, prob.n, prob.N, prob.K[int(k.rsplit("_ax", 1)[1].rstrip("t")) if "_ax" in k else 0]), mode)
+                for k in kt}
             step_bytes = sum(kernel_bytes(k, prob.size, prob.N, prob.n) * c / min(steps, 10) for k, (_, c) in kt.items())
             rec["bytes_per_step"] = step_bytes
             rec["step_GBps"] = round(step_bytes / (ms * 1e-3) / 1e9, 1)
-            rec["roofline"] = roofline_of(kt, prob, name, min(steps, 10))
+            rec["roofline"] = roofline_of(kt, prob, name, min(steps, 10), mode)
             out[mode] = rec
             del plan
             print(f"[bench] {name} {mode}: {ms:.3f} ms/solve, err vs oracle {rec['err_vs_oracle']}",
