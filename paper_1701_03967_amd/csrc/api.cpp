@@ -1055,8 +1055,7 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   if (!rc) rc = dev_alloc(p, (void**)&p->flags, (size_t)p->nrhs * sizeof(int));
   if (!rc) rc = dev_alloc(p, (void**)&p->stats, (size_t)p->nrhs * kStatsLen * sizeof(double));
   if (!rc) {
-    for (int r = 0; r < p->nrhs && !rc; ++r)
-      rc = from_hip(launch_reset(p->flags + r, p->stats + r * kStatsLen, kStatsLen, nullptr));
+    rc = from_hip(launch_reset_many(p->flags, p->stats, kStatsLen, p->nrhs, nullptr));
     if (!rc) rc = from_hip(hipDeviceSynchronize());
   }
   if (rc) {
@@ -1244,8 +1243,7 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
   if (p->longK) {
     // float64, no refinement: reset the statistics, then every right-hand
     // side at once
-    for (int r = 0; r < p->nrhs && !rc; ++r)
-      rc = from_hip(launch_reset(p->flags + r, p->stats + (size_t)r * kStatsLen, kStatsLen, s));
+    rc = from_hip(launch_reset_many(p->flags, p->stats, kStatsLen, p->nrhs, s));
     if (!rc) rc = long_transform(p, MID, f, u, p->nrhs, s, p->flags);
     return rc;
   }

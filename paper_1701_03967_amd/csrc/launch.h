@@ -240,6 +240,7 @@ int band_tile_lines(int K);  // lines per workgroup of launch_band_tile for K el
 template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t batch, int64_t R, int64_t C, hipStream_t s);
 hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s);
+hipError_t launch_reset_many(int* flags, double* stats, int nstats, int count, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nparts, int iter, double tol, int* flag,
                          double* stats, hipStream_t s);
 

@@ -716,6 +716,11 @@ __device__ __forceinline__ void reset_body(int* flag, double* stats, int nstats)
 
 __global__ void reset_kernel(int* flag, double* stats, int nstats) { reset_body(flag, stats, nstats); }
 
+// count consecutive flags and statistics blocks (right-hand sides) at once
+__global__ void reset_many_kernel(int* flags, double* stats, int nstats, int count) {
+  for (int r = blockIdx.x; r < count; r += gridDim.x) reset_body(flags + r, stats + (size_t)r * nstats, nstats);
+}
+
 __global__ void reset_kernel_grouped(const ResetJob* __restrict__ jobs) {
   const ResetJob& j = jobs[blockIdx.x];
   reset_body(j.flag, j.stats, j.nstats);
@@ -916,6 +921,13 @@ hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipS
 
 hipError_t launch_reset(int* flag, double* stats, int nstats, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, flag, stats, nstats);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_many(int* flags, double* stats, int nstats, int count, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  const int nb = count < 4096 ? count : 4096;
+  hipLaunchKernelGGL(reset_many_kernel, dim3(nb), dim3(64), 0, s, flags, stats, nstats, count);
   return hipGetLastError();
 }
 
