@@ -188,3 +188,39 @@ def test_long_coefficients_synthesize_apply(fm, K):
     for r in range(2):
         ref = osolve.apply_A(y[r], n, (K,), (diff,), react, X=(2.0,))
         assert np.linalg.norm(Au[r] - ref) / np.linalg.norm(ref) < 1e-13, r
+
+
+def refined_sparse_solve(n, K, diff, react, f):
+    """The oracle-assembled system solved by sparse LU and refined with the
+    oracle's extended-precision element-wise residual."""
+    import scipy.sparse.linalg as spla
+    from oracle import solve as osolve
+    A, C = fem1d.assemble(n, K, dense=False)
+    lu = spla.splu((diff * 4.0 * K * K * A + react * C).tocsc())
+    ref = lu.solve(f)
+    for _ in range(3):
+        r = f - osolve.apply_A(ref, n, (K,), (diff,), react, extended=True)
+        ref = ref + lu.solve(r.astype(np.float64))
+    return ref
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 7, 8, 9])
+@pytest.mark.parametrize("K", [1 << 11, 1537])
+def test_long_other_orders(fm, n, K):
+    """Every element order of the long-line kernels (n = 1 has no bubbles;
+    even n an unpaired last bubble channel), a power of two and an odd K:
+    the round trip against the oracle's mass operator and the solve of a
+    random load against the refined sparse solve."""
+    say("long orders", n, K)
+    p = fm.Plan((K,), n, (1.0,), 0.3, nrhs=1)
+    y = inputs.draw_rhs([n * K - 1], 1910 + n, "normal")
+    yt = torch.from_numpy(y).cuda()
+    back = p.debug_transform(0, -1, p.debug_transform(0, +1, yt)).cpu().numpy()
+    _, C = element_matrices(n)
+    assert np.linalg.norm(fem1d.apply_elementwise(C, back, 0) - y) / np.linalg.norm(y) < 1e-12
+    u = p.solve(yt).cpu().numpy()
+    ref = refined_sparse_solve(n, K, 1.0, 0.3, y)
+    # the reference's own accuracy: its extended-precision residual (2^-64)
+    # loses the stiffness cancellation factor of about (nK)^2
+    tol = max(1e-11, 2.0 ** -62 * (n * K) ** 2)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < tol
