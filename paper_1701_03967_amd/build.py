@@ -93,12 +93,13 @@ def build(verbose: bool = True, lib: str = LIB, build_dir: str = BUILD, defines=
                    "-c", os.path.join(CSRC, src), "-o", obj])
         if verbose:
             print(f"[build] {src} {dt:.1f}s", flush=True)
-    # kernels: line.hip four times (element counts that are powers of two or
-    # not, float32 or float64), ops.hip once; compiled in parallel
+    # kernels: line.hip six times (element counts that are powers of two,
+    # other 7-smooth counts (mixed radix), all others (Bluestein); float32 or
+    # float64), ops.hip once; compiled in parallel
     extra_any = [f"-D{d}" for d in (ANY_DEFINES if any_defines is None else any_defines)]
-    units = [("line.hip", f"line_{kind}_{real}.o", [f"-DFFTFEM_LINE_POW2={p2}", f"-DFFTFEM_LINE_REAL={real}"]
-              + (extra_any if p2 == 0 else []))
-             for kind, p2 in (("p2", 1), ("any", 0)) for real in ("float", "double")]
+    units = [("line.hip", f"line_{name}_{real}.o", [f"-DFFTFEM_LINE_KIND={kind}", f"-DFFTFEM_LINE_REAL={real}"]
+              + (extra_any if kind != 0 else []))
+             for name, kind in (("p2", 0), ("mr", 1), ("bs", 2)) for real in ("float", "double")]
     units.append(("ops.hip", "ops.o", []))
     units.append(("band.hip", "band.o", []))
     units.append(("lift.hip", "lift.o", []))

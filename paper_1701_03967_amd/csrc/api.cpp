@@ -410,7 +410,7 @@ int line_pass(fftfem_plan_t p, const Geom& gm, int mode, const void* in, int in_
   if (want_partials) p->nparts_last = (int)nblocks;
   if (p->rec) {
     record(p, sizeof(T) == 4 ? REC_LINE32 : REC_LINE64,
-           {n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, (t.K & (t.K - 1)) == 0 ? 1 : 0}, a, nblocks, lds);
+           {n, mode, upd != nullptr ? 1 : 0, gm.es > 1 ? 1 : 0, line_kind(a)}, a, nblocks, lds);
     return FFTFEM_OK;
   }
   Timed tm(p, s, std::string(mode_name(mode, upd != nullptr)) + (sizeof(T) == 4 ? "32" : "64") +

@@ -192,14 +192,12 @@ int build_graph(fftfem_batch_s* b, const double* const* f, double* const* u, hip
     switch (g.kind) {
       case REC_LINE32: {
         GroupedLaunch<float> gl{(const LineArgs<float>*)jobs, jobof, start, g.nblocks, g.lds};
-        e = g.key[4] ? launch_line_grouped_p2<float>(g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap)
-                     : launch_line_grouped_any<float>(g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap);
+        e = launch_line_grouped<float>(g.key[4], g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap);
         break;
       }
       case REC_LINE64: {
         GroupedLaunch<double> gl{(const LineArgs<double>*)jobs, jobof, start, g.nblocks, g.lds};
-        e = g.key[4] ? launch_line_grouped_p2<double>(g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap)
-                     : launch_line_grouped_any<double>(g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap);
+        e = launch_line_grouped<double>(g.key[4], g.key[0], g.key[1], g.key[2], g.key[3], gl, b->cap);
         break;
       }
       case REC_APPLY:

@@ -203,24 +203,46 @@ struct GroupedLaunch {
   size_t lds;
 };
 
+// Line-pass launchers, one per object built from line.hip: element counts
+// that are powers of two (p2), other K with prime factors <= 7 (mr, mixed
+// radix), and all others (bs, Bluestein).  line_kind() names the object a
+// line of the arguments needs.
 template <typename T>
 hipError_t launch_line_grouped_p2(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
 template <typename T>
-hipError_t launch_line_grouped_any(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
-
-// Line-pass launchers, one per object built from line.hip: element counts
-// that are powers of two, and all others.
+hipError_t launch_line_grouped_mr(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
+template <typename T>
+hipError_t launch_line_grouped_bs(int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g, hipStream_t s);
 template <typename T>
 hipError_t launch_line_p2(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
                           hipStream_t s);
 template <typename T>
-hipError_t launch_line_any(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
-                           hipStream_t s);
+hipError_t launch_line_mr(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_line_bs(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
+                          hipStream_t s);
+template <typename T>
+inline int line_kind(const LineArgs<T>& a) {
+  return (a.K & (a.K - 1)) == 0 ? 0 : (a.nrad > 0 ? 1 : 2);
+}
 template <typename T>
 inline hipError_t launch_line(int n, int mode, bool upd, const LineArgs<T>& a, int nblocks, size_t lds,
                               hipStream_t s) {
-  return (a.K & (a.K - 1)) == 0 ? launch_line_p2<T>(n, mode, upd, a, nblocks, lds, s)
-                                 : launch_line_any<T>(n, mode, upd, a, nblocks, lds, s);
+  switch (line_kind(a)) {
+    case 0: return launch_line_p2<T>(n, mode, upd, a, nblocks, lds, s);
+    case 1: return launch_line_mr<T>(n, mode, upd, a, nblocks, lds, s);
+    default: return launch_line_bs<T>(n, mode, upd, a, nblocks, lds, s);
+  }
+}
+template <typename T>
+inline hipError_t launch_line_grouped(int kind, int n, int mode, bool upd, bool lf, const GroupedLaunch<T>& g,
+                                      hipStream_t s) {
+  switch (kind) {
+    case 0: return launch_line_grouped_p2<T>(n, mode, upd, lf, g, s);
+    case 1: return launch_line_grouped_mr<T>(n, mode, upd, lf, g, s);
+    default: return launch_line_grouped_bs<T>(n, mode, upd, lf, g, s);
+  }
 }
 hipError_t launch_apply(int n, const ApplyArgs& a, int nblocks, size_t lds, hipStream_t s);
 hipError_t launch_resid2(int n, bool dd, const Resid2Args& a, hipStream_t s);

@@ -274,29 +274,31 @@ __device__ __forceinline__ void cond_solve0(const T* __restrict__ ar, const T* r
   }
 }
 
-// This file is compiled four times: with FFTFEM_LINE_POW2=1 for element counts K
-// that are powers of two (shift/mask index arithmetic, Stockham FFTs) and
-// with 0 for all other K (divisions, Bluestein DFTs).  The flag is a
-// template argument of the kernels, so the two objects define different
-// symbols.
-#ifndef FFTFEM_LINE_POW2
-#define FFTFEM_LINE_POW2 1
+// This file is compiled six times: FFTFEM_LINE_KIND = 0 for element counts K
+// that are powers of two (shift/mask index arithmetic, Stockham FFTs), 1 for
+// other K with prime factors <= 7 (divisions, mixed-radix Stockham FFTs),
+// 2 for the rest (divisions, Bluestein DFTs); each kernel object carries only
+// its own DFT, which keeps the register allocation of the general-K kernels
+// from paying for code they never run.  The kind is a template argument of
+// the kernels, so the objects define different symbols.
+#ifndef FFTFEM_LINE_KIND
+#define FFTFEM_LINE_KIND 0
 #endif
 // and once per precision (FFTFEM_LINE_REAL: float or double)
 #ifndef FFTFEM_LINE_REAL
 #define FFTFEM_LINE_REAL double
 #endif
-constexpr bool kLinePow2 = FFTFEM_LINE_POW2 != 0;
+constexpr int kLineKind = FFTFEM_LINE_KIND;
 
 // Length-K DFTs of the nfft buffers of a tile: Stockham for K a power of
 // two, mixed-radix Stockham for other K whose prime factors are at most 7,
 // Bluestein otherwise.
-template <typename T, bool INV, int NT, bool P2>
+template <typename T, bool INV, int NT, int KIND>
 __device__ __forceinline__ void line_dft(const LineArgs<T>& a, C2<T>* buf, int nfft, int ls) {
   const int lrmax = a.lrmax ? a.lrmax : 4;
-  if constexpr (P2) {
+  if constexpr (KIND == 0) {
     fft_all<T, INV, NT>(buf, nfft, a.log2K, reinterpret_cast<const C2<T>*>(a.twf), ls, lrmax);
-  } else if (a.nrad > 0) {
+  } else if constexpr (KIND == 1) {
     fft_mixed<T, INV, NT>(buf, nfft, a.K, a.radpack, a.nrad, reinterpret_cast<const C2<T>*>(a.twf), ls);
   } else {
     bluestein<T, INV, NT>(buf, nfft, a.K, a.log2L, reinterpret_cast<const C2<T>*>(a.chirp),
@@ -307,7 +309,7 @@ __device__ __forceinline__ void line_dft(const LineArgs<T>& a, C2<T>* buf, int n
 
 // Body of a line pass for tile `bid` of `nblk` tiles (the launch, or one job
 // of a grouped launch).
-template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
+template <typename T, int NORD, int MODE, bool UPD, bool LF, int KIND>
 __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nblk) {
   constexpr int kNT = LineCfg<T>::NT, kMaxTPT = LineCfg<T>::TPT, kMaxCPT = LineCfg<T>::CPT;
   if (a.flag && *a.flag) return;
@@ -492,7 +494,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
   // element tasks (g, j'), j' < K, and contraction tasks (g, kappa),
   // kappa < ceil(K/2): kappa >= 1 pairs the frequencies kappa and K - kappa,
   // kappa = 0 is the bubble block (and frequency K/2 when K is even)
-  constexpr bool pow2 = P2;
+  constexpr bool pow2 = KIND == 0;
   const int kh = (K + 1) >> 1;
   const int lkh = lk - 1;
   const int ntask = G * K;
@@ -565,7 +567,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       }
     }
     __syncthreads();
-    line_dft<T, false, kNT, P2>(a, buf, G * NB, ls);
+    line_dft<T, false, kNT, KIND>(a, buf, G * NB, ls);
   } else {
     bulk_load(a.in, a.in_f64);
     __syncthreads();
@@ -718,7 +720,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       }
     }
     __syncthreads();
-    line_dft<T, true, kNT, P2>(a, buf, G * NB, ls);
+    line_dft<T, true, kNT, KIND>(a, buf, G * NB, ls);
   } else {
   // held across a barrier: spectral results (FWD) or channel spectra (INV)
   T hw[kMaxCPT][2][NORD];
@@ -857,7 +859,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
       }
     }
     __syncthreads();
-    line_dft<T, true, kNT, P2>(a, buf, G * NB, ls);
+    line_dft<T, true, kNT, KIND>(a, buf, G * NB, ls);
   }
   }
 
@@ -928,18 +930,18 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
   }
 }
 
-template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
+template <typename T, int NORD, int MODE, bool UPD, bool LF, int KIND>
 __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel(LineArgs<T> a) {
-  line_body<T, NORD, MODE, UPD, LF, P2>(a, blockIdx.x, gridDim.x);
+  line_body<T, NORD, MODE, UPD, LF, KIND>(a, blockIdx.x, gridDim.x);
 }
 
 // Grouped launch: block b runs tile b - start[j] of job j = job_of[b].
-template <typename T, int NORD, int MODE, bool UPD, bool LF, bool P2>
+template <typename T, int NORD, int MODE, bool UPD, bool LF, int KIND>
 __global__ __launch_bounds__(LineCfg<T>::NT, LineCfg<T>::MINW) void line_kernel_grouped(
     const LineArgs<T>* __restrict__ jobs, const int* __restrict__ job_of, const int* __restrict__ start) {
   const int j = __builtin_amdgcn_readfirstlane(job_of[blockIdx.x]);
   const int b0 = __builtin_amdgcn_readfirstlane(start[j]), b1 = __builtin_amdgcn_readfirstlane(start[j + 1]);
-  line_body<T, NORD, MODE, UPD, LF, P2>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
+  line_body<T, NORD, MODE, UPD, LF, KIND>(jobs[j], (int)blockIdx.x - b0, b1 - b0);
 }
 
 template <typename F>
@@ -951,12 +953,12 @@ static void allow_lds(F* fn, size_t lds) {
 template <typename T, int NORD, int MODE, bool UPD>
 static hipError_t go(bool lf, const LineArgs<T>& a, int nblocks, size_t lds, hipStream_t s) {
   if (lf) {
-    allow_lds(line_kernel<T, NORD, MODE, UPD, true, kLinePow2>, lds);
-    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, true, kLinePow2>), dim3(nblocks), dim3(LineCfg<T>::NT),
+    allow_lds(line_kernel<T, NORD, MODE, UPD, true, kLineKind>, lds);
+    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, true, kLineKind>), dim3(nblocks), dim3(LineCfg<T>::NT),
                        lds, s, a);
   } else {
-    allow_lds(line_kernel<T, NORD, MODE, UPD, false, kLinePow2>, lds);
-    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, false, kLinePow2>), dim3(nblocks), dim3(LineCfg<T>::NT),
+    allow_lds(line_kernel<T, NORD, MODE, UPD, false, kLineKind>, lds);
+    hipLaunchKernelGGL((line_kernel<T, NORD, MODE, UPD, false, kLineKind>), dim3(nblocks), dim3(LineCfg<T>::NT),
                        lds, s, a);
   }
   return hipGetLastError();
@@ -975,12 +977,12 @@ static hipError_t launch_line_n(int mode, bool upd, const LineArgs<T>& a, int nb
 template <typename T, int NORD, int MODE, bool UPD>
 static hipError_t go_grouped(bool lf, const GroupedLaunch<T>& g, hipStream_t s) {
   if (lf) {
-    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, true, kLinePow2>, g.lds);
-    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, true, kLinePow2>), dim3(g.nblocks),
+    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, true, kLineKind>, g.lds);
+    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, true, kLineKind>), dim3(g.nblocks),
                        dim3(LineCfg<T>::NT), g.lds, s, g.jobs, g.job_of, g.start);
   } else {
-    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, false, kLinePow2>, g.lds);
-    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, false, kLinePow2>), dim3(g.nblocks),
+    allow_lds(line_kernel_grouped<T, NORD, MODE, UPD, false, kLineKind>, g.lds);
+    hipLaunchKernelGGL((line_kernel_grouped<T, NORD, MODE, UPD, false, kLineKind>), dim3(g.nblocks),
                        dim3(LineCfg<T>::NT), g.lds, s, g.jobs, g.job_of, g.start);
   }
   return hipGetLastError();
@@ -993,12 +995,15 @@ static hipError_t grouped_n(int mode, bool upd, bool lf, const GroupedLaunch<T>&
   return upd ? go_grouped<T, NORD, MID, true>(lf, g, s) : go_grouped<T, NORD, MID, false>(lf, g, s);
 }
 
-#if FFTFEM_LINE_POW2
+#if FFTFEM_LINE_KIND == 0
 #define FFTFEM_LAUNCH_LINE launch_line_p2
 #define FFTFEM_LAUNCH_GROUPED launch_line_grouped_p2
+#elif FFTFEM_LINE_KIND == 1
+#define FFTFEM_LAUNCH_LINE launch_line_mr
+#define FFTFEM_LAUNCH_GROUPED launch_line_grouped_mr
 #else
-#define FFTFEM_LAUNCH_LINE launch_line_any
-#define FFTFEM_LAUNCH_GROUPED launch_line_grouped_any
+#define FFTFEM_LAUNCH_LINE launch_line_bs
+#define FFTFEM_LAUNCH_GROUPED launch_line_grouped_bs
 #endif
 
 template <typename T>
