@@ -133,8 +133,16 @@ def profiler_kernel_name(name: str, n: int, N: int, K: int) -> str:
     upd = "true" if "upd" in head else "false"
     ax = name.rsplit("_ax", 1)[1]
     contiguous = ax.endswith("t") or int(ax.rstrip("t")) == N - 1
-    pow2 = "true" if K & (K - 1) == 0 else "false"
-    return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}, {pow2}>"
+    # the kernel object: 0 powers of two, 1 mixed radix (prime factors <= 7), 2 Bluestein
+    kind = 0 if K & (K - 1) == 0 else (1 if smooth7(K) else 2)
+    return f"line_kernel<{dtype}, {n}, {mode}, {upd}, {'false' if contiguous else 'true'}, {kind}>"
+
+
+def smooth7(K: int) -> bool:
+    for p in (2, 3, 5, 7):
+        while K % p == 0:
+            K //= p
+    return K == 1
 
 
 def measured_traffic(workload: str, kernel: str, mode: str = ""):
