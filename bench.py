@@ -663,10 +663,76 @@ def summarize_traffic(workload: str, fetch_dir: str, write_dir: str, nbytes: str
     print("\n".join(lines))
 
 
+def summarize_replay(d: str, cmd: str, out: str):
+    """profiles/<name>.txt from the kernel trace of a run that replays one
+    captured graph several times (the batched workload): the last three
+    replays (the periodic tail of the trace), each one's wall time against the
+    union of its kernels' intervals, the idle gaps between kernels, and the
+    kernels taking most of a replay."""
+    import csv
+    import glob
+    from collections import defaultdict
+    rows = []
+    for fn in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        with open(fn) as fh:
+            for r in csv.DictReader(fh):
+                if "fftfem::" in r["Kernel_Name"]:
+                    rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    names = [r[2] for r in rows]
+    n = len(names)
+    period = None
+    for cand in range(100, n // 3 + 1):
+        if names[-cand:] == names[-2 * cand:-cand] == names[-3 * cand:-2 * cand]:
+            period = cand
+            break
+    lines = ["# graph replays of the batched workload: kernel busy time against wall time, MI355X (gfx950)",
+             f"# command: (from the repository root, TMPDIR=/tmp) {cmd}",
+             "# summary: python bench.py summarize-replay <output dir> <command> <this file>",
+             f"# kernel sources sha256: {sources_sha256()}",
+             f"fftfem kernels in the trace: {n}"]
+    if period is None:
+        lines.append("no periodic tail (three identical replays) found")
+    for rep in range(3 if period else 0):
+        seg = rows[n - (rep + 1) * period: n - rep * period]
+        t0, t1 = seg[0][0], max(e for _, e, _ in seg)
+        busy, cs, ce = 0, None, None
+        for st, en, _ in seg:
+            if ce is None or st > ce:
+                if ce is not None:
+                    busy += ce - cs
+                cs, ce = st, en
+            else:
+                ce = max(ce, en)
+        busy += ce - cs
+        lines.append(f"replay -{rep + 1}: launches {period}, wall {(t1 - t0) / 1e6:.3f} ms, busy (union of kernel "
+                     f"intervals) {busy / 1e6:.3f} ms ({busy / (t1 - t0):.4f} of wall)")
+        if rep == 0:
+            last, gaps = seg[0][1], []
+            for st, en, _ in seg[1:]:
+                gaps.append(max(0, st - last))
+                last = max(last, en)
+            gaps.sort()
+            lines.append(f"  idle gaps between kernels: total {sum(gaps) / 1e6:.3f} ms, median "
+                         f"{gaps[len(gaps) // 2] / 1e3:.2f} us, p90 {gaps[int(len(gaps) * 0.9)] / 1e3:.2f} us, "
+                         f"max {gaps[-1] / 1e3:.2f} us")
+            per = defaultdict(lambda: [0, 0])
+            for st, en, nm in seg:
+                per[nm][0] += en - st
+                per[nm][1] += 1
+            lines.append("  kernels by time in the replay (ms, launches):")
+            for nm, (tt, c) in sorted(per.items(), key=lambda kv: -kv[1][0])[:20]:
+                lines.append(f"    {tt / 1e6:9.3f} {c:5d}  {nm[:120]}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic", "summarize-replay"):
         # text summaries of rocprofv3 output for profiles/ (no GPU use)
-        fn = summarize_stats if sys.argv[1] == "summarize-stats" else summarize_traffic
+        fn = {"summarize-stats": summarize_stats, "summarize-traffic": summarize_traffic,
+              "summarize-replay": summarize_replay}[sys.argv[1]]
         fn(*sys.argv[2:])
         return
     ap = argparse.ArgumentParser()
