@@ -56,11 +56,16 @@ struct fftfem_plan_s {
                              // 2: one LDS-tiled kernel (short lines)
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
   bool longK = false;        // 1D, K > 1024: the multi-pass transforms of long.hip
-  double* Wl[2] = {nullptr, nullptr};  // their work arrays: nrhs x (1 + n/2) x K complex each
-  double* ltw[4] = {nullptr, nullptr, nullptr, nullptr};  // their twiddles: sub-DFTs (K1, K2), low and high
-                                                          // parts of exp(-2 pi i m / K) (1024, K / 1024)
-  int lk1 = 0, lk2 = 0, lgc = 0, lgr = 0;
-  int64_t lD = 0;            // their DFT length: K, or Bluestein's L
+  double* Wl[2] = {nullptr, nullptr};  // their work arrays: lines x (1 + n/2) x D complex each (the
+                                       // largest over the axes; lines: nrhs in 1D, M of the other axis in 2D)
+  // per axis: the four-step split of the DFT length D (K, or Bluestein's L),
+  // the tile shapes, and the twiddles: sub-DFTs (K1, K2), low and high parts
+  // of exp(-2 pi i m / D) (1024, D / 1024)
+  struct LongAxis {
+    int lk1 = 0, lk2 = 0, lgc = 0, lgr = 0;
+    int64_t D = 0;
+    double* tw[4] = {nullptr, nullptr, nullptr, nullptr};
+  } lax[FFTFEM_MAX_DIMS];
                              // then 2 (K_0 - 1) x (size / M_0) node pairs
   bool tr2d = false;         // 2D: run the axis-0 pass on a transposed copy
   bool trfused = false;      // ... made by the axis-1 passes' own stores and loads (no transposes)
@@ -877,16 +882,19 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     if (d.n_axis[i] > kMaxLineOrder) return FFTFEM_ENOTIMPL;
   const bool algb = (d.flags & FFTFEM_ALGORITHM_B) != 0;
   // a line-kernel tile holds at most kLineTasks element tasks; longer lines
-  // take the multi-pass transforms (one axis, float64, K up to kLongMaxK,
-  // algorithm (a), not in batches)
+  // take the multi-pass transforms: one axis, or two axes both longer than
+  // a tile, K up to kLongMaxK, float64, algorithm (a), not in batches
   bool longK = false;
-  for (int i = 0; i < d.N; ++i)
-    if (d.K[i] > kLineTasks) {
-      if (d.N == 1 && d.K[0] <= kLongMaxK && d.precision == FFTFEM_FP64 && !algb && !cache)
-        longK = true;
-      else
-        return FFTFEM_ENOTIMPL;
+  {
+    int nlong = 0;
+    for (int i = 0; i < d.N; ++i) nlong += d.K[i] > kLineTasks ? 1 : 0;
+    if (nlong > 0) {
+      bool ok = (d.N == 1 || (d.N == 2 && nlong == 2)) && d.precision == FFTFEM_FP64 && !algb && !cache;
+      for (int i = 0; i < d.N; ++i) ok = ok && d.K[i] <= kLongMaxK;
+      if (!ok) return FFTFEM_ENOTIMPL;
+      longK = true;
     }
+  }
   if (algb && (d.precision != FFTFEM_FP64 || cache)) return FFTFEM_ENOTIMPL;
   fftfem_plan_s* p = new (std::nothrow) fftfem_plan_s();
   if (!p) return FFTFEM_ENOMEM;
@@ -1018,31 +1026,37 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   if (!rc && p->tr2d && d.precision == FFTFEM_FP64)
     rc = dev_alloc(p, (void**)&p->W64b, (size_t)p->size * sizeof(double));
   if (!rc && p->longK) {
-    // the DFT length D (K, or Bluestein's L), work arrays of D slots per
-    // buffer, and the twiddles of the four-step passes: every (D/K_i)-th
-    // entry of the length-D table for the sub-DFTs, its first 1024 entries
-    // and every 1024th for the products
-    const AxisTables& t = p->host[0];
-    const bool pow2 = is_pow2(p->K[0]);
-    const int64_t D = pow2 ? p->K[0] : t.L;
-    const std::vector<double>& twD = pow2 ? t.twf : t.twl;
-    const int lk = ilog2(D);
-    p->lk1 = lk / 2;
-    p->lk2 = lk - p->lk1;
-    p->lD = D;
-    long_tiles(p->lk1, p->lk2, &p->lgc, &p->lgr);
-    const size_t w = (size_t)p->nrhs * (1 + p->nd[0] / 2) * 2 * (size_t)D;
-    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
-    const int64_t len[4] = {int64_t(1) << p->lk1, int64_t(1) << p->lk2, 1024, D / 1024};
-    const int64_t st[4] = {D / len[0], D / len[1], 1, 1024};
-    for (int i = 0; i < 4 && !rc; ++i) {
-      std::vector<double> tw((size_t)2 * len[i]);
-      for (int64_t q = 0; q < len[i]; ++q) {
-        tw[2 * q] = twD[2 * q * st[i]];
-        tw[2 * q + 1] = twD[2 * q * st[i] + 1];
+    // per axis: the DFT length D (K, or Bluestein's L) and the twiddles of
+    // the four-step passes (every (D/K_i)-th entry of the length-D table for
+    // the sub-DFTs, its first 1024 entries and every 1024th for the
+    // products); work arrays of D slots per buffer for the most lines any
+    // axis transforms at once
+    size_t w = 0;
+    for (int ax = 0; ax < p->N && !rc; ++ax) {
+      const AxisTables& t = p->host[ax];
+      auto& la = p->lax[ax];
+      const bool pow2 = is_pow2(p->K[ax]);
+      const int64_t D = pow2 ? p->K[ax] : t.L;
+      const std::vector<double>& twD = pow2 ? t.twf : t.twl;
+      const int lk = ilog2(D);
+      la.lk1 = lk / 2;
+      la.lk2 = lk - la.lk1;
+      la.D = D;
+      long_tiles(la.lk1, la.lk2, &la.lgc, &la.lgr);
+      const int64_t lines = p->N == 1 ? p->nrhs : p->M[1 - ax];
+      w = std::max(w, (size_t)lines * (1 + p->nd[ax] / 2) * 2 * (size_t)D);
+      const int64_t len[4] = {int64_t(1) << la.lk1, int64_t(1) << la.lk2, 1024, D / 1024};
+      const int64_t st[4] = {D / len[0], D / len[1], 1, 1024};
+      for (int i = 0; i < 4 && !rc; ++i) {
+        std::vector<double> tw((size_t)2 * len[i]);
+        for (int64_t q = 0; q < len[i]; ++q) {
+          tw[2 * q] = twD[2 * q * st[i]];
+          tw[2 * q + 1] = twD[2 * q * st[i] + 1];
+        }
+        rc = upload<double>(p, &la.tw[i], tw);
       }
-      rc = upload<double>(p, &p->ltw[i], tw);
     }
+    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
   }
   p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 4 : 8);
   for (int i = 0; i < p->ntmp && !rc; ++i)
@@ -1146,48 +1160,53 @@ static int band_chain(fftfem_plan_t p, const double* f, double* u, hipStream_t s
 }
 
 // The FC_n transform (FWD: lines -> spectral coefficients), its inverse
-// (INV) or both with the division by react + the axis' denominators in
-// between (MID: the 1D solve) of nlines consecutive lines of a long-line
-// plan, by the multi-pass kernels of long.hip.  The K-point DFTs of the
-// channel buffers: K a power of two, a column and a row pass (wa -> wb);
-// otherwise Bluestein's four passes (wa -> wb -> wa) with the chirp factors
-// of the direction (conjugated for the inverse DFT).
-static int long_transform(fftfem_plan_t p, int mode, const double* in, double* out, int64_t nlines,
-                          hipStream_t s, int* bad = nullptr) {
+// (INV) or both with the division by react + the axis' denominators (+
+// mu_line[l] per line) in between (MID) of nlines consecutive lines along
+// `axis` of a long-line plan, by the multi-pass kernels of long.hip.  The
+// K-point DFTs of the channel buffers: K a power of two, a column and a row
+// pass (wa -> wb); otherwise Bluestein's four passes (wa -> wb -> wa) with
+// the chirp factors of the direction (conjugated for the inverse DFT).
+// NaN / Inf written by the scatter sets bit 2 of bad[l / lpf].
+static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in, double* out, int64_t nlines,
+                          hipStream_t s, int* bad = nullptr, int64_t lpf = 1, const double* mu_line = nullptr) {
+  const auto& la = p->lax[axis];
   LongArgs a{};
   a.bad = bad;
-  a.K = (int)p->K[0];
-  a.ls = (int)p->lD;
-  a.lk1 = p->lk1;
-  a.lk2 = p->lk2;
-  a.K1 = 1 << p->lk1;
-  a.K2 = 1 << p->lk2;
-  a.M = p->M[0];
+  a.lpf = lpf;
+  a.mu_line = mu_line;
+  a.K = (int)p->K[axis];
+  a.ls = (int)la.D;
+  a.lk1 = la.lk1;
+  a.lk2 = la.lk2;
+  a.K1 = 1 << la.lk1;
+  a.K2 = 1 << la.lk2;
+  a.M = p->M[axis];
   a.nlines = nlines;
-  a.Q = tab<double>(p, 0, 0);
-  a.twm = tab<double>(p, 0, 2);
-  a.twd = tab<double>(p, 0, 3);
-  a.mu = tab<double>(p, 0, 4);
-  a.chirp = tab<double>(p, 0, 5);
-  a.bhat = tab<double>(p, 0, 6);
-  a.tw1 = p->ltw[0];
-  a.tw2 = p->ltw[1];
-  a.twlo = p->ltw[2];
-  a.twhi = p->ltw[3];
-  a.lgc = p->lgc;
-  a.lgr = p->lgr;
+  a.Q = tab<double>(p, axis, 0);
+  a.twm = tab<double>(p, axis, 2);
+  a.twd = tab<double>(p, axis, 3);
+  a.mu = tab<double>(p, axis, 4);
+  a.chirp = tab<double>(p, axis, 5);
+  a.bhat = tab<double>(p, axis, 6);
+  a.tw1 = la.tw[0];
+  a.tw2 = la.tw[1];
+  a.twlo = la.tw[2];
+  a.twhi = la.tw[3];
+  a.lgc = la.lgc;
+  a.lgr = la.lgr;
   // lines per contraction thread: enough threads to fill the chip (about
   // 2^18), the rest of the lines in a loop that reuses the cached Q rows
   a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nlines, nlines * ((a.K + 1) / 2) >> 18));
   a.react = p->desc.react;
   double* const W0 = p->Wl[0];
   double* const W1 = p->Wl[1];
-  const bool pow2 = is_pow2(p->K[0]);
-  const int n = p->nd[0];
+  const bool pow2 = is_pow2(p->K[axis]);
+  const int n = p->nd[axis];
+  const std::string ax = "_ax" + std::to_string(axis);
   int rc = FFTFEM_OK;
   auto step = [&](int st, bool inv, double* w, double* o, const char* name) {
     if (rc) return;
-    Timed tm(p, s, name);
+    Timed tm(p, s, p->N == 1 ? std::string(name) : name + ax);
     rc = from_hip(launch_long(n, st, inv, a, w, o, s));
   };
   // DFTs of the buffers of W0 (forward or inverse); returns the array that
@@ -1234,6 +1253,31 @@ static int long_transform(fftfem_plan_t p, int mode, const double* in, double* o
   return rc;
 }
 
+// The last axis of a long-line plan for every right-hand side: one call for
+// one axis (the lines are the right-hand sides), one per right-hand side for
+// two (the work arrays hold one right-hand side's M0 rows).
+static int long_last_axis(fftfem_plan_t p, int mode, const double* in, double* out, hipStream_t s) {
+  if (p->N == 1) return long_transform(p, 0, mode, in, out, p->nrhs, s);
+  int rc = FFTFEM_OK;
+  for (int r = 0; r < p->nrhs && !rc; ++r)
+    rc = long_transform(p, 1, mode, in + (size_t)r * p->size, out + (size_t)r * p->size, p->M[0], s);
+  return rc;
+}
+
+// Axis 0 of a two-axis long-line plan, one right-hand side: in (M0 x M1) is
+// transposed into the plan's scratch, its M1 contiguous lines transformed
+// there (mode as long_transform), and transposed back into out (which may
+// be in).
+static int long_axis0_2d(fftfem_plan_t p, int mode, const double* in, double* out, hipStream_t s,
+                         const double* mu_line = nullptr) {
+  double* T = p->tmp[0];
+  const int64_t M0 = p->M[0], M1 = p->M[1];
+  int rc = from_hip(launch_transpose<double>(in, T, 1, M0, M1, s));
+  if (!rc) rc = long_transform(p, 0, mode, T, T, M1, s, nullptr, 1, mu_line);
+  if (!rc) rc = from_hip(launch_transpose<double>(T, out, 1, M1, M0, s));
+  return rc;
+}
+
 int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
   if (!p || !f || !u) return FFTFEM_EINVAL;
   size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
@@ -1241,10 +1285,22 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
   p->last = s;
   int rc = FFTFEM_OK;
   if (p->longK) {
-    // float64, no refinement: reset the statistics, then every right-hand
-    // side at once
+    // float64, no refinement: reset the statistics; one axis: every
+    // right-hand side at once; two axes: per right-hand side, forward along
+    // axis 1 (rows), the middle step along axis 0 on the transposed array
+    // with the axis-1 denominators per line, the inverse along axis 1
     rc = from_hip(launch_reset_many(p->flags, p->stats, kStatsLen, p->nrhs, s));
-    if (!rc) rc = long_transform(p, MID, f, u, p->nrhs, s, p->flags);
+    if (p->N == 1) {
+      if (!rc) rc = long_transform(p, 0, MID, f, u, p->nrhs, s, p->flags);
+      return rc;
+    }
+    for (int r = 0; r < p->nrhs && !rc; ++r) {
+      const double* fr = f + (size_t)r * p->size;
+      double* ur = u + (size_t)r * p->size;
+      rc = long_transform(p, 1, FWD, fr, ur, p->M[0], s);
+      if (!rc) rc = long_axis0_2d(p, MID, ur, ur, s, tab<double>(p, 1, 4));
+      if (!rc) rc = long_transform(p, 1, INV, ur, ur, p->M[0], s, p->flags + r, p->M[0]);
+    }
     return rc;
   }
   for (int r = 0; r < p->nrhs && !rc; ++r) {
@@ -1454,10 +1510,14 @@ int fftfem_coefficients(fftfem_plan_t p, const double* in, double* out, int kind
   p->last = s;
   int rc = FFTFEM_OK;
   if (p->longK) {
-    // long lines: every right-hand side's line in one multi-pass transform
+    // long lines: the rows of every right-hand side along the last axis,
+    // then (two axes) axis 0 per right-hand side
     for (int r = 0; r < p->nrhs && !rc && kind == 0; ++r)
       rc = mass_apply(p, in + (size_t)r * p->size, nullptr, out + (size_t)r * p->size, 1.0, s);
-    return rc ? rc : long_transform(p, FWD, kind == 0 ? out : in, out, p->nrhs, s);
+    if (!rc) rc = long_last_axis(p, FWD, kind == 0 ? out : in, out, s);
+    for (int r = 0; r < p->nrhs && !rc && p->N == 2; ++r)
+      rc = long_axis0_2d(p, FWD, out + (size_t)r * p->size, out + (size_t)r * p->size, s);
+    return rc;
   }
   for (int r = 0; r < p->nrhs && !rc; ++r) {
     const size_t o = (size_t)r * p->size;
@@ -1561,7 +1621,16 @@ int fftfem_synthesize(fftfem_plan_t p, const double* in, double* out, hipStream_
   const size_t bytes = (size_t)p->size * p->nrhs * sizeof(double);
   if (in != out && overlap(in, out, bytes)) return FFTFEM_EINVAL;
   p->last = s;
-  if (p->longK) return long_transform(p, INV, in, out, p->nrhs, s);
+  if (p->longK) {
+    // (two axes) axis 0 per right-hand side first, then the rows of every
+    // right-hand side along the last axis
+    int rc = FFTFEM_OK;
+    const double* src = in;
+    for (int r = 0; r < p->nrhs && !rc && p->N == 2; ++r)
+      rc = long_axis0_2d(p, INV, in + (size_t)r * p->size, out + (size_t)r * p->size, s);
+    if (p->N == 2) src = out;
+    return rc ? rc : long_last_axis(p, INV, src, out, s);
+  }
   int rc = FFTFEM_OK;
   for (int r = 0; r < p->nrhs && !rc; ++r) {
     const size_t o = (size_t)r * p->size;
@@ -1619,10 +1688,15 @@ int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in,
   int mode = dir > 0 ? FWD : (dir < 0 ? INV : MID);
   p->last = s;
   if (p->longK) {
-    // long lines: float64 only, every right-hand side's line
+    // long lines: float64 only, every right-hand side; the last axis' rows
+    // directly, axis 0 of a two-axis plan through the transposed array
     if (dtype != 0) return FFTFEM_ENOTIMPL;
     if (in != out && overlap(in, out, (size_t)p->size * p->nrhs * sizeof(double))) return FFTFEM_EINVAL;
-    return long_transform(p, mode, in, out, p->nrhs, s);
+    if (axis == p->N - 1) return long_last_axis(p, mode, in, out, s);
+    int rc = FFTFEM_OK;
+    for (int r = 0; r < p->nrhs && !rc; ++r)
+      rc = long_axis0_2d(p, mode, in + (size_t)r * p->size, out + (size_t)r * p->size, s);
+    return rc;
   }
   Geom g = natural_geom(p, axis, false);
   if (dtype == 0) return line_pass<double>(p, g, mode, in, 1, out, 1, nullptr, nullptr, s, false);

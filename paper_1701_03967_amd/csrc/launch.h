@@ -133,7 +133,9 @@ struct LongArgs {
   const double* bhat;     // and L complex: the spectrum of conj(chirp) (zero-padded, cyclic) / L
   const double* mu;       // M: the axis' spectral denominators (divide)
   double react;
-  int* bad;               // scatter: when set, bit 2 of bad[l] marks NaN / Inf in line l
+  int* bad;               // scatter: when set, bit 2 of bad[l / lpf] marks NaN / Inf in line l
+  int64_t lpf;            // lines per flag (1: one flag per line)
+  const double* mu_line;  // divide: when set, mu_line[l] is added to line l's denominators
   int lgc, lgr;           // log2 of the columns per column tile and of the rows per row tile (long_tiles)
   int lpt;                // lines per contraction thread
   int pre, post;          // Bluestein factors of the column loads and the row stores (long.hip)

@@ -449,17 +449,19 @@ __global__ __launch_bounds__(kLongThreads) void long_scatter_kernel(LongArgs a) 
     bool nonfinite = false;
 #pragma unroll
     for (int m = 0; m < n; ++m) nonfinite |= !(hv[m] - hv[m] == 0.0);
-    if (nonfinite) atomicOr(a.bad + l, 2);
+    if (nonfinite) atomicOr(a.bad + l / a.lpf, 2);
   }
 }
 
 // Spectral coefficients of every line divided by react + mu (the axis'
-// denominators): the middle step of a 1D solve.
+// denominators) + mu_line[l] (the other axis' denominator of line l, when
+// the lines are those of a transposed two-axis array): the middle step of a
+// solve.
 __global__ __launch_bounds__(kLongThreads) void long_divide_kernel(LongArgs a) {
   const int64_t t = (int64_t)blockIdx.x * kLongThreads + threadIdx.x;
   if (t >= a.nlines * a.M) return;
-  const int64_t i = t % a.M;
-  a.out[t] = a.in[t] / (a.react + a.mu[i]);
+  const int64_t l = t / a.M, i = t - l * a.M;
+  a.out[t] = a.in[t] / (a.react + a.mu[i] + (a.mu_line ? a.mu_line[l] : 0.0));
 }
 
 static hipError_t grid_launch_check(int64_t threads, unsigned* nb) {
@@ -516,7 +518,7 @@ hipError_t launch_long(int n, int step, bool inv, const LongArgs& a, double* w, 
   const bool pow2 = (a.K & (a.K - 1)) == 0;
   if (a.K < 2 || a.K > (1 << 20) || a.K1 != 1 << a.lk1 || a.K2 != 1 << a.lk2 || a.lk1 < 1 || a.lk2 < 1 ||
       a.lk1 > 11 || a.lk2 > 11 || (pow2 ? D != a.K : D < 2 * a.K - 1) || a.ls != D ||
-      D > (1 << (2 * kLongTwBits + 1)) || a.nlines < 1 || a.lpt < 1)
+      D > (1 << (2 * kLongTwBits + 1)) || a.nlines < 1 || a.lpt < 1 || (a.bad && a.lpf < 1))
     return hipErrorInvalidValue;
   // the Bluestein factors: only for K not a power of two, with their tables
   if (a.pre < 0 || a.pre > 4 || a.post < 0 || a.post > 2 || (pow2 && (a.pre || a.post)) ||

@@ -67,6 +67,10 @@ def _plan_ex(**kw):
     ({"N": 1, "K": (1 << 21,)}, -7), ({"N": 1, "K": ((1 << 20) + 1,)}, -7),
     ({"N": 1, "K": (2048,), "precision": 1}, -7), ({"N": 1, "K": (3001,), "precision": 2}, -7),
     ({"N": 1, "K": (2048,), "flags": 1}, -7), ({"N": 1, "K": (1025,), "flags": 1}, -7),
+    # two axes beyond one tile: both of them, float64, algorithm (a); three axes: not built
+    ({"K": (2048, 1100), "precision": 1}, -7), ({"K": (2048, 1100), "flags": 1}, -7),
+    ({"N": 3, "K": (1100, 1100, 1100), "diff": (1.0, 1.0, 1.0)}, -7),
+    ({"N": 3, "K": (1100, 8, 8), "diff": (1.0, 1.0, 1.0)}, -7),
 ])
 def test_invalid_arguments_rejected_on_host(kw, code):
     rc, h = _plan_ex(**kw)
@@ -180,3 +184,15 @@ def test_tune_table_file_round_trip(tmp_path):
             fftfem.tune_load(str(f))
     with pytest.raises(fftfem.FftfemError):
         fftfem.tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_two_long_axes_accepted_on_host():
+    """A two-axis float64 plan with both axes beyond one tile passes the host
+    checks and builds its tables; without a GPU it then fails at the device
+    query, not with FFTFEM_ENOTIMPL."""
+    rc, h = _plan_ex(K=(1100, 1030), n=2)
+    assert rc != -7
+    if rc != 0:
+        assert not h.value
+    else:
+        fftfem.lib().fftfem_destroy(h)

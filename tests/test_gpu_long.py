@@ -224,3 +224,83 @@ def test_long_other_orders(fm, n, K):
     # loses the stiffness cancellation factor of about (nK)^2
     tol = max(1e-11, 2.0 ** -62 * (n * K) ** 2)
     assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < tol
+
+
+# --- two axes, both longer than a tile (axis 1 directly, axis 0 through the
+# transposed array) ---------------------------------------------------------
+
+_plans2 = {}
+
+
+def plan2(fm, K, n, diff=(1.0, 1.0), react=0.0, X=(1.0, 1.0), nrhs=1):
+    key = (K, n, diff, react, X, nrhs)
+    if key not in _plans2:
+        say("plan 2d", key)
+        _plans2[key] = fm.Plan(K, n, diff, react, X=X, nrhs=nrhs)
+    return _plans2[key]
+
+
+def test_long2d_solve_sine(fm):
+    """-div(diff grad u) + react u = f on (0, 1) x (0, 2) with
+    u = sin(pi x) sin(2 pi y / 2): the load is the product of the oracle's 1D
+    element-by-element loads (the tensor Gauss rule factorizes), times the
+    eigenvalue lam; the FEM error of order h^6 is far below rounding."""
+    K, n, diff, react, X = (1100, 1030), 5, (1.0, 0.6), 0.5, (1.0, 2.0)
+    say("long 2d sine", K, n)
+    p = plan2(fm, K, n, diff, react, X)
+    m = (1, 2)
+    lam = sum(d * (mm * np.pi / x) ** 2 for d, mm, x in zip(diff, m, X)) + react
+    l0 = loads.load_vector_1d(lambda x: np.sin(m[0] * np.pi * x / X[0]), n, K[0], X=X[0])
+    l1 = loads.load_vector_1d(lambda y: np.sin(m[1] * np.pi * y / X[1]), n, K[1], X=X[1])
+    f = lam * np.outer(l0, l1)
+    ue, _ = loads.sin_product(m, diff, react, X=list(X))
+    want = loads.interpolate(ue, n, K, X=list(X))
+    u = p.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert np.abs(u - want).max() < 1e-11
+    assert p.stats()["converged"]
+
+
+def test_long2d_transforms_and_apply(fm):
+    """Expansion coefficients of loads are the forward transforms along axis
+    1 then axis 0 (same kernels, bit for bit); synthesis inverts the
+    coefficients of values (Theorem 2, item 3); the operator apply matches
+    the oracle's element-wise operator; two right-hand sides."""
+    from oracle import solve as osolve
+    K, n, diff, react = (1100, 1030), 2, (1.0, 1.3), 0.4
+    say("long 2d transforms", K, n)
+    p = plan2(fm, K, n, diff, react, nrhs=2)
+    y = inputs.draw_rhs(list(p.shape), 1920, "normal", nrhs=2)
+    yt = torch.from_numpy(y).cuda()
+    c = p.coefficients(yt, kind="loads")
+    c2 = p.debug_transform(0, +1, p.debug_transform(1, +1, yt))
+    assert torch.equal(c, c2)
+    w = p.synthesize(c)
+    back = p.coefficients(w, kind="values")
+    assert (torch.linalg.norm(back - c) / torch.linalg.norm(c)).item() < 1e-12
+    Au = p.apply_A(yt).cpu().numpy()
+    for r in range(2):
+        ref = osolve.apply_A(y[r], n, K, diff, react)
+        assert np.linalg.norm(Au[r] - ref) / np.linalg.norm(ref) < 1e-13, r
+    # A u = f for the solve of a smooth u's load: the solve inverts the apply
+    xs = [np.linspace(0, 1, m + 2)[1:-1] for m in p.shape]
+    u0 = np.outer(np.sin(np.pi * xs[0]) * (1 + xs[0]), np.sin(3 * np.pi * xs[1]))
+    f0 = osolve.apply_A(u0, n, K, diff, react, extended=True).astype(np.float64)
+    p1 = plan2(fm, K, n, diff, react)
+    u = p1.solve(torch.from_numpy(np.ascontiguousarray(f0)).cuda()).cpu().numpy()
+    assert np.linalg.norm(u - u0) / np.linalg.norm(u0) < 1e-10
+
+
+def test_long2d_reports_nonfinite(fm):
+    K, n = (1100, 1030), 2
+    say("long 2d nan", K, n)
+    p = plan2(fm, K, n, nrhs=2)
+    f = inputs.draw_rhs(list(p.shape), 1921, "normal", nrhs=2)
+    f[1, 5, 7] = np.nan
+    u = p.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert np.isfinite(u[0].cpu().numpy()).all()
+    st = p.stats()
+    assert not st["converged"] and st["stop"] == "nonfinite", st
+    f[1, 5, 7] = 0.0
+    p.solve(torch.from_numpy(f).cuda())
+    assert p.stats()["converged"]
