@@ -453,6 +453,61 @@ def run_batch(args, torch, fm):
     print(json.dumps(line))
 
 
+def run_long2d(args, torch, fm):
+    """2D solves with both axes longer than one LDS tile (n = 9, K per axis
+    2048 and 4096: 3.4e8 and 1.36e9 unknowns), float64 by algorithm (a)
+    through the multi-pass long-line transforms: the element-count scaling
+    beyond the C3 size.  Synthetic N(0,1) load, resident in HBM; mean of the
+    timed solves and per-kernel times."""
+    n = 9
+    rows = []
+    for Kd in (2048, 4096):
+        plan = fm.Plan((Kd, Kd), n, (1.0, 1.0), 0.0)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(Kd)
+        f = torch.randn(plan.shape, generator=g, dtype=torch.float64, device="cuda")
+        u = torch.empty_like(f)
+        for _ in range(args.warmup):
+            plan.solve(f, u)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(3, args.steps // 5)
+        e0.record()
+        for _ in range(steps):
+            plan.solve(f, u)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        plan.get_timing()
+        plan.set_timing(True)
+        plan.solve(f, u)
+        torch.cuda.synchronize()
+        kt = {k: v[0] for k, v in plan.get_timing().items()}
+        plan.set_timing(False)
+        st = plan.stats()
+        rows.append({"K": [Kd, Kd], "unknowns": f.numel(), "ms": ms, "unknowns_per_s": f.numel() / (ms * 1e-3),
+                     "finite": bool(torch.isfinite(u).all().item()), "stop": st["stop"], "kernels_ms": kt})
+        print(f"[bench] long2d K={Kd}: {ms:.2f} ms/solve ({f.numel()} unknowns)", file=sys.stderr, flush=True)
+        del plan, f, u
+    line = {
+        "metric": "2D solve time & unknowns/s beyond one LDS tile per axis, n=9, float64",
+        "value": rows[-1]["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": max(3, args.steps // 5),
+        "warmup": args.warmup,
+        "ms_per_step": rows[-1]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "long2d_n9", "n": 9, "value": "the largest K"},
+        "per_K": rows,
+    }
+    print(json.dumps(line))
+
+
 def run_heat(args, torch, fm):
     """Implicit Euler time stepping on the C3 mesh (2D, n = 9, K = 1024,
     diff (1, 1)) with tau = 1e-3 (react = 1000, the batched workload's heat
@@ -773,6 +828,9 @@ def main():
         return
     if args.workload == "heat":
         run_heat(args, torch, fm)
+        return
+    if args.workload == "long2d":
+        run_long2d(args, torch, fm)
         return
     if args.workload == "c5_batch":
         run_batch(args, torch, fm)

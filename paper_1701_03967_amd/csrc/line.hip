@@ -82,106 +82,6 @@ __device__ __forceinline__ T other_den(const LineArgs<T>& a, int64_t base) {
   return d;
 }
 
-// Contractions of the fused MID pass: the forward contraction, division and
-// inverse contraction of the two frequencies k and K - k of a task run as
-// two interleaved chains.  Left alone, the scheduler would issue the n^2
-// table loads of all four contractions up front (several hundred live
-// registers: one wave per SIMD, or spills).  Here the lane offset used by
-// row c + D goes through empty asm statements that also consume that
-// chain's accumulators after row c, so each chain has D rows in flight, and
-// a contraction's first rows wait for `dep` (the previous stage's result).
-template <typename V>
-__device__ __forceinline__ uint32_t after(uint32_t o, V v) {
-  __asm__ volatile("" : "+v"(o) : "v"(v));
-  return o;
-}
-
-// The same, tied to all n accumulators (the scheduler would otherwise finish
-// only the one the asm consumes and keep the other columns' inputs live).
-template <typename T, int NORD>
-__device__ __forceinline__ uint32_t after_all(uint32_t o, const T* v) {
-#pragma unroll
-  for (int l = 0; l < NORD; ++l) __asm__ volatile("" : "+v"(o) : "v"(v[l]));
-  return o;
-}
-
-#ifndef FFTFEM_MID_ROWS
-#define FFTFEM_MID_ROWS 2
-#endif
-
-template <typename T, int NORD>
-__device__ __forceinline__ void contract_fwd2(rsrc_t Q, int K, int ka, int kb, const T* cha,
-                                              const T* chb, T* wa, T* wb, T dep) {
-  constexpr int D = FFTFEM_MID_ROWS < NORD ? FFTFEM_MID_ROWS : NORD;
-  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
-  T qa[NORD][NORD], qb[NORD][NORD];
-  {
-    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-#pragma unroll
-      for (int l = 0; l < NORD; ++l) {
-        qa[c][l] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
-        qb[c][l] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
-      }
-  }
-#pragma unroll
-  for (int l = 0; l < NORD; ++l) wa[l] = wb[l] = 0;
-#pragma unroll
-  for (int c = 0; c < NORD; ++c) {
-#pragma unroll
-    for (int l = 0; l < NORD; ++l) {
-      wa[l] += qa[c][l] * cha[c];
-      wb[l] += qb[c][l] * chb[c];
-    }
-    if (c + D < NORD) {
-      const uint32_t pa = after_all<T, NORD>(oa, wa), pb = after_all<T, NORD>(ob, wb);
-#pragma unroll
-      for (int l = 0; l < NORD; ++l) {
-        qa[c + D][l] = ldq<T>(Q, pa, qrow<T, NORD>(c + D, l, K));
-        qb[c + D][l] = ldq<T>(Q, pb, qrow<T, NORD>(c + D, l, K));
-      }
-    }
-  }
-}
-
-template <typename T, int NORD>
-__device__ __forceinline__ void contract_inv2(rsrc_t Q, int K, int ka, int kb, const T* wa,
-                                              const T* wb, T* cha, T* chb, T dep) {
-  constexpr int D = FFTFEM_MID_ROWS < NORD ? FFTFEM_MID_ROWS : NORD;
-  const uint32_t oa = (uint32_t)ka * (uint32_t)sizeof(T), ob = (uint32_t)kb * (uint32_t)sizeof(T);
-  T qa[NORD][NORD], qb[NORD][NORD];
-  {
-    const uint32_t pa = after(oa, dep), pb = after(ob, dep);
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-#pragma unroll
-      for (int l = 0; l < NORD; ++l) {
-        qa[c][l] = ldq<T>(Q, pa, qrow<T, NORD>(c, l, K));
-        qb[c][l] = ldq<T>(Q, pb, qrow<T, NORD>(c, l, K));
-      }
-  }
-#pragma unroll
-  for (int c = 0; c < NORD; ++c) {
-    T acca = 0, accb = 0;
-#pragma unroll
-    for (int l = 0; l < NORD; ++l) {
-      acca += qa[c][l] * wa[l];
-      accb += qb[c][l] * wb[l];
-    }
-    cha[c] = acca;
-    chb[c] = accb;
-    if (c + D < NORD) {
-      const uint32_t pa = after(oa, acca), pb = after(ob, accb);
-#pragma unroll
-      for (int l = 0; l < NORD; ++l) {
-        qa[c + D][l] = ldq<T>(Q, pa, qrow<T, NORD>(c + D, l, K));
-        qb[c + D][l] = ldq<T>(Q, pb, qrow<T, NORD>(c + D, l, K));
-      }
-    }
-  }
-}
-
 // The fused MID pass needs, per frequency k, x = Q_k diag(1/(bd + mu_kl))
 // Q_k^T y, i.e. the solution of the shifted n x n system
 // (coef A_k + bd C_k) x = y of the projected pencil.  Its bubble blocks do

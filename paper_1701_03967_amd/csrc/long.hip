@@ -237,10 +237,14 @@ __device__ __forceinline__ void long_contract_fwd_line(const LongArgs& a, int64_
     channel_vec<double, NORD>(nodal_post<double, false>(B, K, kb, twd, false), cb, ca, chb);
   }
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
-  contract_fwd<double, NORD>(qtab, K, ka, cha, wa);
-  if (hasb) {
-    contract_fwd<double, NORD>(qtab, K, kb, chb, wb);
-  } else {
+  if (!hasb) {
+#pragma unroll
+    for (int c = 0; c < NORD; ++c) chb[c] = 0.0;
+  }
+  // both frequencies as two chains with a few table rows in flight (without
+  // a second frequency the chain repeats the first one's block, unused)
+  contract_fwd2<double, NORD>(qtab, K, ka, hasb ? kb : ka, cha, chb, wa, wb, cha[0]);
+  if (!hasb) {
 #pragma unroll
     for (int c = 0; c < NORD; ++c) wb[c] = 0.0;
   }
@@ -325,10 +329,8 @@ __device__ __forceinline__ void long_contract_inv_line(const LongArgs& a, int64_
   const int ka = kap, kb = kap == 0 ? kh : K - kap;
   double h0[NORD], h1[NORD];
   const rsrc_t qtab = table_rsrc(a.Q, (uint32_t)((size_t)K * n * n));
-  contract_inv<double, NORD>(qtab, K, ka, wa, h0);
-  if (hasb) {
-    contract_inv<double, NORD>(qtab, K, kb, wb, h1);
-  } else {
+  contract_inv2<double, NORD>(qtab, K, ka, hasb ? kb : ka, wa, wb, h0, h1, wa[0] + wb[0]);
+  if (!hasb) {
 #pragma unroll
     for (int c = 0; c < NORD; ++c) h1[c] = 0.0;
   }
