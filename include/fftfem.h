@@ -82,9 +82,10 @@ enum {
 /* Full plan description.  Fields left zero take the documented defaults. */
 typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
-  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; one-axis
-                                     FFTFEM_FP64 plans of algorithm (a) also accept any K up to
-                                     2^20: multi-pass transforms, not in batches) */
+  int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; FFTFEM_FP64
+                                     plans of algorithm (a), not in batches, also accept any K up to
+                                     2^20 on one axis, or on two axes when both exceed 1024:
+                                     multi-pass transforms) */
   int n;                          /* element order (every axis without n_axis), 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */
@@ -193,8 +194,9 @@ int fftfem_plan_tables(const fftfem_plan_t p, int axis, double* lam, double* Q);
  * inverse F_n transform (spectral -> physical); dir = 0: forward, divide by
  * the axis-only denominator react + diff[d] 4/h_d^2 lambda, inverse.  dtype:
  * 0 = compute in float64, 1 = compute in float32.  in and out may be equal.
- * One-axis plans with K > 1024 (float64 only) transform the lines of all nrhs
- * right-hand sides, by the multi-pass path.
+ * Plans with K > 1024 (float64 only) transform by the multi-pass path; axis
+ * 0 of a two-axis such plan goes through a transposed copy in the plan's
+ * scratch.
  */
 int fftfem_debug_transform(fftfem_plan_t p, int axis, int dir, const double* in, double* out,
                            int dtype, hipStream_t s);
