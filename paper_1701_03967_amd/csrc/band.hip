@@ -43,14 +43,20 @@ struct BandLine {
   double s, d;
 };
 
+// sigma of a line: react + the other axes' terms.
+__device__ __forceinline__ double band_sigma(const BandArgs& a, int64_t line) {
+  double sg = a.react;
+  for (int e = 0; e < a.nother; ++e) sg += a.mu_o[e][(line / a.so[e]) % a.Mo[e]];
+  return sg;
+}
+
 template <int NORD>
 __device__ __forceinline__ void band_line(const BandArgs& a, int64_t line, BandLine& L) {
   constexpr int nb = NORD - 1;
   constexpr int oL = nb * nb, oAL = oL + nb, oCL = oAL + nb, oAR = oCL + nb, oCR = oAR + nb, otL = oCR + nb,
                 otX = otL + nb, oN = otX + nb;
   const double* __restrict__ tb = a.tab;
-  double sg = a.react;
-  for (int e = 0; e < a.nother; ++e) sg += a.mu_o[e][(line / a.so[e]) % a.Mo[e]];
+  const double sg = band_sigma(a, line);
   const double cf = a.coef;
   // a = cf a0 + sg PL, b = -cf a0 + sg PX
   double PL = tb[oN + 0], PX = tb[oN + 1];
@@ -189,110 +195,195 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
 // bubble recovery are independent per element and run one thread per
 // (line, group of kBandEPTc or kBandEPTb elements); only the node elimination, K - 1
 // values per line, stays sequential.
-//   1. cond: y (in) -> w: z in the bubble slots, the condensed node
-//      right-hand sides g in the node slots (a thread recomputes the last
-//      z of the element before its group);
+//   1. cond: y (in) -> the condensed node right-hand sides g in w's node
+//      slots (a thread recomputes the last z of the element before its
+//      group); w's bubble slots are not written;
 //   2. nodes: the tridiagonal node system on w's node slots, forward
 //      elimination (g' and the pivots as pairs into a compact array) and
 //      back substitution: the node values x in w's node slots;
-//   3. back: x_B = V (z - (h_L x_L + h_R x_R) / (.)) and the node values into out.
+//   3. back: z again from y's bubble slots, x_B = V (z - (h_L x_L + h_R
+//      x_R) / (.)) and the node values into out (out may be in: a thread
+//      reads only the bubble slots of its own elements).
+// Recomputing z (n - 1 squared multiply-adds per element) instead of
+// storing it saves a write and a read of the bubble values: 8 (n - 1) / n
+// bytes per value of the array each way.
 // elements per thread of the condensation and of the bubble recovery
 constexpr int kBandEPTc = 16, kBandEPTb = 4;
+
+// The condensation and the bubble recovery keep of the per-line constants
+// only r in registers.  The table (V and the coupling coefficients,
+// (n - 1)(n + 4) values) is copied to LDS and read at each use through an
+// offset the compiler cannot see (zero), one column of V at a time (a
+// scheduling barrier after each): otherwise the scheduler loads the whole
+// table into vector registers at once (three waves per SIMD instead of five).
+// The couplings h_L, h_R are one multiply-add each where they are used.
+template <int NORD>
+__device__ __forceinline__ const double* band_table_lds(const BandArgs& a, double* stb) {
+  constexpr int nb = NORD - 1, ntab = nb * (nb + 5);
+  for (int i = threadIdx.x; i < ntab; i += blockDim.x) stb[i] = a.tab[i];
+  __syncthreads();
+  return stb;
+}
+
+__device__ __forceinline__ const double* band_opaque(const double* p) {
+  int z0 = 0;
+  asm volatile("" : "+v"(z0));
+  return p + z0;
+}
+
+// h_L . z and h_R . z of one element, z = diag(r) V^T y (y: its bubble values).
+template <int NORD>
+__device__ __forceinline__ void band_couple(const double* stb, const double* r, double cf, double sg,
+                                            const double* y, double& pL, double& pR) {
+  constexpr int nb = NORD - 1;
+  constexpr int oL = nb * nb, oAL = oL + nb, oCL = oAL + nb, oAR = oCL + nb, oCR = oAR + nb;
+  const double* tb = band_opaque(stb);
+  pL = pR = 0.0;
+#pragma unroll
+  for (int m = 0; m < nb; ++m) {
+    double tm = 0.0;
+#pragma unroll
+    for (int i = 0; i < nb; ++i) tm += tb[i * nb + m] * y[i];
+    const double z = r[m] * tm;
+    pL += (cf * tb[oAL + m] + sg * tb[oCL + m]) * z;
+    pR += (cf * tb[oAR + m] + sg * tb[oCR + m]) * z;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// The bubble values of the element at p (stride S) and the node value before it.
+template <int NORD>
+__device__ __forceinline__ void band_load_elem(const double* p, int64_t S, bool node, double* y, double& yn) {
+  constexpr int nb = NORD - 1;
+#pragma unroll
+  for (int i = 0; i < nb; ++i) y[i] = p[(int64_t)i * S];
+  yn = node ? p[-S] : 0.0;
+}
 
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_cond_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  __shared__ double stb_[nb * (nb + 5) > 0 ? nb * (nb + 5) : 1];
+  const double* stb = band_table_lds<NORD>(a, stb_);
   const int64_t ng = (a.K + kBandEPTc - 1) / kBandEPTc;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= a.nlines * ng) return;
   const int64_t line = t % a.nlines, grp = t / a.nlines;
   const int64_t S = a.nlines;
-  BandLine L;
-  band_line<NORD>(a, line, L);
+  const double sg = band_sigma(a, line), cf = a.coef;
+  double r[NB];
+#pragma unroll
+  for (int m = 0; m < nb; ++m) r[m] = 1.0 / (cf * stb[nb * nb + m] + sg);
   const double* in = a.in + line;
   double* w = a.cp + line;
   const int e0 = (int)grp * kBandEPTc, e1 = min(a.K, e0 + kBandEPTc);
   double carry = 0.0;  // -h_R . z of the element before
+  double y[NB], yn;
   if (e0 > 0 && nb > 0) {
-    double z[NB];
-    band_z<NORD>(a.tab, L, in + (int64_t)(e0 - 1) * NORD * S, S, z);
-#pragma unroll
-    for (int m = 0; m < nb; ++m) carry -= L.hR[m] * z[m];
+    double pL, pR;
+    band_load_elem<NORD>(in + (int64_t)(e0 - 1) * NORD * S, S, false, y, yn);
+    band_couple<NORD>(stb, r, cf, sg, y, pL, pR);
+    carry = -pR;
   }
+  // the loads of element e + 1 are issued before the arithmetic of element e
+  band_load_elem<NORD>(in + (int64_t)e0 * NORD * S, S, e0 > 0, y, yn);
   for (int e = e0; e < e1; ++e) {
     const int64_t b0 = (int64_t)e * NORD;
-    double z[NB];
+    double y1[NB] = {}, yn1 = 0.0;
+    if (e + 1 < e1) band_load_elem<NORD>(in + (b0 + NORD) * S, S, true, y1, yn1);
     double pL = 0.0, pR = 0.0;
-    if constexpr (nb > 0) band_z<NORD>(a.tab, L, in + b0 * S, S, z);
-#pragma unroll
-    for (int m = 0; m < nb; ++m) {
-      pL += L.hL[m] * z[m];
-      pR += L.hR[m] * z[m];
-      w[(b0 + m) * S] = z[m];
-    }
-    if (e > 0) w[(b0 - 1) * S] = in[(b0 - 1) * S] + carry - pL;
+    if constexpr (nb > 0) band_couple<NORD>(stb, r, cf, sg, y, pL, pR);
+    if (e > 0) w[(b0 - 1) * S] = yn + carry - pL;
     carry = -pR;
+#pragma unroll
+    for (int i = 0; i < nb; ++i) y[i] = y1[i];
+    yn = yn1;
   }
 }
 
-// Node elimination, one thread per line: the forward sweep loads kBandNF
-// right-hand sides ahead, the backward sweep kBandNB pairs (g', pivot).
-// One-wave workgroups spread the few waves (2D: M_2 / 64) over as many CUs
-// as possible: each wave's sweeps are bound by its own memory latency, and
-// four waves sharing a CU's load path took 0.26 ms against 0.18 ms at C3.
-constexpr int kBandNF = 24, kBandNB = 24, kBandNodesBlock = 64;
+// Node elimination by a twisted factorization, two lanes per line: lane
+// t < 32 eliminates nodes 1 .. m - 1 downward and lane t + 32 nodes
+// K - 1 .. m + 1 upward (m = K / 2), each with the recurrence of band_kernel
+// (the node matrix reads the same from either end, so both halves have the
+// same non-negative pivot terms).  The middle node then has the equation
+//   (d + rho_{m-1} e_{m-1} + rho'_{m+1} e'_{m+1}) x_m = g_m + s g'_{m-1} + s g''_{m+1},
+// again a sum of non-negative terms in the pivot; both lanes form it in the
+// same order, and each substitutes back outward from x_m.  Each lane's chain
+// of divisions is half a line long, and the grid has twice as many waves.
+// The sweeps load kBandNF right-hand sides, then kBandNB pairs (g', pivot),
+// one block ahead.  One-wave workgroups spread the few waves (2D: M_2 / 32)
+// over as many CUs as possible: each wave's sweeps are bound by its own
+// memory latency.
+constexpr int kBandNF = 24, kBandNB = 24, kBandNodesBlock = 64, kBandNodesLines = 32;
 
 template <int NORD>
 __global__ __launch_bounds__(kBandNodesBlock) void band_nodes_kernel(BandArgs a) {
-  const int64_t line = (int64_t)blockIdx.x * kBandNodesBlock + threadIdx.x;
-  if (line >= a.nlines) return;
+  const int half = threadIdx.x >> 5;  // 0: top half, 1: bottom half
+  const int64_t line = (int64_t)blockIdx.x * kBandNodesLines + (threadIdx.x & 31);
+  const bool live = line < a.nlines;  // every lane takes part in the exchange
   const int64_t S = a.nlines;
   BandLine L;
-  band_line<NORD>(a, line, L);
+  band_line<NORD>(a, live ? line : 0, L);
   const double sn = L.s, dn = L.d;
   const int nn = a.K - 1;  // node j (1..K-1) at slot j NORD - 1 of w
+  const int m = (nn + 1) >> 1;
+  const int cnt = half ? nn - m : m - 1;  // nodes this lane eliminates
+  const int jf = half ? nn : 1, dj = half ? -1 : 1;
   const int64_t st = (int64_t)NORD * S;
-  double* wn = a.cp + line + (int64_t)(NORD - 1) * S;  // node 1
+  double* wn = a.cp + (live ? line : 0) + (int64_t)(NORD - 1) * S;  // node 1
   // (g'_j, pivot_j) of node j at pair (j - 1) S + line: one 16-byte access per step
-  double2* pr = reinterpret_cast<double2*>(a.pr) + line;
+  double2* pr = reinterpret_cast<double2*>(a.pr) + (live ? line : 0);
+  auto slot = [&](int i) { return (int64_t)(jf + dj * i - 1); };  // 0-based node of step i
   double ex = sn, rho = 1.0, gprev = 0.0;  // e_1 = d + 1 * s
   {
     double g[kBandNF], gn[kBandNF];
 #pragma unroll
-    for (int i = 0; i < kBandNF; ++i) g[i] = i < nn ? wn[(int64_t)i * st] : 0.0;
-    for (int j0 = 0; j0 < nn; j0 += kBandNF) {
+    for (int i = 0; i < kBandNF; ++i) g[i] = live && i < cnt ? wn[slot(i) * st] : 0.0;
+    for (int i0 = 0; i0 < cnt; i0 += kBandNF) {
 #pragma unroll
-      for (int i = 0; i < kBandNF; ++i) gn[i] = j0 + kBandNF + i < nn ? wn[(int64_t)(j0 + kBandNF + i) * st] : 0.0;
+      for (int i = 0; i < kBandNF; ++i) {
+        const int k = i0 + kBandNF + i;
+        gn[i] = live && k < cnt ? wn[slot(k) * st] : 0.0;
+      }
 #pragma unroll
       for (int i = 0; i < kBandNF; ++i)
-        if (j0 + i < nn) {
+        if (i0 + i < cnt) {
           ex = dn + rho * ex;
           const double inv = 1.0 / (sn + ex);
           rho = sn * inv;
           gprev = (g[i] + sn * gprev) * inv;
-          pr[(int64_t)(j0 + i) * S] = make_double2(gprev, rho);
+          if (live) pr[slot(i0 + i) * S] = make_double2(gprev, rho);
         }
 #pragma unroll
       for (int i = 0; i < kBandNF; ++i) g[i] = gn[i];
     }
   }
-  // backward: x_j = g'_j + rho_j x_{j+1} into w's node slots, likewise one block ahead
-  double x = 0.0;
-  const int last = nn - 1;
+  // the middle node: this half's terms and the other half's, summed top first
+  const double gm = live ? wn[(int64_t)(m - 1) * st] : 0.0;
+  const double cme = rho * ex, rme = sn * gprev;
+  const double coth = __shfl_xor(cme, 32), roth = __shfl_xor(rme, 32);
+  const double ctop = half ? coth : cme, cbot = half ? cme : coth;
+  const double rtop = half ? roth : rme, rbot = half ? rme : roth;
+  double x = (gm + rtop + rbot) / (dn + ctop + cbot);
+  if (live && half == 0) wn[(int64_t)(m - 1) * st] = x;
+  // back substitution outward: x_j = g'_j + pivot_j x_(j toward m), one block ahead
   double2 q[kBandNB], qn[kBandNB];
 #pragma unroll
-  for (int i = 0; i < kBandNB; ++i) q[i] = last - i >= 0 ? pr[(int64_t)(last - i) * S] : make_double2(0.0, 0.0);
-  for (int j0 = last; j0 >= 0; j0 -= kBandNB) {
+  for (int i = 0; i < kBandNB; ++i) {
+    const int k = cnt - 1 - i;
+    q[i] = live && k >= 0 ? pr[slot(k) * S] : make_double2(0.0, 0.0);
+  }
+  for (int k0 = cnt - 1; k0 >= 0; k0 -= kBandNB) {
 #pragma unroll
     for (int i = 0; i < kBandNB; ++i) {
-      const int j = j0 - kBandNB - i;
-      qn[i] = j >= 0 ? pr[(int64_t)j * S] : make_double2(0.0, 0.0);
+      const int k = k0 - kBandNB - i;
+      qn[i] = live && k >= 0 ? pr[slot(k) * S] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int i = 0; i < kBandNB; ++i)
-      if (j0 - i >= 0) {
+      if (k0 - i >= 0) {
         x = q[i].x + q[i].y * x;
-        wn[(int64_t)(j0 - i) * st] = x;
+        if (live) wn[slot(k0 - i) * st] = x;
       }
 #pragma unroll
     for (int i = 0; i < kBandNB; ++i) q[i] = qn[i];
@@ -302,15 +393,20 @@ __global__ __launch_bounds__(kBandNodesBlock) void band_nodes_kernel(BandArgs a)
 template <int NORD>
 __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
+  constexpr int oL = nb * nb, oAL = oL + nb, oCL = oAL + nb, oAR = oCL + nb, oCR = oAR + nb;
+  __shared__ double stb_[nb * (nb + 5) > 0 ? nb * (nb + 5) : 1];
+  const double* stb = band_table_lds<NORD>(a, stb_);
   const int64_t ng = (a.K + kBandEPTb - 1) / kBandEPTb;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= a.nlines * ng) return;
   const int64_t line = t % a.nlines, grp = t / a.nlines;
   const int64_t S = a.nlines;
-  BandLine L;
-  band_line<NORD>(a, line, L);
-  const double* __restrict__ tb = a.tab;
+  const double sg = band_sigma(a, line), cf = a.coef;
+  double r[NB];
+#pragma unroll
+  for (int m = 0; m < nb; ++m) r[m] = 1.0 / (cf * stb[oL + m] + sg);
   const double* w = a.cp + line;
+  const double* in = a.in + line;
   double* out = a.out + line;
   const int e0 = (int)grp * kBandEPTb, e1 = min(a.K, e0 + kBandEPTb);
   double xL = e0 > 0 ? w[((int64_t)e0 * NORD - 1) * S] : 0.0;
@@ -319,15 +415,26 @@ __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
     const double xR = e + 1 < a.K ? w[(b0 + NORD - 1) * S] : 0.0;
     if (e > 0) out[(b0 - 1) * S] = xL;
     if constexpr (nb > 0) {
-      double v[NB];
+      const double* tb = band_opaque(stb);
+      double y[NB], v[NB];
 #pragma unroll
-      for (int m = 0; m < nb; ++m) v[m] = w[(b0 + m) * S] - L.r[m] * (L.hL[m] * xL + L.hR[m] * xR);
+      for (int i = 0; i < nb; ++i) y[i] = in[(b0 + i) * S];
+#pragma unroll
+      for (int m = 0; m < nb; ++m) {
+        double tm = 0.0;
+#pragma unroll
+        for (int i = 0; i < nb; ++i) tm += tb[i * nb + m] * y[i];
+        const double hL = cf * tb[oAL + m] + sg * tb[oCL + m], hR = cf * tb[oAR + m] + sg * tb[oCR + m];
+        v[m] = r[m] * tm - r[m] * (hL * xL + hR * xR);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll
       for (int i = 0; i < nb; ++i) {
         double x = 0.0;
 #pragma unroll
         for (int m = 0; m < nb; ++m) x += tb[i * nb + m] * v[m];
         out[(b0 + i) * S] = x;
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     xL = xR;
@@ -335,13 +442,14 @@ __global__ __launch_bounds__(kBlock) void band_back_kernel(BandArgs a) {
 }
 
 // The same solve in one kernel for short lines (K G <= 1024): a workgroup
-// takes G adjacent lines; thread t works on line t mod G and on elements
-// t / G + (256 / G) i.  The condensation keeps z in registers and leaves the
+// of 256 threads takes G adjacent lines; thread t works on line t mod G and
+// on elements t / G + (256 / G) i.  The condensation keeps z in registers and leaves the
 // node couplings h_L . z, h_R . z and the node loads in LDS; G threads then
 // eliminate the node systems from LDS, and every thread recovers its
 // elements' bubbles and nodes and stores them.  y is read once and x written
 // once, with no work array.
-constexpr int kBandTileEPT = 4;  // elements per thread: K G <= 256 kBandTileEPT
+constexpr int kBandTileBlock = 256;  // threads per workgroup of the tiled form
+constexpr int kBandTileEPT = 4;      // elements per thread: K G <= kBandTileBlock kBandTileEPT
 
 // 1 / x on the node elimination's dependency chain (x > 0 normal).
 __device__ __forceinline__ double band_inv(double x) { return 1.0 / x; }
@@ -359,10 +467,13 @@ __device__ __forceinline__ unsigned band_tile_of(unsigned b, unsigned nblk) {
 }
 
 template <int NORD, int G>
-__global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
+__global__ __launch_bounds__(kBandTileBlock, 3) void band_tile_kernel(BandArgs a) {
   constexpr int nb = NORD - 1, NB = nb > 0 ? nb : 1;
-  constexpr int STEP = kBlock / G;
+  constexpr int oL = nb * nb, oAL = oL + nb, oCL = oAL + nb, oAR = oCL + nb, oCR = oAR + nb;
+  constexpr int STEP = kBandTileBlock / G;
   extern __shared__ double band_lds[];
+  __shared__ double stb_[nb * (nb + 5) > 0 ? nb * (nb + 5) : 1];
+  const double* stb = band_table_lds<NORD>(a, stb_);
   const int K = a.K;
   double* pl = band_lds;                    // [K][G]: h_L . z of element e
   double* pq = pl + (size_t)K * G;          // [K][G]: h_R . z
@@ -372,11 +483,14 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
   const int64_t line = (int64_t)band_tile_of(blockIdx.x, gridDim.x) * G + l;
   const bool live = line < a.nlines;
   const int64_t S = a.nlines;
-  const double* __restrict__ tb = a.tab;
-  BandLine L;
-  band_line<NORD>(a, live ? line : 0, L);
+  const double sg = band_sigma(a, live ? line : 0), cf = a.coef;
+  double r[NB];
+#pragma unroll
+  for (int m = 0; m < nb; ++m) r[m] = 1.0 / (cf * stb[oL + m] + sg);
   const double* in = a.in + (live ? line : 0);
   double* out = a.out + (live ? line : 0);
+  // z of this thread's elements stay in registers across the node solve;
+  // the table is read from LDS one column at a time (as in band_couple)
   double zr[kBandTileEPT][NB];
 #pragma unroll
   for (int i = 0; i < kBandTileEPT; ++i) {
@@ -385,11 +499,19 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
       const int64_t b0 = (int64_t)e * NORD;
       double pL = 0.0, pR = 0.0;
       if constexpr (nb > 0) {
-        band_z<NORD>(tb, L, in + b0 * S, S, zr[i]);
+        const double* tb = band_opaque(stb);
+        double y[NB];
+#pragma unroll
+        for (int j = 0; j < nb; ++j) y[j] = in[(b0 + j) * S];
 #pragma unroll
         for (int m = 0; m < nb; ++m) {
-          pL += L.hL[m] * zr[i][m];
-          pR += L.hR[m] * zr[i][m];
+          double tm = 0.0;
+#pragma unroll
+          for (int j = 0; j < nb; ++j) tm += tb[j * nb + m] * y[j];
+          zr[i][m] = r[m] * tm;
+          pL += (cf * tb[oAL + m] + sg * tb[oCL + m]) * zr[i][m];
+          pR += (cf * tb[oAR + m] + sg * tb[oCR + m]) * zr[i][m];
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       pl[e * G + l] = pL;
@@ -399,7 +521,17 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
   }
   __syncthreads();
   if (tid < G && live) {
-    const double sn = L.s, dn = L.d;
+    // s and d of the node system as in band_line, from the r already held
+    constexpr int otL = oCR + nb, otX = otL + nb, oN = otX + nb;
+    const double* __restrict__ tb = a.tab;
+    double PL = tb[oN + 0], PX = tb[oN + 1];
+#pragma unroll
+    for (int m = 0; m < nb; ++m) {
+      const double cl = tb[oCL + m], cr = tb[oCR + m];
+      PL -= r[m] * (cf * tb[otL + m] + sg * cl * cl);
+      PX -= r[m] * (cf * tb[otX + m] + sg * cl * cr);
+    }
+    const double sn = cf * tb[oN + 2] - sg * PX, dn = 2.0 * sg * (PL + PX);
     double ex = sn, rho = 1.0, gprev = 0.0;
     for (int j = 1; j < K; ++j) {
       const double g = yn[j * G + l] - pq[(j - 1) * G + l] - pl[j * G + l];
@@ -427,15 +559,20 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
       const double xR = e + 1 < K ? yn[(e + 1) * G + l] : 0.0;
       if (e > 0) out[(b0 - 1) * S] = xL;
       if constexpr (nb > 0) {
+        const double* tb = band_opaque(stb);
         double w[NB];
 #pragma unroll
-        for (int m = 0; m < nb; ++m) w[m] = zr[i][m] - L.r[m] * (L.hL[m] * xL + L.hR[m] * xR);
+        for (int m = 0; m < nb; ++m) {
+          const double hL = cf * tb[oAL + m] + sg * tb[oCL + m], hR = cf * tb[oAR + m] + sg * tb[oCR + m];
+          w[m] = zr[i][m] - r[m] * (hL * xL + hR * xR);
+        }
 #pragma unroll
-        for (int r = 0; r < nb; ++r) {
+        for (int j = 0; j < nb; ++j) {
           double x = 0.0;
 #pragma unroll
-          for (int m = 0; m < nb; ++m) x += tb[r * nb + m] * w[m];
-          out[(b0 + r) * S] = x;
+          for (int m = 0; m < nb; ++m) x += tb[j * nb + m] * w[m];
+          out[(b0 + j) * S] = x;
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -444,8 +581,8 @@ __global__ __launch_bounds__(kBlock, 3) void band_tile_kernel(BandArgs a) {
 
 // Lines per workgroup of the tiled form for K elements (0: not applicable).
 int band_tile_lines(int K) {
-  if (16 * K <= kBlock * kBandTileEPT) return 16;
-  if (8 * K <= kBlock * kBandTileEPT) return 8;
+  if (16 * K <= kBandTileBlock * kBandTileEPT) return 16;
+  if (8 * K <= kBandTileBlock * kBandTileEPT) return 8;
   return 0;
 }
 
@@ -458,10 +595,10 @@ hipError_t launch_band_tile(int n, const BandArgs& a, hipStream_t s) {
   switch (n * 100 + G) {
 #define FFTFEM_CASE(N)                                                                                    \
   case N * 100 + 16:                                                                                      \
-    hipLaunchKernelGGL((band_tile_kernel<N, 16>), dim3((unsigned)nblk), dim3(kBlock), lds, s, a);         \
+    hipLaunchKernelGGL((band_tile_kernel<N, 16>), dim3((unsigned)nblk), dim3(kBandTileBlock), lds, s, a);         \
     return hipGetLastError();                                                                             \
   case N * 100 + 8:                                                                                       \
-    hipLaunchKernelGGL((band_tile_kernel<N, 8>), dim3((unsigned)nblk), dim3(kBlock), lds, s, a);          \
+    hipLaunchKernelGGL((band_tile_kernel<N, 8>), dim3((unsigned)nblk), dim3(kBandTileBlock), lds, s, a);          \
     return hipGetLastError();
     FFTFEM_CASE(1)
     FFTFEM_CASE(2)
@@ -483,7 +620,7 @@ hipError_t launch_band_split(int n, int step, const BandArgs& a, hipStream_t s) 
     return hipErrorInvalidValue;
   const int64_t ept = step == 0 ? kBandEPTc : kBandEPTb;
   const int64_t nb_el = (a.nlines * ((a.K + ept - 1) / ept) + kBlock - 1) / kBlock;
-  const int64_t nb_ln = (a.nlines + kBandNodesBlock - 1) / kBandNodesBlock;
+  const int64_t nb_ln = (a.nlines + kBandNodesLines - 1) / kBandNodesLines;
   if (nb_el > 0x7fffffff || nb_ln > 0x7fffffff) return hipErrorInvalidValue;
   if (step == 1 && a.K < 2) return hipSuccess;  // no nodes
   switch (n) {
