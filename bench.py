@@ -64,12 +64,16 @@ def kernel_bytes(name: str, size: int, N: int, n0: int = 9) -> float:
     if name.startswith("band"):
         # algorithm (b) along axis 0 (order n0).  One-sweep kernel: the first
         # sweep reads y and writes z and the node pivots, the second reads
-        # them and writes x.  Three-kernel form: cond reads y and writes z and
-        # the node right-hand sides, back reads them and writes x, nodes
-        # moves the node values (1/n0 of the array) through the elimination:
-        # read g, write g' and the pivot, read both, write x.  Tiled kernel
-        # (short lines): y read once, x written once.
-        if name.startswith("bandcond") or name.startswith("bandback") or name.startswith("bandtile"):
+        # them and writes x.  Three-kernel form: cond reads y and writes the
+        # node right-hand sides (1/n0 of the array), nodes moves the node
+        # values through the elimination (read g, write g' and the pivot,
+        # read both, write x), back reads y and the node values and writes
+        # x.  Tiled kernel (short lines): y read once, x written once.
+        if name.startswith("bandcond"):
+            return size * (8.0 + 8.0 / n0)
+        if name.startswith("bandback"):
+            return size * (16.0 + 8.0 / n0)
+        if name.startswith("bandtile"):
             return size * 16.0
         if name.startswith("bandnodes"):
             return size * 48.0 / n0
