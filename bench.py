@@ -459,13 +459,15 @@ def run_batch(args, torch, fm):
 
 def run_long2d(args, torch, fm):
     """2D solves with both axes longer than one LDS tile (n = 9, K per axis
-    2048 and 4096: 3.4e8 and 1.36e9 unknowns), float64 by algorithm (a)
-    through the multi-pass long-line transforms: the element-count scaling
-    beyond the C3 size.  Synthetic N(0,1) load, resident in HBM; mean of the
-    timed solves and per-kernel times."""
+    2048, 4096 and 11000: 3.4e8, 1.36e9 and 9.8e9 unknowns, the last filling
+    most of the 288 GB of HBM: f, u and the plan's transposed copy at 78.4 GB
+    each), float64 by algorithm (a) through the multi-pass long-line
+    transforms: the element-count scaling beyond the C3 size.  Synthetic
+    N(0,1) load, resident in HBM; mean of the timed solves and per-kernel
+    times."""
     n = 9
     rows = []
-    for Kd in (2048, 4096):
+    for Kd in (2048, 4096, 11000):
         plan = fm.Plan((Kd, Kd), n, (1.0, 1.0), 0.0)
         g = torch.Generator(device="cuda")
         g.manual_seed(Kd)
@@ -489,10 +491,14 @@ def run_long2d(args, torch, fm):
         kt = {k: v[0] for k, v in plan.get_timing().items()}
         plan.set_timing(False)
         st = plan.stats()
+        # finiteness in blocks of rows (no full-size temporary)
+        finite = all(bool(torch.isfinite(u[r0:r0 + 4096]).all().item()) for r0 in range(0, u.shape[0], 4096))
         rows.append({"K": [Kd, Kd], "unknowns": f.numel(), "ms": ms, "unknowns_per_s": f.numel() / (ms * 1e-3),
-                     "finite": bool(torch.isfinite(u).all().item()), "stop": st["stop"], "kernels_ms": kt})
+                     "finite": finite, "stop": st["stop"], "kernels_ms": kt,
+                     "workspace_bytes": plan.workspace_bytes()})
         print(f"[bench] long2d K={Kd}: {ms:.2f} ms/solve ({f.numel()} unknowns)", file=sys.stderr, flush=True)
         del plan, f, u
+        torch.cuda.empty_cache()
     line = {
         "metric": "2D solve time & unknowns/s beyond one LDS tile per axis, n=9, float64",
         "value": rows[-1]["unknowns_per_s"],

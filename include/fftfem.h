@@ -85,7 +85,10 @@ typedef struct {
   int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; FFTFEM_FP64
                                      plans of algorithm (a), not in batches, also accept any K up to
                                      2^20 on one axis, or on two axes when both exceed 1024:
-                                     multi-pass transforms) */
+                                     multi-pass transforms, whose two work arrays hold up to
+                                     8 GiB each and take the lines in chunks beyond that; a
+                                     two-axis plan of one order keeps one full-size scratch
+                                     array) */
   int n;                          /* element order (every axis without n_axis), 1..FFTFEM_MAX_ORDER */
   double diff[FFTFEM_MAX_DIMS];   /* diffusion per axis, > 0 */
   double react;                   /* reaction coefficient */

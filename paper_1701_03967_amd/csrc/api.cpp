@@ -57,7 +57,8 @@ struct fftfem_plan_s {
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
   bool longK = false;        // 1D, K > 1024: the multi-pass transforms of long.hip
   double* Wl[2] = {nullptr, nullptr};  // their work arrays: lines x (1 + n/2) x D complex each (the
-                                       // largest over the axes; lines: nrhs in 1D, M of the other axis in 2D)
+                                       // largest over the axes) for long_chunk lines at a time
+  int64_t long_chunk = 0;              // lines per pass (of nrhs in 1D, M of the other axis in 2D)
   // per axis: the four-step split of the DFT length D (K, or Bluestein's L),
   // the tile shapes, and the twiddles: sub-DFTs (K1, K2), low and high parts
   // of exp(-2 pi i m / D) (1024, D / 1024)
@@ -609,6 +610,7 @@ int operator_apply(fftfem_plan_t p, const double* u, const double* f, void* out,
   int rc;
   p->phase = ph;
   if (out_kind == 1 && fused2d(p)) return resid2(p, u, f, (double*)out, true, flag, s);
+  if (p->N == 2 && !T[3]) return FFTFEM_ENOTIMPL;  // long-line plan: no planes for the two-pass form
   if (fused3d(p)) {
     rc = resid3p(p, u, true, flag, s);
     if (rc) return rc;
@@ -993,7 +995,7 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
   size_t elt = d.precision == FFTFEM_FP64 ? sizeof(double) : sizeof(float);
   if (d.N == 2) {
     int G0 = choose_G(p->nd[0], p->K[0], elt, p->size / p->M[0]);
-    p->tr2d = (size_t)G0 * elt < 64;
+    p->tr2d = (size_t)G0 * elt < 64 && !p->longK;  // long-line plans take no line passes
     // float64: the axis-1 passes store and load the transposed layout
     // themselves (measured at n = 9, K = 1024: 3.38 ms against 3.54 ms with
     // the two transposes); float32: the transposes are cheaper (4-byte values)
@@ -1029,9 +1031,12 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     // per axis: the DFT length D (K, or Bluestein's L) and the twiddles of
     // the four-step passes (every (D/K_i)-th entry of the length-D table for
     // the sub-DFTs, its first 1024 entries and every 1024th for the
-    // products); work arrays of D slots per buffer for the most lines any
-    // axis transforms at once
-    size_t w = 0;
+    // products); work arrays of D slots per buffer for long_chunk lines:
+    // all the lines an axis transforms at once when that takes at most
+    // kLongWorkBytes per array, else chunks of lines (FFTFEM_LONG_CHUNK sets
+    // a smaller chunk)
+    size_t per = 0;
+    int64_t lines_max = 1;
     for (int ax = 0; ax < p->N && !rc; ++ax) {
       const AxisTables& t = p->host[ax];
       auto& la = p->lax[ax];
@@ -1044,7 +1049,8 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
       la.D = D;
       long_tiles(la.lk1, la.lk2, &la.lgc, &la.lgr);
       const int64_t lines = p->N == 1 ? p->nrhs : p->M[1 - ax];
-      w = std::max(w, (size_t)lines * (1 + p->nd[ax] / 2) * 2 * (size_t)D);
+      lines_max = std::max(lines_max, lines);
+      per = std::max(per, (size_t)(1 + p->nd[ax] / 2) * 2 * (size_t)D);
       const int64_t len[4] = {int64_t(1) << la.lk1, int64_t(1) << la.lk2, 1024, D / 1024};
       const int64_t st[4] = {D / len[0], D / len[1], 1, 1024};
       for (int i = 0; i < 4 && !rc; ++i) {
@@ -1056,9 +1062,19 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
         rc = upload<double>(p, &la.tw[i], tw);
       }
     }
-    for (int i = 0; i < 2 && !rc; ++i) rc = dev_alloc(p, (void**)&p->Wl[i], w * sizeof(double));
+    int64_t chunk = std::max<int64_t>(1, (int64_t)(kLongWorkBytes / (per * sizeof(double))));
+    if (const char* e = std::getenv("FFTFEM_LONG_CHUNK")) {
+      const long long v = std::atoll(e);
+      if (v > 0) chunk = std::min<int64_t>(chunk, v);
+    }
+    p->long_chunk = std::min(chunk, lines_max);
+    for (int i = 0; i < 2 && !rc; ++i)
+      rc = dev_alloc(p, (void**)&p->Wl[i], (size_t)p->long_chunk * per * sizeof(double));
   }
-  p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? 4 : 8);
+  // full-size scratch: the operator passes' planes (2D: four, 3D: eight);
+  // a two-axis long-line plan with one order uses only the first (the
+  // transposed copy; its operator apply is the fused pass)
+  p->ntmp = d.N == 1 ? 0 : (d.N == 2 ? (p->longK && p->nd[0] == p->nd[1] ? 1 : 4) : 8);
   for (int i = 0; i < p->ntmp && !rc; ++i)
     rc = dev_alloc(p, (void**)&p->tmp[i], (size_t)p->size * sizeof(double));
   if (!rc) {
@@ -1171,9 +1187,7 @@ static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in,
                           hipStream_t s, int* bad = nullptr, int64_t lpf = 1, const double* mu_line = nullptr) {
   const auto& la = p->lax[axis];
   LongArgs a{};
-  a.bad = bad;
   a.lpf = lpf;
-  a.mu_line = mu_line;
   a.K = (int)p->K[axis];
   a.ls = (int)la.D;
   a.lk1 = la.lk1;
@@ -1181,7 +1195,6 @@ static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in,
   a.K1 = 1 << la.lk1;
   a.K2 = 1 << la.lk2;
   a.M = p->M[axis];
-  a.nlines = nlines;
   a.Q = tab<double>(p, axis, 0);
   a.twm = tab<double>(p, axis, 2);
   a.twd = tab<double>(p, axis, 3);
@@ -1194,9 +1207,6 @@ static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in,
   a.twhi = la.tw[3];
   a.lgc = la.lgc;
   a.lgr = la.lgr;
-  // lines per contraction thread: enough threads to fill the chip (about
-  // 2^18), the rest of the lines in a loop that reuses the cached Q rows
-  a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nlines, nlines * ((a.K + 1) / 2) >> 18));
   a.react = p->desc.react;
   double* const W0 = p->Wl[0];
   double* const W1 = p->Wl[1];
@@ -1229,26 +1239,42 @@ static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in,
     a.post = 0;
     return W0;
   };
-  if (mode == FWD || mode == MID) {
-    a.in = in;
-    a.out = out;
-    a.wa = W0;
-    step(LONG_GATHER, false, nullptr, nullptr, "lgather64");
-    a.wb = dft(false);
-    step(LONG_CONTRACT_FWD, false, nullptr, nullptr, "lcfwd64");
-  }
-  if (mode == MID) {
-    a.in = out;
-    a.out = out;
-    step(LONG_DIVIDE, false, nullptr, nullptr, "ldiv64");
-  }
-  if (mode == INV || mode == MID) {
-    a.in = mode == INV ? in : out;
-    a.out = out;
-    a.wa = W0;
-    step(LONG_CONTRACT_INV, false, nullptr, nullptr, "lcinv64");
-    a.wb = dft(true);
-    step(LONG_SCATTER, false, nullptr, nullptr, "lscatter64");
+  // the lines in chunks of at most long_chunk (the work arrays' size); the
+  // non-finite flag of line l is bad[l / lpf], so a chunk boundary must not
+  // split the lines of one flag unless all lines share one
+  const int64_t chunk = p->long_chunk;
+  if (bad && lpf > 1 && lpf < nlines && chunk % lpf) return FFTFEM_EINVAL;
+  for (int64_t c0 = 0; c0 < nlines && !rc; c0 += chunk) {
+    const int64_t nl = std::min(chunk, nlines - c0);
+    const double* cin = in + c0 * a.M;
+    double* cout = out + c0 * a.M;
+    a.nlines = nl;
+    a.bad = bad ? bad + (lpf >= nlines ? 0 : c0 / lpf) : nullptr;
+    a.mu_line = mu_line ? mu_line + c0 : nullptr;
+    // lines per contraction thread: enough threads to fill the chip (about
+    // 2^18), the rest of the lines in a loop that reuses the cached Q rows
+    a.lpt = (int)std::max<int64_t>(1, std::min<int64_t>(nl, nl * ((a.K + 1) / 2) >> 18));
+    if (mode == FWD || mode == MID) {
+      a.in = cin;
+      a.out = cout;
+      a.wa = W0;
+      step(LONG_GATHER, false, nullptr, nullptr, "lgather64");
+      a.wb = dft(false);
+      step(LONG_CONTRACT_FWD, false, nullptr, nullptr, "lcfwd64");
+    }
+    if (mode == MID) {
+      a.in = cout;
+      a.out = cout;
+      step(LONG_DIVIDE, false, nullptr, nullptr, "ldiv64");
+    }
+    if (mode == INV || mode == MID) {
+      a.in = mode == INV ? cin : cout;
+      a.out = cout;
+      a.wa = W0;
+      step(LONG_CONTRACT_INV, false, nullptr, nullptr, "lcinv64");
+      a.wb = dft(true);
+      step(LONG_SCATTER, false, nullptr, nullptr, "lscatter64");
+    }
   }
   return rc;
 }
@@ -1711,7 +1737,7 @@ int plan_num_passes(fftfem_plan_t p) { return p ? 2 * p->N - 1 : 0; }
 
 int plan_pass_info(fftfem_plan_t p, int pass, PassInfo* info) {
   if (!p || !info || pass < 0 || pass >= 2 * p->N - 1) return FFTFEM_EINVAL;
-  if (p->N < 2) return FFTFEM_ENOTIMPL;
+  if (p->N < 2 || p->longK) return FFTFEM_ENOTIMPL;
   const Geom g = tune_geom(p, pass);
   const int64_t K = p->K[g.axis];
   info->elt = p->desc.precision == FFTFEM_FP64 ? (int)sizeof(double) : (int)sizeof(float);

@@ -271,6 +271,7 @@ hipError_t launch_reduce(const double* partials, int nparts, int iter, double to
 constexpr int kBlock = 256;        // threads per workgroup of every kernel
 constexpr int kLineTasks = 1024;   // G * K limit of one line-kernel tile
 constexpr int64_t kLongMaxK = int64_t(1) << 20;  // largest K of the long-line transforms (1D)
+constexpr size_t kLongWorkBytes = size_t(8) << 30;  // per work array of the long-line transforms (chunks of lines beyond)
 constexpr int kMaxLineOrder = 9;   // element orders compiled into the line kernels
 
 }  // namespace fftfem

@@ -304,3 +304,62 @@ def test_long2d_reports_nonfinite(fm):
     f[1, 5, 7] = 0.0
     p.solve(torch.from_numpy(f).cuda())
     assert p.stats()["converged"]
+
+
+@pytest.mark.parametrize("K,n,nrhs,chunk", [((2308,), 5, 3, 2), ((1100, 1030), 3, 2, 333)])
+def test_long_chunked_lines_match_whole(fm, monkeypatch, K, n, nrhs, chunk):
+    """Work arrays smaller than an axis' lines (FFTFEM_LONG_CHUNK lines per
+    pass, the last chunk ragged) give the same solve, coefficients and
+    synthesis bit for bit (the kernels see the same lines in the same order),
+    and still report a NaN in one right-hand side."""
+    say("long chunked", K, n, nrhs, chunk)
+    N = len(K)
+    whole = fm.Plan(K, n, (1.0,) * N, 0.3, nrhs=nrhs)
+    monkeypatch.setenv("FFTFEM_LONG_CHUNK", str(chunk))
+    part = fm.Plan(K, n, (1.0,) * N, 0.3, nrhs=nrhs)
+    monkeypatch.delenv("FFTFEM_LONG_CHUNK")
+    assert part.workspace_bytes() < whole.workspace_bytes()
+    f = inputs.draw_rhs(list(whole.shape), 1930 + N, "normal", nrhs=nrhs)
+    ft = torch.from_numpy(f).cuda()
+    assert torch.equal(part.solve(ft), whole.solve(ft))
+    c = whole.coefficients(ft, kind="loads")
+    assert torch.equal(part.coefficients(ft, kind="loads"), c)
+    assert torch.equal(part.synthesize(c), whole.synthesize(c))
+    f[nrhs - 1].flat[77] = np.nan
+    u = part.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert np.isfinite(u[0].cpu().numpy()).all()
+    assert part.stats()["stop"] == "nonfinite"
+
+
+def test_long2d_solve_sine_fills_hbm(fm):
+    """The largest two-axis case that fits one MI355X: n = 9, K = 11000 per
+    axis, 9.8e9 unknowns (78.4 GB per float64 array; f, u and the plan's
+    transposed copy take 235 GB, the work arrays 16 GB in chunks of lines).
+    u = sin(pi x) sin(pi y) on the unit square: the load is lam times the
+    outer product of the oracle's 1D loads, the expected values the outer
+    product of the 1D interpolants (FEM error of order h^10, far below
+    rounding); compared in blocks of rows on the device."""
+    K, n = 11000, 9
+    say("long 2d fills hbm", K, n)
+    lam = 2 * np.pi ** 2
+    l1 = loads.load_vector_1d(lambda x: np.sin(np.pi * x), n, K)
+    i1 = loads.interpolate(lambda x: np.sin(np.pi * x), n, (K,))
+    p = fm.Plan((K, K), n, (1.0, 1.0), 0.0)
+    lt = torch.from_numpy(l1).cuda()
+    it = torch.from_numpy(np.ascontiguousarray(i1)).cuda()
+    f = torch.outer(lt * lam, lt)
+    u = p.solve(f)
+    del f
+    torch.cuda.synchronize()
+    st = p.stats()
+    assert st["converged"] and st["stop"] == "none", st
+    M = u.shape[0]
+    err = 0.0
+    for r0 in range(0, M, 4096):
+        r1 = min(M, r0 + 4096)
+        err = max(err, (u[r0:r1] - torch.outer(it[r0:r1], it)).abs().max().item())
+    say("long 2d fills hbm: max error", err)
+    assert err < 1e-11
+    del u, p
+    torch.cuda.empty_cache()
