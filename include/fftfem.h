@@ -84,7 +84,7 @@ typedef struct {
   int N;                          /* number of axes, 1..FFTFEM_MAX_DIMS */
   int64_t K[FFTFEM_MAX_DIMS];     /* elements per axis, 2 <= K[d] <= 1024 (ENOTIMPL above; FFTFEM_FP64
                                      plans of algorithm (a), not in batches, also accept any K up to
-                                     2^20 on one axis, or on two axes when both exceed 1024:
+                                     2^20 on one axis, or on one or both of two axes:
                                      multi-pass transforms, whose two work arrays hold up to
                                      8 GiB each and take the lines in chunks beyond that; a
                                      two-axis plan of one order keeps one full-size scratch

@@ -55,7 +55,7 @@ struct fftfem_plan_s {
   int band_form = 0;         // ... 0: one sweep per line, 1: three kernels (few lines),
                              // 2: one LDS-tiled kernel (short lines)
   double* Wband = nullptr;   // its work: (K_0 - 1) x (size / M_0) pivots, or (split) size values
-  bool longK = false;        // 1D, K > 1024: the multi-pass transforms of long.hip
+  bool longK = false;        // an axis with K > 1024 (1D, or one or both of 2D): multi-pass transforms
   double* Wl[2] = {nullptr, nullptr};  // their work arrays: lines x (1 + n/2) x D complex each (the
                                        // largest over the axes) for long_chunk lines at a time
   int64_t long_chunk = 0;              // lines per pass (of nrhs in 1D, M of the other axis in 2D)
@@ -884,14 +884,15 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     if (d.n_axis[i] > kMaxLineOrder) return FFTFEM_ENOTIMPL;
   const bool algb = (d.flags & FFTFEM_ALGORITHM_B) != 0;
   // a line-kernel tile holds at most kLineTasks element tasks; longer lines
-  // take the multi-pass transforms: one axis, or two axes both longer than
-  // a tile, K up to kLongMaxK, float64, algorithm (a), not in batches
+  // take the multi-pass transforms: one axis, or two axes of which one or
+  // both are longer than a tile (the other by the line passes), K up to
+  // kLongMaxK, float64, algorithm (a), not in batches
   bool longK = false;
   {
     int nlong = 0;
     for (int i = 0; i < d.N; ++i) nlong += d.K[i] > kLineTasks ? 1 : 0;
     if (nlong > 0) {
-      bool ok = (d.N == 1 || (d.N == 2 && nlong == 2)) && d.precision == FFTFEM_FP64 && !algb && !cache;
+      bool ok = d.N <= 2 && d.precision == FFTFEM_FP64 && !algb && !cache;
       for (int i = 0; i < d.N; ++i) ok = ok && d.K[i] <= kLongMaxK;
       if (!ok) return FFTFEM_ENOTIMPL;
       longK = true;
@@ -1038,6 +1039,7 @@ int fftfem::plan_create(fftfem_plan_t* out, const fftfem_desc* din, TableCache* 
     size_t per = 0;
     int64_t lines_max = 1;
     for (int ax = 0; ax < p->N && !rc; ++ax) {
+      if (p->K[ax] <= kLineTasks) continue;  // a short axis of a two-axis plan: line passes
       const AxisTables& t = p->host[ax];
       auto& la = p->lax[ax];
       const bool pow2 = is_pow2(p->K[ax]);
@@ -1279,6 +1281,18 @@ static int long_transform(fftfem_plan_t p, int axis, int mode, const double* in,
   return rc;
 }
 
+// The rows (axis 1) of one right-hand side of a two-axis long-line plan:
+// the multi-pass transforms when axis 1 is long, else one line pass.  NaN /
+// Inf written by the pass sets bit 2 of *bad (when given).
+static int rows_2d(fftfem_plan_t p, int mode, const double* in, double* out, hipStream_t s, int* bad = nullptr) {
+  if (p->K[1] > kLineTasks) return long_transform(p, 1, mode, in, out, p->M[0], s, bad, p->M[0]);
+  int* keep = p->bad;
+  p->bad = bad;
+  const int rc = line_pass<double>(p, natural_geom(p, 1, false), mode, in, 1, out, 1, nullptr, nullptr, s, false);
+  p->bad = keep;
+  return rc;
+}
+
 // The last axis of a long-line plan for every right-hand side: one call for
 // one axis (the lines are the right-hand sides), one per right-hand side for
 // two (the work arrays hold one right-hand side's M0 rows).
@@ -1286,20 +1300,39 @@ static int long_last_axis(fftfem_plan_t p, int mode, const double* in, double* o
   if (p->N == 1) return long_transform(p, 0, mode, in, out, p->nrhs, s);
   int rc = FFTFEM_OK;
   for (int r = 0; r < p->nrhs && !rc; ++r)
-    rc = long_transform(p, 1, mode, in + (size_t)r * p->size, out + (size_t)r * p->size, p->M[0], s);
+    rc = rows_2d(p, mode, in + (size_t)r * p->size, out + (size_t)r * p->size, s);
   return rc;
 }
 
 // Axis 0 of a two-axis long-line plan, one right-hand side: in (M0 x M1) is
 // transposed into the plan's scratch, its M1 contiguous lines transformed
-// there (mode as long_transform), and transposed back into out (which may
-// be in).
+// there (mode as long_transform; the multi-pass transforms when axis 0 is
+// long, else one line pass, whose MID step takes the axis-1 denominator of
+// line l from axis 1's table, as mu_line does), and transposed back into out
+// (which may be in).
 static int long_axis0_2d(fftfem_plan_t p, int mode, const double* in, double* out, hipStream_t s,
                          const double* mu_line = nullptr) {
   double* T = p->tmp[0];
   const int64_t M0 = p->M[0], M1 = p->M[1];
   int rc = from_hip(launch_transpose<double>(in, T, 1, M0, M1, s));
-  if (!rc) rc = long_transform(p, 0, mode, T, T, M1, s, nullptr, 1, mu_line);
+  if (!rc) {
+    if (p->K[0] > kLineTasks) {
+      rc = long_transform(p, 0, mode, T, T, M1, s, nullptr, 1, mu_line);
+    } else {
+      Geom g;
+      g.axis = 0;
+      g.M = M0;
+      g.es = 1;
+      g.nlines = M1;
+      if (mu_line) {
+        g.nother = 1;
+        g.oaxis[0] = 1;
+        g.so[0] = M0;  // line l starts at l M0: other-axis index (l M0 / M0) mod M1 = l
+        g.Mo[0] = M1;
+      }
+      rc = line_pass<double>(p, g, mode, T, 1, T, 1, nullptr, nullptr, s, false);
+    }
+  }
   if (!rc) rc = from_hip(launch_transpose<double>(T, out, 1, M1, M0, s));
   return rc;
 }
@@ -1323,9 +1356,9 @@ int fftfem_solve(fftfem_plan_t p, const double* f, double* u, hipStream_t s) {
     for (int r = 0; r < p->nrhs && !rc; ++r) {
       const double* fr = f + (size_t)r * p->size;
       double* ur = u + (size_t)r * p->size;
-      rc = long_transform(p, 1, FWD, fr, ur, p->M[0], s);
+      rc = rows_2d(p, FWD, fr, ur, s);
       if (!rc) rc = long_axis0_2d(p, MID, ur, ur, s, tab<double>(p, 1, 4));
-      if (!rc) rc = long_transform(p, 1, INV, ur, ur, p->M[0], s, p->flags + r, p->M[0]);
+      if (!rc) rc = rows_2d(p, INV, ur, ur, s, p->flags + r);
     }
     return rc;
   }

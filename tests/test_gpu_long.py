@@ -363,3 +363,38 @@ def test_long2d_solve_sine_fills_hbm(fm):
     assert err < 1e-11
     del u, p
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("K,n", [((1030, 20), 2), ((24, 1100), 3), ((1025, 12), (3, 2))])
+def test_long2d_one_long_axis(fm, K, n):
+    """Two axes of which only one is longer than a tile: the multi-pass
+    transforms on that axis, the LDS line passes on the other (axis 0 on the
+    transposed copy, with the axis-1 denominators per line).  Solves of two
+    random loads against the oracle's eigen solve, expansion coefficients and
+    synthesis (Theorem 2), the operator apply (one order: the fused pass;
+    two orders: the two-pass form) and NaN reporting."""
+    from oracle import solve as osolve
+    say("long 2d one long axis", K, n)
+    diff, react = (1.0, 0.7), 0.3
+    p = fm.Plan(K, n, diff, react, nrhs=2)
+    f = inputs.draw_rhs(list(p.shape), 1940 + K[0] + K[1], "normal", nrhs=2)
+    ft = torch.from_numpy(f).cuda()
+    u = p.solve(ft).cpu().numpy()
+    want = osolve.solve(f, n, K, diff, react)
+    for r in range(2):
+        assert np.linalg.norm(u[r] - want[r]) / np.linalg.norm(want[r]) < 1e-11, r
+    assert p.stats()["converged"]
+    c = p.coefficients(ft, kind="loads")
+    assert torch.equal(c, p.debug_transform(0, +1, p.debug_transform(1, +1, ft)))
+    w = p.synthesize(c)
+    back = p.coefficients(w, kind="values")
+    assert (torch.linalg.norm(back - c) / torch.linalg.norm(c)).item() < 1e-12
+    Au = p.apply_A(ft).cpu().numpy()
+    for r in range(2):
+        ref = osolve.apply_A(f[r], n, K, diff, react)
+        assert np.linalg.norm(Au[r] - ref) / np.linalg.norm(ref) < 1e-13, r
+    f[1, 3, 5] = np.nan
+    u = p.solve(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert np.isfinite(u[0].cpu().numpy()).all()
+    assert p.stats()["stop"] == "nonfinite"
