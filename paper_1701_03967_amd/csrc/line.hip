@@ -65,6 +65,19 @@ struct LineCfg {
   static constexpr int MINW = sizeof(T) == 8 ? FFTFEM_MINW64 : FFTFEM_MINW32;
 };
 
+// Flat float64 tile I/O with the non-temporal hint: each value is read or
+// written once, and the streaming lines should not evict the tables that
+// every tile rereads (Q_k, twiddles) from L2.
+typedef double fftfem_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const fftfem_d2v t = __builtin_nontemporal_load(reinterpret_cast<const fftfem_d2v*>(p));
+  return double2{t.x, t.y};
+}
+__device__ __forceinline__ void st_stream(double2* p, double x, double y) {
+  const fftfem_d2v t = {x, y};
+  __builtin_nontemporal_store(t, reinterpret_cast<fftfem_d2v*>(p));
+}
+
 template <typename T>
 __device__ __forceinline__ int64_t line_base(const LineArgs<T>& a, int64_t line) {
   int64_t outer = line / a.es;
@@ -296,7 +309,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             int i = i0 + u * kNT;
-            v[u] = i < np ? s2[i] : double2{0.0, 0.0};
+            v[u] = i < np ? ld_stream(s2 + i) : double2{0.0, 0.0};
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -377,7 +390,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
           double2* o2 = reinterpret_cast<double2*>(op + head);
           for (int i = tid; i < np; i += kNT) {
             const double v0 = raw[head + 2 * i], v1 = raw[head + 2 * i + 1];
-            o2[i] = double2{v0, v1};
+            st_stream(o2 + i, v0, v1);
             if (chk) nonfinite |= !(v0 - v0 == 0.0) || !(v1 - v1 == 0.0);
           }
           if (tid == 0 && nflat > 0) {
