@@ -55,6 +55,11 @@ extern __shared__ double2 fftfem_lds[];
 #define FFTFEM_NT64 512
 #endif
 
+// Value pairs per thread and sweep of the flat float64 tile loads: 10 x 512
+// covers the largest tile (9 x 1024 - 1 values) in one sweep, so its loads
+// take one memory round trip.
+constexpr int kFlatPairs = 10;
+
 template <typename T>
 struct LineCfg {
   static constexpr int NT = sizeof(T) == 8 ? FFTFEM_NT64 : 512;
@@ -304,15 +309,15 @@ __device__ __forceinline__ void line_body(const LineArgs<T>& a, int bid, int nbl
         const int head = (reinterpret_cast<uintptr_t>(sp) & 15) ? 1 : 0;
         const int np = (nflat - head) >> 1;
         const double2* s2 = reinterpret_cast<const double2*>(sp + head);
-        for (int i0 = tid; i0 < np; i0 += 8 * kNT) {
-          double2 v[8];
+        for (int i0 = tid; i0 < np; i0 += kFlatPairs * kNT) {
+          double2 v[kFlatPairs];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < kFlatPairs; ++u) {
             int i = i0 + u * kNT;
             v[u] = i < np ? ld_stream(s2 + i) : double2{0.0, 0.0};
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < kFlatPairs; ++u) {
             int i = i0 + u * kNT;
             if (i < np) {
               raw[head + 2 * i] = v[u].x;
