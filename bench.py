@@ -793,11 +793,78 @@ def summarize_replay(d: str, cmd: str, out: str):
     print("\n".join(lines))
 
 
+def summarize_counters(d: str, bench_json: str, title: str, cmd: str, out: str):
+    """profiles/counters_<name>.txt from a rocprofv3 --pmc run of SQ
+    counters (SQ_WAVES, SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_WAIT_INST_LDS,
+    SQ_WAVE_CYCLES, ...) in directory d: per kernel the mean over its
+    dispatches, and, with the kernel's mean duration from a bench line on the
+    same sources (bench_json; the mean over the modes that launch the kernel:
+    an unprofiled run, since the profiler slows the kernels), VALU busy
+    (VALU instructions x 4 cycles
+    per wave64 instruction over 4 SIMDs x 256 CUs x the kernel's cycles at
+    2.4 GHz), the LDS-wait share of the wave cycles, and the mean resident
+    waves per CU (SQ_WAVE_CYCLES, counted in units of 4 cycles, over 256 x
+    the kernel's cycles)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    acc = defaultdict(lambda: defaultdict(list))
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as fh:
+            for r in csv.DictReader(fh):
+                try:
+                    acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                except (KeyError, ValueError):
+                    continue
+    # mean duration per kernel symbol over the modes that launch it
+    durs = defaultdict(list)
+    with open(bench_json) as fh:
+        rec = json.loads([line for line in fh.read().splitlines() if line.startswith("{")][-1])
+    cfg = rec["config"]
+    for mode in rec.get("modes", {}).values():
+        for nm, t in mode.get("kernels_ms", {}).items():
+            durs[profiler_kernel_name(nm, cfg["n"], cfg["N"], cfg["K"][0])].append(t)
+    ms = {sym: sum(v) / len(v) for sym, v in durs.items()}
+    lines = [f"# rocprofv3 --pmc SQ counters, MI355X (gfx950): {title}",
+             f"# command: (from the repository root, TMPDIR=/tmp) {cmd}",
+             "# summary: python bench.py summarize-counters <output dir> <bench line of the same sources> <title> "
+             "<command> <this file>",
+             f"# kernel sources sha256: {sources_sha256()}",
+             "# per kernel: mean over its dispatches of each counter; derived figures use the kernel's mean "
+             "duration in the default bench run (no profiler), averaged over the modes that launch it",
+             "kernel | ms | waves | VALU instr/wave | LDS instr/wave | VALU busy | LDS-wait share | waves/CU"]
+    for name, cs in sorted(acc.items()):
+        mean = {c: sum(v) / len(v) for c, v in cs.items()}
+        t = next((v for sym, v in ms.items() if sym in name), None)
+        waves = mean.get("SQ_WAVES", 0.0)
+        row = [name[:110], f"{t:.3f}" if t else "-", f"{waves:.0f}"]
+        row.append(f"{mean.get('SQ_INSTS_VALU', 0) / waves:.0f}" if waves else "-")
+        row.append(f"{mean.get('SQ_INSTS_LDS', 0) / waves:.0f}" if waves else "-")
+        if t and waves:
+            cyc = t * 1e-3 * 2.4e9
+            row.append(f"{mean.get('SQ_INSTS_VALU', 0) * 4 / (4 * 256 * cyc):.2f}")
+            wc = mean.get("SQ_WAVE_CYCLES", 0.0)
+            row.append(f"{mean.get('SQ_WAIT_INST_LDS', 0) / wc:.3f}" if wc else "-")
+            row.append(f"{wc * 4 / (256 * cyc):.1f}")
+        else:
+            row += ["-", "-", "-"]
+        lines.append(" | ".join(row))
+    lines.append("# counter means")
+    for name, cs in sorted(acc.items()):
+        lines.append(f"kernel: {name[:140]}")
+        for c, v in sorted(cs.items()):
+            lines.append(f"    {c} mean={sum(v) / len(v):.6g} dispatches={len(v)}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:20]))
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic", "summarize-replay"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic", "summarize-replay",
+                                             "summarize-counters"):
         # text summaries of rocprofv3 output for profiles/ (no GPU use)
         fn = {"summarize-stats": summarize_stats, "summarize-traffic": summarize_traffic,
-              "summarize-replay": summarize_replay}[sys.argv[1]]
+              "summarize-replay": summarize_replay, "summarize-counters": summarize_counters}[sys.argv[1]]
         fn(*sys.argv[2:])
         return
     ap = argparse.ArgumentParser()

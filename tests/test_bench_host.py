@@ -90,3 +90,27 @@ def test_summarize_replay_finds_the_periodic_tail(tmp_path):
     frac = float(line.split("(")[-1].split(" of wall")[0])
     assert frac == pytest.approx(120 * 100 / (120 * 105 - 5), rel=1e-3)
     assert "idle gaps between kernels: total 0.001 ms" in text  # 119 gaps of 5 ns
+
+
+def test_summarize_counters_derives_busy_and_residency(tmp_path):
+    """Means over dispatches; VALU busy and resident waves from the kernel's
+    mean duration over the modes of a bench line (one symbol, two modes)."""
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    kern = "void fftfem::line_kernel<double, 9, 0, false, false, 0>(fftfem::LineArgs<double>)"
+    rows = []
+    for v in (100.0, 300.0):
+        rows += [[kern, "SQ_WAVES", 1000.0], [kern, "SQ_INSTS_VALU", 2.0e6], [kern, "SQ_INSTS_LDS", 1.0e5],
+                 [kern, "SQ_WAVE_CYCLES", 6.144e8], [kern, "SQ_WAIT_INST_LDS", v * 1e4]]
+    _write_csv(str(tmp_path / "c" / "run_counter_collection.csv"), hdr, rows)
+    line = {"config": {"N": 2, "n": 9, "K": [1024, 1024]},
+            "modes": {"fp64": {"kernels_ms": {"fwd64_ax1": 1.5}}, "fp64_b": {"kernels_ms": {"fwd64_ax1": 0.5}}}}
+    (tmp_path / "b.json").write_text("noise\n" + __import__("json").dumps(line) + "\n")
+    out = str(tmp_path / "c.txt")
+    bench.summarize_counters(str(tmp_path / "c"), str(tmp_path / "b.json"), "t", "cmd", out)
+    row = [x for x in open(out).read().splitlines() if x.startswith("void fftfem::line_kernel")][0]
+    f = [x.strip() for x in row.split("|")]
+    # duration 1.0 ms (mean of the two modes) = 2.4e6 cycles
+    assert f[1] == "1.000" and f[2] == "1000" and f[3] == "2000" and f[4] == "100"
+    assert float(f[5]) == pytest.approx(2.0e6 * 4 / (4 * 256 * 2.4e6), abs=0.01)
+    assert float(f[6]) == pytest.approx(2.0e6 / 6.144e8, abs=1e-3)
+    assert float(f[7]) == pytest.approx(6.144e8 * 4 / (256 * 2.4e6), abs=0.1)
